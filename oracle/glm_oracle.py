@@ -1,0 +1,548 @@
+"""FP64 CPU oracle for the point-process GLM log-likelihood and its gradient.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+bench's CPU-baseline leg may import this module; the library never does.
+It shares no code with the GPU path.
+
+What it computes (Zaytsev, Morrison, Deger, "Reconstruction of recurrent
+synaptic connectivity of thousands of neurons from simulated spiking
+activity"):
+
+* Sec. 2.1, Eq. (1)-(2): L = sum_i L_i,
+  L_i = sum_k log lambda_i(t_{i,k}) - integral lambda_i dt.
+* Sec. 2.2, Eq. (3) and (5) with delta_u = 1: U_i = J_i0 + sum_j J_ij (h * s_j),
+  h(t) = H(t) exp(-t/tau), lambda_i = exp(U_i).  J_i0 is called mu_i here.
+* Sec. 2.3.3, Eq. (11)-(12): dL_i/dJ_ij = sum_k v_ij(t_{i,k}) - integral
+  lambda_i v_ij dt, with v_ij = h * s_j and v_i0 = 1 (so dL_i/dmu_i = q_i -
+  integral lambda_i dt).
+
+Grid form (the method evaluated on a uniform grid of B bins of width dt,
+covering [0, B dt)):
+
+* s_i[t] = number of spikes of neuron i in bin t.
+* trace x_j[t] = sum_{t' < t} a^(t-t'-1) s_j[t'], a = exp(-dt/tau); i.e.
+  x_j[0] = 0, x_j[t] = a x_j[t-1] + s_j[t-1].  A spike acts on later bins only,
+  with weight 1 in the next bin (the peak amplitude, as h(0) = 1).  This is the
+  grid counterpart of the recurrence Eq. (13).
+* U_i[t] = mu_i + sum_j J_ij x_j[t], lambda_i[t] = exp(U_i[t]) in 1/s.
+* L_i = sum_t s_i[t] U_i[t] - dt sum_t lambda_i[t].  (The constant
+  sum_t s_i[t] log dt that a binned likelihood would add is excluded.)
+* dL/dJ_ij = sum_t (s_i[t] - dt lambda_i[t]) x_j[t],
+  dL/dmu_i = q_i - dt sum_t lambda_i[t].
+* dL/dtau = sum_{t,i} (s_i[t] - dt lambda_i[t]) sum_j J_ij y_j[t] with
+  y_j = d x_j / d tau, y_j[0] = 0, y_j[t] = a y_j[t-1] + (dt/tau^2) a x_j[t-1]
+  (the time constant is not part of theta_i, Sec. 2.2, so this gradient is
+  taken separately).
+
+Continuous-time form (tiny inputs only, used to pin the grid form): the
+closed-form integral Eq. (9)-(10) with the exponential integral Ei (proof in
+App. B), the gradient integral Eq. (14), and the same quantities by adaptive
+quadrature.
+
+Fits: exact per-row Newton (Hessian Eq. (18), App. A) for small problems,
+scipy L-BFGS-B (the optimiser family of Sec. 2.6.3) on the joint vector for
+larger ones, stopping on the fractional change of L (Sec. 2.6.3).
+
+Classification: 1-D k-means with k = 3 (Sec. 3.3 / App. C.2), MER over the
+off-diagonal pairs, the confusion bookkeeping of Tables 2, 3, 5, 6, and the
+chance level MER_0 of Eq. (20).
+
+Every function is plain FP64 NumPy/SciPy; nothing is blocked or fused beyond
+time-chunking (a memory bound that does not change any value beyond rounding).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import scipy.integrate
+import scipy.optimize
+import scipy.signal
+import scipy.sparse
+import scipy.special
+
+DEFAULT_CHUNK = 65536
+
+
+# --------------------------------------------------------------------- data
+
+def decay(dt: float, tau: float) -> float:
+    """a = exp(-dt/tau): the kernel h decays by this factor per bin."""
+    return math.exp(-dt / tau)
+
+
+def spike_matrix(bins: np.ndarray, neurons: np.ndarray, N: int, B: int) -> scipy.sparse.csr_matrix:
+    """S[t, i] = s_i[t], the spike count of neuron i in bin t (CSR, float64)."""
+    bins = np.asarray(bins, dtype=np.int64)
+    neurons = np.asarray(neurons, dtype=np.int64)
+    if bins.size and (bins.min() < 0 or bins.max() >= B):
+        raise ValueError("spike bin outside [0, B)")
+    if neurons.size and (neurons.min() < 0 or neurons.max() >= N):
+        raise ValueError("spike neuron outside [0, N)")
+    data = np.ones(bins.shape[0], dtype=np.float64)
+    S = scipy.sparse.coo_matrix((data, (bins, neurons)), shape=(B, N)).tocsr()
+    S.sum_duplicates()
+    return S
+
+
+def spike_counts(neurons: np.ndarray, N: int) -> np.ndarray:
+    """q_i: number of spikes of neuron i (Sec. 2.1)."""
+    return np.bincount(np.asarray(neurons, dtype=np.int64), minlength=N).astype(np.int64)
+
+
+# -------------------------------------------------------------------- trace
+
+def trace_recursive(S: np.ndarray, a: float) -> np.ndarray:
+    """x[0] = 0, x[t] = a x[t-1] + s[t-1]  (grid form of Eq. (13)); loop over t."""
+    S = np.asarray(S, dtype=np.float64)
+    X = np.zeros_like(S)
+    for t in range(1, S.shape[0]):
+        X[t] = a * X[t - 1] + S[t - 1]
+    return X
+
+
+def trace_direct(S: np.ndarray, a: float) -> np.ndarray:
+    """x[t] = sum_{t' < t} a^(t-t'-1) s[t']  (the convolution h * s_j of Eq. (3)
+    sampled on the grid); brute force, O(B^2)."""
+    S = np.asarray(S, dtype=np.float64)
+    B = S.shape[0]
+    X = np.zeros_like(S)
+    for t in range(B):
+        for tp in range(t):
+            X[t] += a ** (t - tp - 1) * S[tp]
+    return X
+
+
+def trace_lfilter(S: np.ndarray, a: float, x0: Optional[np.ndarray] = None) -> np.ndarray:
+    """The same trace as the IIR filter y[t] = a y[t-1] + s[t-1]
+    (scipy.signal.lfilter with b = [0, 1], a = [1, -a]).  x0 is the trace value
+    at the first row (the carry from earlier bins); it decays as a^t."""
+    S = np.asarray(S, dtype=np.float64)
+    X = scipy.signal.lfilter([0.0, 1.0], [1.0, -a], S, axis=0)
+    if x0 is not None:
+        X = X + np.power(a, np.arange(S.shape[0], dtype=np.float64))[:, None] * x0[None, :]
+    return X
+
+
+def tau_trace_recursive(S: np.ndarray, a: float, dt: float, tau: float):
+    """(x, y) with y = dx/dtau: y[0] = 0, y[t] = a y[t-1] + (dt/tau^2) a x[t-1]."""
+    S = np.asarray(S, dtype=np.float64)
+    X = np.zeros_like(S)
+    Y = np.zeros_like(S)
+    c = dt / (tau * tau)
+    for t in range(1, S.shape[0]):
+        X[t] = a * X[t - 1] + S[t - 1]
+        Y[t] = a * Y[t - 1] + c * a * X[t - 1]
+    return X, Y
+
+
+def tau_trace_direct(S: np.ndarray, a: float, dt: float, tau: float) -> np.ndarray:
+    """y[t] = sum_{t'<t} (t-t'-1) a^(t-t'-1) (dt/tau^2) s[t'], the derivative of
+    the direct sum with respect to tau (da/dtau = a dt / tau^2)."""
+    S = np.asarray(S, dtype=np.float64)
+    B = S.shape[0]
+    Y = np.zeros_like(S)
+    c = dt / (tau * tau)
+    for t in range(B):
+        for tp in range(t):
+            m = t - tp - 1
+            Y[t] += m * a ** m * c * S[tp]
+    return Y
+
+
+# ------------------------------------------------- likelihood and gradient
+
+def _colsum(M: np.ndarray) -> np.ndarray:
+    """Column sums by pairwise summation (rows made contiguous first)."""
+    return np.add.reduce(np.ascontiguousarray(M.T), axis=1)
+
+
+def loglik(bins, neurons, N: int, B: int, dt: float, tau: float, J: np.ndarray,
+           mu: np.ndarray, want_grad: bool = True, want_tau: bool = False,
+           chunk: int = DEFAULT_CHUNK, bin_range: Optional[Sequence[int]] = None) -> Dict:
+    """Grid log-likelihood (Eq. (2)/(7)) and gradient (Eq. (12)) in FP64.
+
+    J[i, j] is the weight from presynaptic j to postsynaptic i, mu[i] = J_i0.
+    Returns a dict with
+      ll       total log-likelihood (float)
+      ll_rows  L_i per neuron [N]
+      spike_term, integral_term  the two parts of Eq. (7) per neuron [N]
+      gJ [N, N], gmu [N]  (if want_grad)
+      gtau (float)        (if want_tau)
+      q [N]               spike counts
+    bin_range = (b0, b1) restricts every sum over t to bins b0 <= t < b1 (the
+    trace still sees every spike before b1); used for bounded timing samples.
+    The time axis is processed in chunks of `chunk` bins with the trace value
+    carried exactly across chunk boundaries.
+    """
+    J = np.asarray(J, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    S = spike_matrix(bins, neurons, N, B)
+    a = decay(dt, tau)
+    c_tau = dt / (tau * tau)
+    b0, b1 = (0, B) if bin_range is None else (int(bin_range[0]), int(bin_range[1]))
+    spike_parts: List[np.ndarray] = []
+    integ_parts: List[np.ndarray] = []
+    gJ = np.zeros((N, N)) if want_grad else None
+    lam_parts: List[np.ndarray] = []
+    gtau_parts: List[float] = []
+    x_carry = np.zeros(N)
+    y_carry = np.zeros(N)
+    # carry the trace through the skipped prefix [0, b0) without summing
+    if b0 > 0:
+        for t0 in range(0, b0, chunk):
+            t1 = min(t0 + chunk, b0)
+            Sc = S[t0:t1].toarray()
+            Xc = trace_lfilter(Sc, a, x_carry)
+            if want_tau:
+                Yc = trace_lfilter(c_tau * a * Xc, a, y_carry)
+                y_carry = a * Yc[-1] + c_tau * a * Xc[-1]
+            x_carry = a * Xc[-1] + Sc[-1]
+    for t0 in range(b0, b1, chunk):
+        t1 = min(t0 + chunk, b1)
+        Sc = S[t0:t1].toarray()
+        Xc = trace_lfilter(Sc, a, x_carry)
+        U = mu[None, :] + Xc @ J.T
+        lam = np.exp(U)
+        spike_parts.append(_colsum(Sc * U))
+        lam_sum = _colsum(lam)
+        integ_parts.append(dt * lam_sum)
+        lam_parts.append(lam_sum)
+        R = Sc - dt * lam  # s - dt lambda
+        if want_grad:
+            gJ += R.T @ Xc
+        if want_tau:
+            Yc = trace_lfilter(c_tau * a * Xc, a, y_carry)
+            V = Yc @ J.T
+            gtau_parts.append(float(np.sum(_colsum(R * V))))
+            y_carry = a * Yc[-1] + c_tau * a * Xc[-1]
+        x_carry = a * Xc[-1] + Sc[-1]
+    spike_term = np.array([math.fsum(p[i] for p in spike_parts) for i in range(N)])
+    integral_term = np.array([math.fsum(p[i] for p in integ_parts) for i in range(N)])
+    ll_rows = spike_term - integral_term
+    q = np.asarray(S[b0:b1].sum(axis=0)).ravel()
+    out = dict(ll=math.fsum(ll_rows), ll_rows=ll_rows, spike_term=spike_term,
+               integral_term=integral_term, q=q)
+    if want_grad:
+        lam_total = np.array([math.fsum(p[i] for p in lam_parts) for i in range(N)])
+        out["gJ"] = gJ
+        out["gmu"] = q - dt * lam_total
+    if want_tau:
+        out["gtau"] = math.fsum(gtau_parts)
+    return out
+
+
+def spike_term_matrix(bins, neurons, N: int, B: int, dt: float, tau: float,
+                      chunk: int = DEFAULT_CHUNK) -> np.ndarray:
+    """partial^Sigma_ij = sum_t s_i[t] x_j[t] (Eq. (12)); parameter-free (L212)."""
+    S = spike_matrix(bins, neurons, N, B)
+    a = decay(dt, tau)
+    D = np.zeros((N, N))
+    x_carry = np.zeros(N)
+    for t0 in range(0, B, chunk):
+        t1 = min(t0 + chunk, B)
+        Sc = S[t0:t1].toarray()
+        Xc = trace_lfilter(Sc, a, x_carry)
+        D += Sc.T @ Xc
+        x_carry = a * Xc[-1] + Sc[-1]
+    return D
+
+
+def dense_trace(bins, neurons, N: int, B: int, dt: float, tau: float) -> np.ndarray:
+    """The whole trace matrix X [B, N] (small problems only)."""
+    S = spike_matrix(bins, neurons, N, B).toarray()
+    return trace_lfilter(S, decay(dt, tau))
+
+
+# ---------------------------------------------------------------- fitting
+
+def _row_objective(A: np.ndarray, s: np.ndarray, dt: float, theta: np.ndarray):
+    """L_i, gradient and Hessian for one row with design A = [1, X] (Eq. (18))."""
+    U = A @ theta
+    lam = np.exp(U)
+    L = math.fsum(s * U) - dt * math.fsum(lam)
+    g = A.T @ (s - dt * lam)
+    H = -dt * (A.T * lam[None, :]) @ A
+    return L, g, H
+
+
+def newton_fit(bins, neurons, N: int, B: int, dt: float, tau: float,
+               J0: Optional[np.ndarray] = None, mu0: Optional[np.ndarray] = None,
+               rows: Optional[Sequence[int]] = None, fit_J: bool = True,
+               max_iter: int = 100, eta_tol: float = 1e-15):
+    """Exact per-row Newton ascent with backtracking (small problems only).
+
+    Each row theta_i = (mu_i, J_i1..J_iN) is a separate concave problem
+    (Sec. 2.2, App. A).  Iterates until the fractional change of L_i is below
+    eta_tol (Sec. 2.6.3) and the Newton decrement vanishes.  fit_J=False keeps
+    J fixed at J0 and fits mu only.
+    Returns (J, mu, info) with info['iters'] per row."""
+    S = spike_matrix(bins, neurons, N, B).toarray()
+    X = trace_lfilter(S, decay(dt, tau))
+    J = np.zeros((N, N)) if J0 is None else np.array(J0, dtype=np.float64)
+    mu = np.zeros(N) if mu0 is None else np.array(mu0, dtype=np.float64)
+    rows = range(N) if rows is None else rows
+    iters = {}
+    for i in rows:
+        s = S[:, i]
+        if fit_J:
+            A = np.concatenate([np.ones((B, 1)), X], axis=1)
+            theta = np.concatenate([[mu[i]], J[i]])
+        else:
+            A = np.ones((B, 1))
+            theta = np.array([mu[i]])
+            s_off = X @ J[i]
+        def obj(th):
+            if fit_J:
+                return _row_objective(A, s, dt, th)
+            U = th[0] + s_off
+            lam = np.exp(U)
+            L = math.fsum(s * U) - dt * math.fsum(lam)
+            return L, np.array([s.sum() - dt * lam.sum()]), np.array([[-dt * lam.sum()]])
+        L, g, H = obj(theta)
+        k = 0
+        for k in range(1, max_iter + 1):
+            step = np.linalg.solve(H, -g)  # ascent direction (H negative definite)
+            decrement = float(g @ step)  # Newton decrement g^T (-H)^-1 g >= 0
+            t = 1.0
+            while True:
+                Ln, gn, Hn = obj(theta + t * step)
+                if np.isfinite(Ln) and Ln >= L + 1e-4 * t * float(g @ step):
+                    break
+                t *= 0.5
+                if t < 1e-12:
+                    Ln, gn, Hn = L, g, H
+                    break
+            eta = abs(Ln - L) / max(abs(Ln), 1e-300)
+            theta = theta + t * step
+            L, g, H = Ln, gn, Hn
+            if eta <= eta_tol or decrement <= 1e-13 * max(abs(L), 1.0):
+                break
+        iters[i] = k
+        mu[i] = theta[0]
+        if fit_J:
+            J[i] = theta[1:]
+    return J, mu, dict(iters=iters)
+
+
+def lbfgs_fit(bins, neurons, N: int, B: int, dt: float, tau: float,
+              J0: Optional[np.ndarray] = None, mu0: Optional[np.ndarray] = None,
+              ftol: float = 1e-15, gtol: float = 1e-10, maxiter: int = 5000,
+              chunk: int = DEFAULT_CHUNK):
+    """scipy L-BFGS-B on the joint vector (mu, J) maximising L (Sec. 2.6.3)."""
+    J = np.zeros((N, N)) if J0 is None else np.array(J0, dtype=np.float64)
+    mu = np.zeros(N) if mu0 is None else np.array(mu0, dtype=np.float64)
+    theta0 = np.concatenate([mu, J.ravel()])
+
+    def f(theta):
+        r = loglik(bins, neurons, N, B, dt, tau, theta[N:].reshape(N, N), theta[:N],
+                   want_grad=True, chunk=chunk)
+        return -r["ll"], -np.concatenate([r["gmu"], r["gJ"].ravel()])
+
+    res = scipy.optimize.minimize(f, theta0, jac=True, method="L-BFGS-B",
+                                  options=dict(ftol=ftol, gtol=gtol, maxiter=maxiter,
+                                               maxcor=10))
+    return res.x[N:].reshape(N, N), res.x[:N], res
+
+
+# ------------------------------------------- continuous time (tiny inputs)
+
+def _ei_diff(D: float, xi: float) -> float:
+    """Ei(D) - Ei(D xi) for 0 < xi < 1 and D of either sign.  For small |D| the
+    two Ei values nearly cancel; then use Ei(x) = gamma + ln|x| + sum_n x^n/(n n!),
+    whose difference is ln(1/xi) + sum_n D^n (1 - xi^n)/(n n!)."""
+    if D == 0.0:
+        return -math.log(xi)
+    if abs(D) < 1e-2:
+        acc = -math.log(xi)
+        term = 1.0
+        for n in range(1, 30):
+            term *= D / n  # D^n / n!
+            acc += term * (1.0 - xi ** n) / n
+        return acc
+    return float(scipy.special.expi(D) - scipy.special.expi(D * xi))
+
+
+def _events(spike_times: Sequence[np.ndarray]):
+    ev = []
+    for j, ts in enumerate(spike_times):
+        for t in np.asarray(ts, dtype=np.float64):
+            ev.append((float(t), j))
+    ev.sort()
+    return ev
+
+
+def continuous_ll(spike_times: Sequence[np.ndarray], T0: float, T1: float, tau: float,
+                  J: np.ndarray, mu: np.ndarray, method: str = "ei") -> np.ndarray:
+    """Continuous-time L_i for every neuron (Eq. (2), (7)).
+
+    The potential follows the key recurrence Eq. (8) between the network's
+    events t_1..t_q (with t_0 = T0, t_{q+1} = T1).  The integral term is the
+    closed form Eq. (10) ("ei") or adaptive quadrature of Eq. (9) per interval
+    ("quad").  The intensity at a spike of neuron i is the left limit (the
+    spike does not act on its own intensity at its own time)."""
+    N = len(spike_times)
+    ev = _events(spike_times)
+    times = [T0] + [t for t, _ in ev] + [T1]
+    out = np.zeros(N)
+    for i in range(N):
+        c = math.exp(mu[i])
+        D = 0.0  # U - J_i0 right after the current event
+        spike_sum = []
+        integ = []
+        for k in range(len(times) - 1):
+            tk, tk1 = times[k], times[k + 1]
+            if k >= 1:
+                j = ev[k - 1][1]
+                # value just before this event (left limit) is D (already decayed)
+                if j == i:
+                    spike_sum.append(mu[i] + D)
+                D += J[i, j]
+            dtk = tk1 - tk
+            xi = math.exp(-dtk / tau)
+            if method == "ei":
+                integ.append(c * tau * _ei_diff(D, xi))
+            else:
+                Dk = D
+                val, _ = scipy.integrate.quad(lambda t: c * math.exp(Dk * math.exp(-(t - tk) / tau)),
+                                              tk, tk1, epsabs=0.0, epsrel=1e-13, limit=200)
+                integ.append(val)
+            D *= xi
+        out[i] = math.fsum(spike_sum) - math.fsum(integ)
+    return out
+
+
+def continuous_grad_integral(spike_times: Sequence[np.ndarray], T0: float, T1: float,
+                             tau: float, J: np.ndarray, mu: np.ndarray, i: int,
+                             method: str = "closed") -> np.ndarray:
+    """partial^int_ij = integral lambda_i v_ij dt for all j (Eq. (12)), by the
+    closed form Eq. (14) ("closed") or by quadrature ("quad")."""
+    N = len(spike_times)
+    ev = _events(spike_times)
+    times = [T0] + [t for t, _ in ev] + [T1]
+    c = math.exp(mu[i])
+    D = 0.0
+    v = np.zeros(N)
+    parts = [[] for _ in range(N)]
+    for k in range(len(times) - 1):
+        tk, tk1 = times[k], times[k + 1]
+        if k >= 1:
+            j = ev[k - 1][1]
+            D += J[i, j]
+            v[j] += 1.0
+        xi = math.exp(-(tk1 - tk) / tau)
+        for j in range(N):
+            if v[j] == 0.0:
+                continue
+            if method == "closed":
+                if abs(D) < 1e-8:
+                    f = (1.0 - xi) + D * (1.0 - xi * xi) / 2.0
+                else:
+                    f = (math.exp(D) - math.exp(D * xi)) / D
+                parts[j].append(c * v[j] * tau * f)
+            else:
+                Dk, vk = D, v[j]
+                val, _ = scipy.integrate.quad(
+                    lambda t: c * math.exp(Dk * math.exp(-(t - tk) / tau)) * vk * math.exp(-(t - tk) / tau),
+                    tk, tk1, epsabs=0.0, epsrel=1e-13, limit=200)
+                parts[j].append(val)
+        D *= xi
+        v *= xi
+    return np.array([math.fsum(p) for p in parts])
+
+
+def grid_ll_from_times(spike_times: Sequence[np.ndarray], T: float, dt: float, tau: float,
+                       J: np.ndarray, mu: np.ndarray) -> np.ndarray:
+    """Bin continuous spike times on a grid of width dt and return the grid L_i."""
+    N = len(spike_times)
+    B = int(round(T / dt))
+    bins, neu = [], []
+    for j, ts in enumerate(spike_times):
+        b = np.floor(np.asarray(ts) / dt).astype(np.int64)
+        bins.append(b)
+        neu.append(np.full(b.shape, j))
+    bins = np.concatenate(bins)
+    neu = np.concatenate(neu)
+    return loglik(bins, neu, N, B, dt, tau, J, mu, want_grad=False)["ll_rows"]
+
+
+# ------------------------------------------------------- classification
+
+def kmeans3(values: np.ndarray, max_iter: int = 1000):
+    """1-D Lloyd k-means with k = 3, initial centroids (min, 0, max), run to a
+    fixed point.  Returns (labels, centroids); label 0 = lowest centroid
+    (inhibitory), 1 = middle (unconnected), 2 = highest (excitatory)."""
+    v = np.asarray(values, dtype=np.float64).ravel()
+    c = np.array([v.min(), 0.0, v.max()])
+    lab = None
+    for _ in range(max_iter):
+        d = np.abs(v[:, None] - c[None, :])
+        new = np.argmin(d, axis=1)
+        if lab is not None and np.array_equal(new, lab):
+            break
+        lab = new
+        for k in range(3):
+            if np.any(lab == k):
+                c[k] = math.fsum(v[lab == k]) / int(np.sum(lab == k))
+    order = np.argsort(c)
+    remap = np.empty(3, dtype=np.int64)
+    remap[order] = np.arange(3)
+    return remap[lab], c[order]
+
+
+def truth_classes(J_true: np.ndarray) -> np.ndarray:
+    """0 = inhibitory (J < 0), 1 = none (J == 0), 2 = excitatory (J > 0)."""
+    return np.where(J_true > 0, 2, np.where(J_true < 0, 0, 1))
+
+
+def classify(J_hat: np.ndarray) -> np.ndarray:
+    """k-means class of every off-diagonal entry (diagonal = -1: self-connections
+    are treated separately, Sec. 3.1)."""
+    N = J_hat.shape[0]
+    off = ~np.eye(N, dtype=bool)
+    lab, _ = kmeans3(J_hat[off])
+    out = np.full((N, N), -1, dtype=np.int64)
+    out[off] = lab
+    return out
+
+
+def mer(labels: np.ndarray, J_true: np.ndarray, is_exc: Optional[np.ndarray] = None) -> Dict:
+    """Misclassification error rate over the off-diagonal pairs (Eq. (20)'s
+    denominator N(N-1)) and over N^2 (the denominator of Tables 2-6), plus the
+    per-class breakdown of the tables: each error is counted in the row of its
+    true class (false negative) and of its assigned class (false positive);
+    ND = errors violating Dale's law (presynaptic type vs assigned sign)."""
+    N = J_true.shape[0]
+    off = ~np.eye(N, dtype=bool)
+    truth = truth_classes(J_true)
+    wrong = off & (labels != truth)
+    n_err = int(wrong.sum())
+    rows = {}
+    for k, name in ((2, "excitatory"), (0, "inhibitory"), (1, "unconnected")):
+        fn = int((wrong & (truth == k)).sum())
+        fp = int((wrong & (labels == k)).sum())
+        row = dict(errors=fn + fp, fp=fp, fn=fn)
+        if is_exc is not None and k != 1:
+            pre_exc = np.broadcast_to(np.asarray(is_exc, dtype=bool)[None, :], (N, N))
+            dale = wrong & (labels == k) & ((pre_exc & (k == 0)) | (~pre_exc & (k == 2)))
+            row["nd"] = int(dale.sum())
+        rows[name] = row
+    total_rows = sum(r["errors"] for r in rows.values())
+    return dict(errors=n_err, mer=n_err / (N * (N - 1)), mer_n2=n_err / (N * N),
+                rows=rows, half_row_sum=total_rows // 2)
+
+
+def mer0(p: float, f_e: float) -> float:
+    """Chance-level MER of a random classifier that keeps p, f_e, f_i (Eq. (20))."""
+    f_i = 1.0 - f_e
+    return p * (2.0 - p * (1.0 + f_e * f_e + f_i * f_i))
+
+
+def mer0_counts(p: float, f_e: float, N: int) -> float:
+    """Eq. (20) from its three expected error counts n_e, n_i, n_n (App. C.1)."""
+    f_i = 1.0 - f_e
+    n_e = p * (f_e * N) * (N - 1) * (1.0 - p * f_e)
+    n_i = p * (f_i * N) * (N - 1) * (1.0 - p * f_i)
+    n_n = (1.0 - p) * N * (N - 1) * p
+    return (n_e + n_i + n_n) / (N * (N - 1))
