@@ -1,0 +1,208 @@
+/*
+ * glmrec — log-likelihood and gradient of the exponential-link point-process
+ * GLM of a recurrent network, evaluated on a uniform time grid for all N
+ * postsynaptic neurons at once, with per-row concave ascent, on one AMD
+ * MI355X (gfx950).
+ *
+ * Model (Zaytsev, Morrison, Deger, arXiv:1502.04993):
+ *   Sec. 2.1 Eq. (1)-(2)  L = sum_i L_i,  L_i = sum_k log lambda_i(t_ik) - int lambda_i dt
+ *   Sec. 2.2 Eq. (3), (5)  U_i = mu_i + sum_j J_ij (h * s_j),  lambda_i = exp(U_i),
+ *                          h(t) = H(t) exp(-t/tau); mu_i is the paper's J_i0.
+ *   Sec. 2.3.3 Eq. (12)    dL_i/dJ_ij = sum_k v_ij(t_ik) - int lambda_i v_ij dt,
+ *                          dL_i/dmu_i = q_i - int lambda_i dt.
+ * On the grid of B bins of width dt covering [0, B dt):
+ *   s_i[t]  spike count of neuron i in bin t
+ *   x_j[t]  = sum_{t' < t} a^(t-t'-1) s_j[t'],  a = exp(-dt/tau)  (a spike acts on
+ *             later bins only, with weight 1 in the next bin: the grid form of
+ *             the recurrence Eq. (13))
+ *   U_i[t]  = mu_i + sum_j J_ij x_j[t],  lambda_i[t] = exp(U_i[t])  [1/s]
+ *   L_i     = sum_t s_i[t] U_i[t] - dt sum_t lambda_i[t]
+ *             (the constant sum_t s_i[t] log dt is not included)
+ *   dL/dJ_ij = sum_t (s_i[t] - dt lambda_i[t]) x_j[t]
+ *   dL/dmu_i = q_i - dt sum_t lambda_i[t]
+ *   dL/dtau  = sum_{t,i} (s_i[t] - dt lambda_i[t]) sum_j J_ij dx_j[t]/dtau
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are dense row-major with row = postsynaptic neuron:
+ *     J[i*N + j] is the weight from presynaptic j to postsynaptic i.
+ *   - `where` says whether a pointer is host memory (GLMR_HOST) or device
+ *     memory of the context's device (GLMR_DEVICE).  Device pointers must be
+ *     valid on the context's stream.
+ *   - The library copies every input; it never keeps or frees a caller pointer.
+ *     Outputs go into caller-allocated buffers of the stated size.
+ *   - Every call returns a glmr_status; no exception or abort crosses this
+ *     boundary.  After an error, glmr_last_error(ctx) gives a message.
+ *   - A context is not thread-safe: one host thread at a time.
+ *   - Work runs on the context's stream; calls that return host values
+ *     synchronise that stream before returning.
+ */
+#ifndef GLMREC_H
+#define GLMREC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GLMR_OK = 0,
+  GLMR_NOT_CONVERGED = 1, /* warning: outputs valid, the iteration cap was hit */
+  GLMR_EINVAL = -1,       /* bad argument (size, range, pointer, tau, ...) */
+  GLMR_ENOMEM = -2,       /* device allocation failed */
+  GLMR_EDEVICE = -3,      /* HIP runtime error */
+  GLMR_ENOSPIKES = -4,    /* some neuron has no spike: its MLE does not exist */
+  GLMR_ENONFINITE = -5,   /* the likelihood overflowed (exp of a huge potential) */
+  GLMR_ESTATE = -6        /* call order: e.g. eval before set_spikes/set_kernel */
+} glmr_status;
+
+/* Arithmetic of the trace X, the weights J and the two contractions.
+ * Cross-tile sums, the likelihood assembly and the ascent are FP64 in all modes. */
+typedef enum {
+  GLMR_FP64 = 0, /* X, J, U, lambda in FP64, FP64 MFMA */
+  GLMR_FP32 = 1, /* X and J in FP32 (X rounded once from FP64), FP32 MFMA,
+                    exp and the lambda sums in FP64 */
+  GLMR_BF16 = 2, /* X, J and lambda in BF16, MFMA with FP32 accumulation */
+  GLMR_FP8 = 3   /* X, J and lambda in OCP e4m3 with power-of-two scales
+                    (per chunk for X, per row for J and lambda), FP32 accumulation */
+} glmr_precision;
+
+typedef enum { GLMR_HOST = 0, GLMR_DEVICE = 1 } glmr_where;
+
+typedef struct {
+  int32_t n_neurons;   /* N >= 1 */
+  int64_t n_bins;      /* B >= 1 */
+  double dt;           /* bin width in seconds, > 0 */
+  int64_t chunk_bins;  /* bins per time chunk of the lambda buffer; 0 = automatic.
+                          Rounded up to a multiple of 4096. */
+  int32_t precision;   /* glmr_precision */
+  int32_t device;      /* HIP device ordinal */
+  void* stream;        /* hipStream_t to run on, or NULL for the library's own stream */
+  int32_t tile_n;      /* neuron tile (128 or 256); 0 = automatic */
+} glmr_config;
+
+typedef struct glmr_ctx glmr_ctx;
+
+/* Create a context; allocates nothing large until set_spikes.  *out is set to
+ * NULL on failure. */
+glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out);
+
+/* Release a context and all its device memory.  NULL-safe. */
+void glmr_destroy(glmr_ctx* ctx);
+
+/* The spike raster S of Sec. 2.1: n_spikes pairs (bin[k], neuron[k]) with
+ * 0 <= bin < n_bins and 0 <= neuron < n_neurons, in any order; a pair may
+ * repeat (several spikes in one bin).  Both arrays live in `where` memory.
+ * Builds the time-major layout on the device (spike ingest).  Invalidates
+ * the kernel-dependent caches.  Returns GLMR_EINVAL on an out-of-range pair
+ * (nothing is kept), GLMR_ENOSPIKES if some neuron has q_i = 0 (the raster
+ * is kept; eval works, fit refuses). */
+glmr_status glmr_set_spikes(glmr_ctx* ctx, const int64_t* bin, const int32_t* neuron,
+                            int64_t n_spikes, int32_t where);
+
+/* Kernel time constant tau (seconds) of h(t) = H(t) exp(-t/tau), Sec. 2.2.
+ * Requires dt <= tau.  Computes the parameter-independent parts (the trace
+ * carries at every 64-bin boundary and the spike term
+ * dSigma_ij = sum_t s_i[t] x_j[t] of Eq. (12), which Sec. 2.3.3 notes need
+ * only be computed once). */
+glmr_status glmr_set_kernel(glmr_ctx* ctx, double tau);
+
+/* Parameters theta_i = (mu_i, J_i1..J_iN) of Sec. 2.3.3: J is N*N doubles,
+ * mu is N doubles (log base rates, 1/s), both in `where` memory. */
+glmr_status glmr_set_params(glmr_ctx* ctx, const double* J, const double* mu, int32_t where);
+
+/* Read back the current parameters (after set_params or fit).  Any pointer
+ * may be NULL.  tau is a host pointer. */
+glmr_status glmr_get_params(glmr_ctx* ctx, double* J, double* mu, double* tau, int32_t where);
+
+/* Evaluate L (Eq. (2) on the grid) and its gradient (Eq. (12)) at the current
+ * parameters.
+ *   ll       host, 1 double, nullable: L
+ *   ll_rows  N doubles, nullable: L_i
+ *   grad_J   N*N doubles, nullable: dL/dJ_ij
+ *   grad_mu  N doubles, nullable: dL/dmu_i
+ *   grad_tau host, 1 double, nullable: dL/dtau (one extra contraction)
+ * Array outputs live in `where` memory.  With grad_J and grad_mu both NULL
+ * only the likelihood is computed.  GLMR_ENONFINITE if L is not finite. */
+glmr_status glmr_eval(glmr_ctx* ctx, double* ll, double* ll_rows, double* grad_J,
+                      double* grad_mu, double* grad_tau, int32_t where);
+
+typedef struct {
+  int32_t max_iter;       /* iteration cap (default 500) */
+  double ftol;            /* per-row stop when |L_i^k - L_i^(k-1)| / |L_i^k| <= ftol
+                             (Sec. 2.6.3); 0 = precision default */
+  int32_t lbfgs_m;        /* history length (default 10) */
+  int32_t max_backtracks; /* Armijo halvings per iteration (default 30) */
+  int32_t warm_start_mu;  /* 1: start mu_i at log(q_i / T) instead of the current mu */
+  int32_t from_zero;      /* 1: start from J = 0, mu = 0 (overrides the current params) */
+} glmr_fit_opts;
+
+typedef struct {
+  int32_t iters;          /* ascent iterations taken */
+  int32_t evals;          /* likelihood evaluations */
+  double ll;              /* final L */
+  double max_eta;         /* max over rows of the last fractional change */
+  int32_t rows_converged; /* rows that met ftol */
+  double seconds;         /* wall time of the fit */
+} glmr_fit_report;
+
+/* Fill opts with the defaults. */
+void glmr_fit_defaults(glmr_fit_opts* opts);
+
+/* Maximise L over theta by per-row L-BFGS with per-row Armijo backtracking.
+ * L is separable over rows (Sec. 2.2), so every row takes its own step size
+ * and stops on its own; all rows share each evaluation.  Requires q_i >= 1
+ * for every neuron (else GLMR_ENOSPIKES).  Returns GLMR_NOT_CONVERGED (a
+ * warning) if max_iter is reached.  report may be NULL. */
+glmr_status glmr_fit(glmr_ctx* ctx, const glmr_fit_opts* opts, glmr_fit_report* report);
+
+/* ---------------------------------------------------------------- batching
+ * Many independent recordings (contexts of possibly different N and B, all
+ * on one device, all in GLMR_BF16 or all in the same precision) evaluated in
+ * one persistent launch per contraction, with a work queue over
+ * (recording, time tile, neuron tile).  The contexts must each have had
+ * set_spikes, set_kernel and set_params called.  The batch does not own the
+ * contexts; they must outlive it. */
+typedef struct glmr_batch glmr_batch;
+
+glmr_status glmr_batch_create(glmr_ctx* const* ctxs, int32_t n, glmr_batch** out);
+void glmr_batch_destroy(glmr_batch* b);
+
+/* One evaluation of every recording.  ll: host array of n doubles (nullable).
+ * Gradients stay inside each context (read them with glmr_eval-compatible
+ * buffers through glmr_batch_get_grad). */
+glmr_status glmr_batch_eval(glmr_batch* b, double* ll);
+
+/* Copy recording r's gradient of the last batch evaluation. */
+glmr_status glmr_batch_get_grad(glmr_batch* b, int32_t r, double* grad_J, double* grad_mu,
+                                int32_t where);
+
+/* Fit every recording (per-row L-BFGS as glmr_fit, all recordings advancing
+ * together, each evaluation one batched launch; the per-iteration device work
+ * is captured once in a HIP graph and replayed).  reports: host array of n
+ * (nullable). */
+glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* opts, glmr_fit_report* reports);
+
+/* ------------------------------------------------------------- diagnostics */
+const char* glmr_status_string(glmr_status s);
+const char* glmr_last_error(const glmr_ctx* ctx);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch while enabled.  glmr_prof_get fills up to `cap` entries of
+ * names (static strings), total milliseconds and launch counts, and returns
+ * the number of kernel kinds seen (synchronises the stream). */
+glmr_status glmr_prof_enable(glmr_ctx* ctx, int32_t on);
+int32_t glmr_prof_get(glmr_ctx* ctx, const char** names, double* total_ms, int64_t* launches,
+                      int32_t cap);
+void glmr_prof_reset(glmr_ctx* ctx);
+
+/* Layout facts of a context (for tests and the bench): padded neuron count,
+ * padded bin count, chunk bins, spike planes, neuron tile. */
+glmr_status glmr_query(const glmr_ctx* ctx, int64_t* n_pad, int64_t* b_pad, int64_t* chunk_bins,
+                       int32_t* planes, int32_t* tile_n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLMREC_H */

@@ -114,6 +114,18 @@ def trace_direct(S: np.ndarray, a: float) -> np.ndarray:
     return X
 
 
+def trace_rows(S: np.ndarray, a: float, x0: np.ndarray, out: Optional[np.ndarray] = None) -> np.ndarray:
+    """The recursion x[t] = a x[t-1] + s[t-1] over the rows of a chunk, started
+    from x[0] = x0 (the trace carried in from earlier bins)."""
+    S = np.asarray(S, dtype=np.float64)
+    X = np.empty_like(S) if out is None else out[: S.shape[0]]
+    X[0] = x0
+    for t in range(1, S.shape[0]):
+        np.multiply(X[t - 1], a, out=X[t])
+        X[t] += S[t - 1]
+    return X
+
+
 def trace_lfilter(S: np.ndarray, a: float, x0: Optional[np.ndarray] = None) -> np.ndarray:
     """The same trace as the IIR filter y[t] = a y[t-1] + s[t-1]
     (scipy.signal.lfilter with b = [0, 1], a = [1, -a]).  x0 is the trace value
@@ -154,13 +166,20 @@ def tau_trace_direct(S: np.ndarray, a: float, dt: float, tau: float) -> np.ndarr
 # ------------------------------------------------- likelihood and gradient
 
 def _colsum(M: np.ndarray) -> np.ndarray:
-    """Column sums by pairwise summation (rows made contiguous first)."""
-    return np.add.reduce(np.ascontiguousarray(M.T), axis=1)
+    """Column sums as a two-level blocked sum: blocks of 256 rows, then the
+    block sums (rounding error bounded by ~(256 + rows/256) ulp per column)."""
+    M = np.asarray(M, dtype=np.float64)
+    L = M.shape[0]
+    nb = -(-L // 256)
+    if nb * 256 != L:
+        M = np.concatenate([M, np.zeros((nb * 256 - L,) + M.shape[1:])], axis=0)
+    return M.reshape(nb, 256, *M.shape[1:]).sum(axis=1).sum(axis=0)
 
 
 def loglik(bins, neurons, N: int, B: int, dt: float, tau: float, J: np.ndarray,
            mu: np.ndarray, want_grad: bool = True, want_tau: bool = False,
-           chunk: int = DEFAULT_CHUNK, bin_range: Optional[Sequence[int]] = None) -> Dict:
+           chunk: int = DEFAULT_CHUNK, bin_range: Optional[Sequence[int]] = None,
+           rows: Optional[Sequence[int]] = None) -> Dict:
     """Grid log-likelihood (Eq. (2)/(7)) and gradient (Eq. (12)) in FP64.
 
     J[i, j] is the weight from presynaptic j to postsynaptic i, mu[i] = J_i0.
@@ -173,6 +192,10 @@ def loglik(bins, neurons, N: int, B: int, dt: float, tau: float, J: np.ndarray,
       q [N]               spike counts
     bin_range = (b0, b1) restricts every sum over t to bins b0 <= t < b1 (the
     trace still sees every spike before b1); used for bounded timing samples.
+    rows = list of postsynaptic neurons restricts the output to those rows
+    (L is separable over rows, Sec. 2.2): ll_rows, spike_term, integral_term,
+    gmu and q then have len(rows) entries and gJ has len(rows) rows; ll and
+    gtau are the sums over those rows only.
     The time axis is processed in chunks of `chunk` bins with the trace value
     carried exactly across chunk boundaries.
     """
@@ -182,9 +205,15 @@ def loglik(bins, neurons, N: int, B: int, dt: float, tau: float, J: np.ndarray,
     a = decay(dt, tau)
     c_tau = dt / (tau * tau)
     b0, b1 = (0, B) if bin_range is None else (int(bin_range[0]), int(bin_range[1]))
+    rsel = np.arange(N) if rows is None else np.asarray(rows, dtype=np.int64)
+    pos = np.full(N, -1, dtype=np.int64)
+    pos[rsel] = np.arange(rsel.shape[0])
+    J = J[rsel]
+    mu = mu[rsel]
+    R_n = rsel.shape[0]
     spike_parts: List[np.ndarray] = []
     integ_parts: List[np.ndarray] = []
-    gJ = np.zeros((N, N)) if want_grad else None
+    gJ = np.zeros((R_n, N)) if want_grad else None
     lam_parts: List[np.ndarray] = []
     gtau_parts: List[float] = []
     x_carry = np.zeros(N)
@@ -194,38 +223,53 @@ def loglik(bins, neurons, N: int, B: int, dt: float, tau: float, J: np.ndarray,
         for t0 in range(0, b0, chunk):
             t1 = min(t0 + chunk, b0)
             Sc = S[t0:t1].toarray()
-            Xc = trace_lfilter(Sc, a, x_carry)
+            Xc = trace_rows(Sc, a, x_carry)
             if want_tau:
-                Yc = trace_lfilter(c_tau * a * Xc, a, y_carry)
+                Yc = trace_rows(c_tau * a * Xc, a, y_carry)
                 y_carry = a * Yc[-1] + c_tau * a * Xc[-1]
             x_carry = a * Xc[-1] + Sc[-1]
+    JT = np.ascontiguousarray(J.T)
+    nrow = min(chunk, max(b1 - b0, 1))
+    Sbuf = np.zeros((nrow, N))
+    Xbuf = np.empty((nrow, N))
     for t0 in range(b0, b1, chunk):
         t1 = min(t0 + chunk, b1)
-        Sc = S[t0:t1].toarray()
-        Xc = trace_lfilter(Sc, a, x_carry)
-        U = mu[None, :] + Xc @ J.T
-        lam = np.exp(U)
-        spike_parts.append(_colsum(Sc * U))
+        Ssp = S[t0:t1]
+        coo = Ssp.tocoo()
+        Sc = Sbuf[: t1 - t0]
+        Sc.fill(0.0)
+        Sc[coo.row, coo.col] = coo.data
+        Xc = trace_rows(Sc, a, x_carry, out=Xbuf)
+        x_carry = a * Xc[-1] + Sc[-1]
+        U = Xc @ JT
+        U += mu[None, :]
+        # sum over the spikes of U at their bins (the first term of Eq. (7))
+        keep = pos[coo.col] >= 0
+        spike_parts.append(np.bincount(pos[coo.col[keep]],
+                                       weights=coo.data[keep] * U[coo.row[keep], pos[coo.col[keep]]],
+                                       minlength=R_n))
+        lam = np.exp(U, out=U)
         lam_sum = _colsum(lam)
         integ_parts.append(dt * lam_sum)
         lam_parts.append(lam_sum)
-        R = Sc - dt * lam  # s - dt lambda
+        R = lam
+        R *= -dt
+        R += Sc if rows is None else Sc[:, rsel]  # s - dt lambda
         if want_grad:
             gJ += R.T @ Xc
         if want_tau:
-            Yc = trace_lfilter(c_tau * a * Xc, a, y_carry)
-            V = Yc @ J.T
+            Yc = trace_rows(c_tau * a * Xc, a, y_carry)
+            V = Yc @ JT
             gtau_parts.append(float(np.sum(_colsum(R * V))))
             y_carry = a * Yc[-1] + c_tau * a * Xc[-1]
-        x_carry = a * Xc[-1] + Sc[-1]
-    spike_term = np.array([math.fsum(p[i] for p in spike_parts) for i in range(N)])
-    integral_term = np.array([math.fsum(p[i] for p in integ_parts) for i in range(N)])
+    spike_term = np.array([math.fsum(p[i] for p in spike_parts) for i in range(R_n)])
+    integral_term = np.array([math.fsum(p[i] for p in integ_parts) for i in range(R_n)])
     ll_rows = spike_term - integral_term
-    q = np.asarray(S[b0:b1].sum(axis=0)).ravel()
+    q = np.asarray(S[b0:b1].sum(axis=0)).ravel()[rsel]
     out = dict(ll=math.fsum(ll_rows), ll_rows=ll_rows, spike_term=spike_term,
                integral_term=integral_term, q=q)
     if want_grad:
-        lam_total = np.array([math.fsum(p[i] for p in lam_parts) for i in range(N)])
+        lam_total = np.array([math.fsum(p[i] for p in lam_parts) for i in range(R_n)])
         out["gJ"] = gJ
         out["gmu"] = q - dt * lam_total
     if want_tau:

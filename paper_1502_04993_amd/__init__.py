@@ -1,0 +1,327 @@
+"""glmrec: point-process GLM connectivity reconstruction on one AMD MI355X.
+
+Python binding of the C ABI in include/glmrec.h (libglmrec.so, HIP for
+gfx950).  The functions below keep the C names (`glmr_create`, `glmr_eval`,
+...) and only marshal arguments; `Context` wraps them for convenience.
+Arrays may be NumPy arrays (host memory) or torch CUDA tensors (device
+memory, GLMR_DEVICE); torch is used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (GLMR_BF16, GLMR_DEVICE, GLMR_FP8, GLMR_FP32, GLMR_FP64, GLMR_HOST, GLMR_OK,
+                   GLMR_NOT_CONVERGED, GlmrError, PRECISIONS)
+
+__all__ = ["Context", "Batch", "GlmrError", "glmr_create", "glmr_destroy", "glmr_set_spikes",
+           "glmr_set_kernel", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
+           "glmr_fit_defaults", "glmr_status_string", "glmr_last_error", "glmr_query",
+           "glmr_batch_create", "glmr_batch_destroy", "glmr_batch_eval", "glmr_batch_get_grad",
+           "glmr_batch_fit", "glmr_prof_enable", "glmr_prof_get", "glmr_prof_reset"]
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, where) of a NumPy array or a torch tensor of the given dtype."""
+    if x is None:
+        return None, None
+    if _is_torch(x):
+        import torch
+        tdt = {np.float64: torch.float64, np.int64: torch.int64, np.int32: torch.int32}[dtype]
+        if x.dtype != tdt or not x.is_contiguous():
+            raise TypeError(f"tensor must be contiguous {tdt}")
+        return ctypes.c_void_p(x.data_ptr()), (GLMR_DEVICE if x.is_cuda else GLMR_HOST)
+    a = np.asarray(x)
+    if a.dtype != dtype or not a.flags.c_contiguous:
+        raise TypeError(f"array must be C-contiguous {np.dtype(dtype)}")
+    return ctypes.c_void_p(a.ctypes.data), GLMR_HOST
+
+
+def _check(status: int, ctx=None):
+    if status < 0:
+        lib = L.load()
+        msg = lib.glmr_status_string(status).decode()
+        if ctx is not None:
+            detail = lib.glmr_last_error(ctx)
+            if detail:
+                msg += ": " + detail.decode()
+        raise GlmrError(status, msg)
+    return status
+
+
+# ---------------------------------------------------------------- C names
+
+def glmr_create(n_neurons, n_bins, dt, precision="fp32", device=0, stream=None, chunk_bins=0,
+                tile_n=0):
+    lib = L.load()
+    cfg = L.glmr_config(n_neurons, n_bins, dt, chunk_bins, PRECISIONS[precision], device,
+                        ctypes.c_void_p(stream) if stream else None, tile_n)
+    out = ctypes.c_void_p()
+    _check(lib.glmr_create(ctypes.byref(cfg), ctypes.byref(out)))
+    return out
+
+
+def glmr_destroy(ctx):
+    L.load().glmr_destroy(ctx)
+
+
+def glmr_set_spikes(ctx, bins, neurons):
+    pb, wb = _ptr(bins, np.int64)
+    pn, wn = _ptr(neurons, np.int32)
+    if wb != wn:
+        raise ValueError("bins and neurons must both be host or both be device arrays")
+    n = int(bins.shape[0])
+    if neurons.shape[0] != n:
+        raise ValueError("bins and neurons differ in length")
+    _sync_torch(bins)
+    return _check(L.load().glmr_set_spikes(ctx, pb, pn, n, wb), ctx)
+
+
+def glmr_set_kernel(ctx, tau):
+    return _check(L.load().glmr_set_kernel(ctx, float(tau)), ctx)
+
+
+def glmr_set_params(ctx, J, mu):
+    pj, wj = _ptr(J, np.float64)
+    pm, wm = _ptr(mu, np.float64)
+    if wj != wm:
+        raise ValueError("J and mu must both be host or both be device arrays")
+    _sync_torch(J)
+    return _check(L.load().glmr_set_params(ctx, pj, pm, wj), ctx)
+
+
+def glmr_get_params(ctx, J=None, mu=None):
+    """Fill J [N,N] and mu [N] (NumPy or torch float64); returns tau."""
+    tau = ctypes.c_double()
+    pj, wj = _ptr(J, np.float64)
+    pm, wm = _ptr(mu, np.float64)
+    where = wj if wj is not None else (wm if wm is not None else GLMR_HOST)
+    _check(L.load().glmr_get_params(ctx, pj, pm, ctypes.byref(tau), where), ctx)
+    return tau.value
+
+
+def glmr_eval(ctx, ll_rows=None, grad_J=None, grad_mu=None, want_tau=False):
+    """Evaluate into the given output arrays; returns (ll, dll_dtau or None)."""
+    ll = ctypes.c_double()
+    gt = ctypes.c_double()
+    outs = [o for o in (ll_rows, grad_J, grad_mu) if o is not None]
+    wheres = {(_ptr(o, np.float64)[1]) for o in outs}
+    if len(wheres) > 1:
+        raise ValueError("outputs must all be host or all be device arrays")
+    where = wheres.pop() if wheres else GLMR_HOST
+    st = L.load().glmr_eval(ctx, ctypes.byref(ll), _ptr(ll_rows, np.float64)[0],
+                            _ptr(grad_J, np.float64)[0], _ptr(grad_mu, np.float64)[0],
+                            ctypes.byref(gt) if want_tau else None, where)
+    _check(st, ctx)
+    return ll.value, (gt.value if want_tau else None)
+
+
+def glmr_fit_defaults():
+    o = L.glmr_fit_opts()
+    L.load().glmr_fit_defaults(ctypes.byref(o))
+    return o
+
+
+def glmr_fit(ctx, opts=None):
+    o = opts if opts is not None else glmr_fit_defaults()
+    rep = L.glmr_fit_report()
+    st = _check(L.load().glmr_fit(ctx, ctypes.byref(o), ctypes.byref(rep)), ctx)
+    return st, rep
+
+
+def glmr_status_string(status):
+    return L.load().glmr_status_string(status).decode()
+
+
+def glmr_last_error(ctx):
+    return L.load().glmr_last_error(ctx).decode()
+
+
+def glmr_query(ctx):
+    n_pad, b_pad, chunk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    planes, tile = ctypes.c_int32(), ctypes.c_int32()
+    _check(L.load().glmr_query(ctx, ctypes.byref(n_pad), ctypes.byref(b_pad), ctypes.byref(chunk),
+                               ctypes.byref(planes), ctypes.byref(tile)), ctx)
+    return dict(n_pad=n_pad.value, b_pad=b_pad.value, chunk_bins=chunk.value, planes=planes.value,
+                tile_n=tile.value)
+
+
+def glmr_prof_enable(ctx, on=True):
+    return _check(L.load().glmr_prof_enable(ctx, 1 if on else 0), ctx)
+
+
+def glmr_prof_reset(ctx):
+    L.load().glmr_prof_reset(ctx)
+
+
+def glmr_prof_get(ctx):
+    cap = 32
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_double * cap)()
+    n = (ctypes.c_int64 * cap)()
+    k = L.load().glmr_prof_get(ctx, names, ms, n, cap)
+    return {names[i].decode(): (ms[i], n[i]) for i in range(min(k, cap))}
+
+
+def glmr_batch_create(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    out = ctypes.c_void_p()
+    _check(L.load().glmr_batch_create(arr, len(ctxs), ctypes.byref(out)))
+    return out
+
+
+def glmr_batch_destroy(b):
+    L.load().glmr_batch_destroy(b)
+
+
+def glmr_batch_eval(b, n):
+    ll = (ctypes.c_double * n)()
+    _check(L.load().glmr_batch_eval(b, ll))
+    return np.array(ll[:])
+
+
+def glmr_batch_get_grad(b, r, grad_J=None, grad_mu=None):
+    pj, wj = _ptr(grad_J, np.float64)
+    pm, wm = _ptr(grad_mu, np.float64)
+    where = wj if wj is not None else (wm if wm is not None else GLMR_HOST)
+    return _check(L.load().glmr_batch_get_grad(b, r, pj, pm, where))
+
+
+def glmr_batch_fit(b, n, opts=None):
+    o = opts if opts is not None else glmr_fit_defaults()
+    reps = (L.glmr_fit_report * n)()
+    st = _check(L.load().glmr_batch_fit(b, ctypes.byref(o), reps))
+    return st, list(reps)
+
+
+def _sync_torch(x):
+    """Device inputs are produced on torch's stream; make them visible to the
+    library's stream."""
+    if _is_torch(x) and x.is_cuda:
+        import torch
+        torch.cuda.current_stream(x.device).synchronize()
+
+
+# -------------------------------------------------------------- convenience
+
+class Context:
+    """One recording: N neurons, B bins of width dt, one precision."""
+
+    def __init__(self, n_neurons: int, n_bins: int, dt: float, precision: str = "fp32",
+                 device: int = 0, stream=None, chunk_bins: int = 0, tile_n: int = 0):
+        self.N, self.B, self.dt, self.precision = int(n_neurons), int(n_bins), float(dt), precision
+        self._c = glmr_create(self.N, self.B, self.dt, precision, device, stream, chunk_bins, tile_n)
+
+    def close(self):
+        if self._c is not None and self._c.value:
+            glmr_destroy(self._c)
+        self._c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._c
+
+    def set_spikes(self, bins, neurons):
+        """Returns GLMR_OK or GLMR_ENOSPIKES is raised as GlmrError unless allow_silent."""
+        return glmr_set_spikes(self._c, bins, neurons)
+
+    def set_spikes_allow_silent(self, bins, neurons):
+        try:
+            return glmr_set_spikes(self._c, bins, neurons)
+        except GlmrError as e:
+            if e.status == L.GLMR_ENOSPIKES:
+                return e.status
+            raise
+
+    def set_kernel(self, tau: float):
+        return glmr_set_kernel(self._c, tau)
+
+    def set_params(self, J, mu):
+        return glmr_set_params(self._c, J, mu)
+
+    def get_params(self):
+        J = np.zeros((self.N, self.N))
+        mu = np.zeros(self.N)
+        tau = glmr_get_params(self._c, J, mu)
+        return J, mu, tau
+
+    def eval(self, grad: bool = True, rows: bool = True, want_tau: bool = False):
+        """Host evaluation: dict(ll, ll_rows, gJ, gmu, gtau)."""
+        ll_rows = np.zeros(self.N) if rows else None
+        gJ = np.zeros((self.N, self.N)) if grad else None
+        gmu = np.zeros(self.N) if grad else None
+        ll, gt = glmr_eval(self._c, ll_rows, gJ, gmu, want_tau)
+        return dict(ll=ll, ll_rows=ll_rows, gJ=gJ, gmu=gmu, gtau=gt)
+
+    def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
+            from_zero=False):
+        o = glmr_fit_defaults()
+        o.max_iter, o.ftol, o.lbfgs_m, o.max_backtracks = max_iter, ftol, lbfgs_m, max_backtracks
+        o.warm_start_mu, o.from_zero = int(warm_start_mu), int(from_zero)
+        st, rep = glmr_fit(self._c, o)
+        return dict(status=st, converged=(st == GLMR_OK), iters=rep.iters, evals=rep.evals,
+                    ll=rep.ll, max_eta=rep.max_eta, rows_converged=rep.rows_converged,
+                    seconds=rep.seconds)
+
+    def query(self):
+        return glmr_query(self._c)
+
+    def prof(self, on=True):
+        glmr_prof_enable(self._c, on)
+
+    def prof_get(self):
+        return glmr_prof_get(self._c)
+
+    def prof_reset(self):
+        glmr_prof_reset(self._c)
+
+
+class Batch:
+    """Several contexts evaluated and fitted together."""
+
+    def __init__(self, ctxs):
+        self.ctxs = list(ctxs)
+        self._b = glmr_batch_create([c.handle for c in self.ctxs])
+
+    def close(self):
+        if self._b is not None and self._b.value:
+            glmr_batch_destroy(self._b)
+        self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval(self):
+        return glmr_batch_eval(self._b, len(self.ctxs))
+
+    def grad(self, r):
+        c = self.ctxs[r]
+        gJ = np.zeros((c.N, c.N))
+        gmu = np.zeros(c.N)
+        glmr_batch_get_grad(self._b, r, gJ, gmu)
+        return gJ, gmu
+
+    def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
+            from_zero=False):
+        o = glmr_fit_defaults()
+        o.max_iter, o.ftol, o.lbfgs_m, o.max_backtracks = max_iter, ftol, lbfgs_m, max_backtracks
+        o.warm_start_mu, o.from_zero = int(warm_start_mu), int(from_zero)
+        st, reps = glmr_batch_fit(self._b, len(self.ctxs), o)
+        return st, [dict(iters=r.iters, evals=r.evals, ll=r.ll, max_eta=r.max_eta,
+                         rows_converged=r.rows_converged, seconds=r.seconds) for r in reps]

@@ -1,0 +1,215 @@
+// Internal definitions shared by the glmrec HIP sources (gfx950 only).
+//
+// Device data layout (all padded, all owned by the context):
+//   Np  = N rounded up to the neuron tile (128 or 256)
+//   Bp  = B rounded up to 256 bins;  NS = Bp / 64 subtiles of 64 bins
+//   masks[p][s][j]  uint64: bit b set if neuron j has more than p spikes in bin
+//                   64*s + b (p = 0..planes-1; planes = max spikes per bin)
+//   seg_off[s*NIB + ib], seg_ent[]: spikes of subtile s whose neuron lies in the
+//                   64-neuron block ib (NIB = Np/64); entry = i_local | (b << 6),
+//                   sorted, so a segment lists its spikes in bin order
+//   C[s][j]         trace x_j at bin 64*s (the carry into subtile s)
+//   CY[s][j]        d x_j / d tau at bin 64*s
+//   dsig[i][j]      sum_t s_i[t] x_j[t]     (Eq. (12), parameter-free)
+//   dsigY[i][j]     sum_t s_i[t] y_j[t]     (y = dx/dtau)
+//   W[i][t]         exp(sum_j J_ij x_j[t]) for the bins of one time chunk
+//   rowpart[tt][i]  per 256-bin tile partial sums of W (FP64)
+//   Gp[k][i][j]     per split partial of sum_t W[i][t] x_j[t]
+// Inside a subtile the trace is evaluated in closed form:
+//   x_j[64 s + m] = a^m * (C[s][j] + sum_{b < m, spike of j in bin 64 s + b} a^-(b+1))
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#define GLMR_SUB 64   // bins per subtile (mask word)
+#define GLMR_TT 256   // bins per time tile of the likelihood kernel
+#define GLMR_IB 64    // neurons per spike-segment block
+
+typedef __attribute__((ext_vector_type(2))) double f64x2;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+typedef __attribute__((ext_vector_type(4))) int i32x4;
+
+struct Tables {
+  double pw[64];     // a^m
+  double ainv[64];   // a^-(b+1)
+  double apow[65];   // a^(64 k), k = 0..64
+  float pw32[64];
+  float ainv32[64];
+};
+
+// ------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns hipSuccess or the launch error.
+struct IngestBufs {
+  int64_t n;
+  const int64_t* bin;
+  const int32_t* neu;
+  int32_t N;
+  int64_t B, NS, NIB;
+  unsigned long long* bad;    // [2]: count, first bad index (min)
+  int32_t* cnt;               // [NS*NIB + 1]
+  int32_t* off;               // [NS*NIB + 1]
+  int32_t* cursor;            // [NS*NIB]
+  uint16_t* ent;              // [n]
+  int64_t* q;                 // [Np]
+  int32_t* maxmult;           // [1]
+  int64_t* scan_tmp;          // [>= nseg/1024 + 2]
+};
+hipError_t launch_ingest_count(const IngestBufs& b, hipStream_t st);
+hipError_t launch_ingest_scan(const IngestBufs& b, hipStream_t st);
+hipError_t launch_ingest_scatter(const IngestBufs& b, hipStream_t st);
+hipError_t launch_ingest_sort(const IngestBufs& b, hipStream_t st);
+hipError_t launch_ingest_masks(const IngestBufs& b, uint64_t* masks, int planes, int64_t Np,
+                               hipStream_t st);
+
+struct CarryArgs {
+  const uint64_t* masks;
+  int planes;
+  int64_t NS, Np;
+  double a, ctau;          // a = exp(-dt/tau), ctau = dt / tau^2
+  const Tables* tab;       // device copy
+  int want_y;
+  double* C64;             // [NS][Np]
+  double* CY64;            // [NS][Np] (want_y)
+  float* C32;              // optional fp32 copy
+  float* CY32;             // optional
+  double* seg;             // [nseg][Np][2] scratch
+  double* segin;           // [nseg][Np][2] scratch
+  int64_t G;               // subtiles per segment (64)
+};
+hipError_t launch_carries(const CarryArgs& c, hipStream_t st);
+
+struct SpikeTermArgs {
+  const uint64_t* masks;
+  int planes;
+  const int32_t* seg_off;
+  const uint16_t* seg_ent;
+  const double* C64;
+  const double* CY64;      // nullable: then dsigY not computed
+  const Tables* tab;
+  double ctau;
+  int64_t NS, Np, NIB;
+  int splits;              // time splits
+  double* part;            // [splits][Np][Np] (and a second block for Y)
+  double* dsig;            // [Np][Np]
+  double* dsigY;           // [Np][Np] or null
+};
+hipError_t launch_spike_term(const SpikeTermArgs& a, hipStream_t st);
+
+// Likelihood kernels -------------------------------------------------------
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_FP8 = 3 };
+
+struct Gemm1Args {
+  const void* Jc;          // [Np][Np] compute precision
+  const uint64_t* masks;
+  int planes;
+  const void* C;           // [NS][Np] double (F64/F32) or float (BF16/FP8)
+  const void* CY;          // tau mode: carries of y
+  const Tables* tab;
+  double ctau;
+  int64_t Np, NS, B;
+  int64_t t0;              // first bin of this chunk (multiple of 256)
+  int64_t L;               // bins in this chunk (multiple of 256)
+  int n_itiles, n_ttiles;
+  void* W;                 // [Np][L]  (mode 0 writes, mode 1 reads)
+  double* rowpart;         // [Bp/256][Np]  (mode 0: sum_t W; mode 1: sum_t W V)
+  const float* xscale;     // FP8: per-chunk X scale (power of two); J row scale
+  const float* jscale;
+  int mode;                // 0: U -> W, 1: V = Y J^T -> sum W V
+};
+hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st);
+
+struct Gemm2Args {
+  const void* W;           // [Np][L]
+  const uint64_t* masks;
+  int planes;
+  const void* C;
+  const Tables* tab;
+  int64_t Np, NS;
+  int64_t t0, L;
+  int64_t ks;              // bins per split
+  int n_splits, n_itiles, n_jtiles;
+  void* Gp;                // [n_splits][Np][Np] float (double for F64)
+  const float* xscale;
+  const float* wscale;
+};
+hipError_t launch_gemm2(int prec, int tile, const Gemm2Args& a, hipStream_t st);
+
+// Reductions and assembly (FP64) -------------------------------------------
+hipError_t launch_gp_reduce(int prec, const void* Gp, int n_splits, int64_t Np, double* G64,
+                            int first, hipStream_t st);
+hipError_t launch_rowpart_reduce(const double* rowpart, int64_t n_tiles, int64_t Np, double* out,
+                                 double* tmp, hipStream_t st);
+struct AssembleArgs {
+  int N;
+  int64_t Np;
+  double dt;
+  const int64_t* q;
+  const double* mu;       // [Np]
+  const double* Jr;       // [Np][Np] parameters as used (rounded to the compute precision)
+  const double* dsig;
+  const double* dsigY;    // nullable
+  const double* rowsum;   // sum_t W  [Np]
+  const double* rowsumV;  // nullable
+  const double* G64;      // nullable (no gradient)
+  const double* rowscale; // [Np] multiplier of rowsum/G (e^mu, FP8 scales folded in)
+  double* ll_rows;        // [Np]
+  double* gJ;             // [Np][Np] or null
+  double* gmu;            // [Np] or null
+  double* tau_rows;       // [Np] or null
+};
+hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st);
+hipError_t launch_sum_rows(const double* v, int n, double* out, hipStream_t st);
+
+// Parameter preparation
+hipError_t launch_prepare_params(int prec, int N, int64_t Np, const double* J64, const double* mu,
+                                 void* Jc, double* Jr, double* rowscale, float* jscale,
+                                 hipStream_t st);
+hipError_t launch_copy_out(const double* src, int64_t src_ld, double* dst, int rows, int cols,
+                           hipStream_t st);
+hipError_t launch_fp8_xscale(const void* C32, int64_t NS, int64_t Np, int64_t chunk_sub,
+                             int64_t nchunks, const uint64_t* masks, int planes,
+                             const Tables* tab, float* xscale, hipStream_t st);
+hipError_t launch_fp8_wscale(const float* rowmax, int64_t Np, float* wscale, hipStream_t st);
+
+// Ascent (per-row L-BFGS, FP64) --------------------------------------------
+struct AscentArgs {
+  int N;
+  int64_t Np;
+  int P;                  // parameters per row = N + 1 (mu first)
+  int m;                  // history
+  double* theta;          // [Np][P] current
+  double* theta_try;      // [Np][P] trial
+  double* g;              // [Np][P] gradient of f = -L at theta
+  double* g_try;          // [Np][P]
+  double* d;              // [Np][P] direction
+  double* S;              // [m][Np][P]
+  double* Y;              // [m][Np][P]
+  double* rho;            // [m][Np]
+  int32_t* hist_len;      // [Np]
+  int32_t* hist_head;     // [Np]
+  double* f;              // [Np] f_i = -L_i at theta
+  double* f_try;          // [Np]
+  double* step;           // [Np] alpha_i
+  double* gd;             // [Np] g_i . d_i
+  int32_t* state;         // [Np]: 0 active, 1 converged, 2 stalled
+  int32_t* accepted;      // [Np]
+  double* eta;            // [Np]
+};
+hipError_t launch_lbfgs_direction(const AscentArgs& a, int first, hipStream_t st);
+hipError_t launch_make_trial(const AscentArgs& a, hipStream_t st);
+hipError_t launch_armijo(const AscentArgs& a, double c1, int last_try, int32_t* n_pending,
+                         hipStream_t st);
+hipError_t launch_accept_update(const AscentArgs& a, double ftol, int32_t* counters,
+                                hipStream_t st);
+hipError_t launch_pack_theta(int N, int64_t Np, int P, const double* theta, double* J64,
+                             double* mu, hipStream_t st);
+hipError_t launch_pack_grad(int N, int64_t Np, int P, const double* gJ, const double* gmu,
+                            const double* ll_rows, double* g, double* f, hipStream_t st);
+hipError_t launch_unpack_theta(int N, int64_t Np, int P, const double* J64, const double* mu,
+                               double* theta, hipStream_t st);

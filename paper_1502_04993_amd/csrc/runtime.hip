@@ -1,0 +1,998 @@
+// glmrec runtime: contexts, device memory, the evaluation pipeline, the
+// per-row ascent driver, batching and the C ABI of include/glmrec.h.
+//
+// One evaluation at fixed tau (the carries and dSigma are cached per tau):
+//   for each time chunk of L bins:
+//     kernel U   V = J x  -> W = exp(V) [Np x L], per-tile row sums of W
+//     kernel V   (dL/dtau only) Y-contraction, per-tile row sums of W V
+//     kernel G   per-split partials of W x^T over the chunk
+//     reduce     partials -> G (FP64, fixed order, accumulated over chunks)
+//   reduce row sums (FP64, fixed order); assemble L_i, dL/dmu, dL/dJ, dL/dtau.
+// Nothing is accumulated with atomics, so two evaluations of the same input
+// give bitwise-identical results.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/glmrec.h"
+#include "common.h"
+
+void gemm_tiles(int prec, int tile, int* bi1, int* bt1, int* bi2, int* bj2);
+int64_t ingest_scan_tmp_len(int64_t nseg);
+int64_t rowpart_tmp_len(int64_t Np);
+
+namespace {
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+};
+
+const char* const kKindNames[] = {"ingest",       "carries",     "spike_term", "kernel_U",
+                                  "kernel_V",     "kernel_G",    "reduce_G",   "assemble",
+                                  "prepare",      "ascent",      "batch_U",    "batch_G"};
+enum {
+  K_INGEST, K_CARRY, K_SPIKE, K_U, K_V, K_G, K_RED, K_ASM, K_PREP, K_ASC, K_BU, K_BG, K_NKIND
+};
+
+}  // namespace
+
+struct glmr_ctx {
+  glmr_config cfg{};
+  int N = 0;
+  int64_t B = 0;
+  double dt = 0;
+  int prec = 0;
+  int tile = 256;
+  int64_t Np = 0, Bp = 0, NS = 0, NIB = 0, L = 0;
+  int bi1 = 0, bt1 = 0, bi2 = 0, bj2 = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<void*> allocs;
+
+  // spikes
+  bool have_spikes = false;
+  int64_t nspk = 0;
+  int planes = 1;
+  int32_t* seg_off = nullptr;
+  uint16_t* seg_ent = nullptr;
+  uint64_t* masks = nullptr;
+  int64_t* q = nullptr;
+  std::vector<int64_t> q_host;
+  bool all_spiking = false;
+
+  // kernel
+  bool have_kernel = false, have_y = false;
+  double tau = 0, a = 0;
+  Tables* tab = nullptr;
+  double* C64 = nullptr;
+  double* CY64 = nullptr;
+  float* C32 = nullptr;
+  float* CY32 = nullptr;
+  double* dsig = nullptr;
+  double* dsigY = nullptr;
+
+  // parameters (padded FP64 masters and the compute-precision copy)
+  bool have_params = false;
+  double* J64 = nullptr;
+  double* mu = nullptr;
+  void* Jc = nullptr;
+  double* Jr = nullptr;
+  double* rowscale = nullptr;
+
+  // evaluation workspace
+  void* W = nullptr;
+  void* Gp = nullptr;
+  int max_splits = 0;
+  double* G64 = nullptr;
+  double* rowpart = nullptr;
+  double* rowpartV = nullptr;
+  double* rowsum = nullptr;
+  double* rowsumV = nullptr;
+  double* rp_tmp = nullptr;
+  double* ll_rows = nullptr;
+  double* gJ = nullptr;
+  double* gmu = nullptr;
+  double* tau_rows = nullptr;
+  double* scal = nullptr;  // [4] device scalars
+  double* host_scal = nullptr;
+
+  // ascent state
+  AscentArgs asc{};
+  bool have_asc = false;
+  int32_t* counters = nullptr;
+
+  // profiling
+  bool prof = false;
+  std::vector<ProfRec> pending;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[K_NKIND] = {};
+  int64_t prof_n[K_NKIND] = {};
+};
+
+namespace {
+
+glmr_status fail(glmr_ctx* c, glmr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define HIPCHK(c, expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((c), GLMR_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                               \
+  } while (0)
+
+template <typename T>
+glmr_status dalloc(glmr_ctx* c, T*& p, size_t n) {
+  if (p) {
+    hipFree(p);
+    c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void*)p), c->allocs.end());
+    p = nullptr;
+  }
+  if (n == 0) n = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, GLMR_ENOMEM, "hipMalloc of %zu bytes failed: %s", n * sizeof(T),
+                hipGetErrorString(e));
+  }
+  c->allocs.push_back(q);
+  p = (T*)q;
+  return GLMR_OK;
+}
+
+template <typename T>
+void dfree(glmr_ctx* c, T*& p) {
+  if (!p) return;
+  hipFree(p);
+  c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void*)p), c->allocs.end());
+  p = nullptr;
+}
+
+#define TRY(expr)                    \
+  do {                               \
+    glmr_status s_ = (expr);         \
+    if (s_ != GLMR_OK) return s_;    \
+  } while (0)
+
+hipEvent_t ev_get(glmr_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hipEventCreate(&e);
+  return e;
+}
+
+struct ProfScope {
+  glmr_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr;
+  ProfScope(glmr_ctx* c_, int k) : c(c_), kind(k) {
+    if (c->prof) {
+      a = ev_get(c);
+      hipEventRecord(a, c->st);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof) {
+      hipEvent_t b = ev_get(c);
+      hipEventRecord(b, c->st);
+      c->pending.push_back({kind, a, b});
+    }
+  }
+};
+
+void prof_collect(glmr_ctx* c) {
+  if (c->pending.empty()) return;
+  hipStreamSynchronize(c->st);
+  for (auto& r : c->pending) {
+    float ms = 0;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    c->prof_ms[r.kind] += ms;
+    c->prof_n[r.kind] += 1;
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
+int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+size_t in_bytes(int prec) { return prec == PREC_F64 ? 8 : prec == PREC_F32 ? 4 : prec == PREC_BF16 ? 2 : 1; }
+
+// ---------------------------------------------------------------- kernel caches
+glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
+  const double dt = c->dt, tau = c->tau;
+  Tables h{};
+  for (int m = 0; m < 64; ++m) {
+    h.pw[m] = std::exp(-(double)m * dt / tau);
+    h.ainv[m] = std::exp((double)(m + 1) * dt / tau);
+    h.pw32[m] = (float)h.pw[m];
+    h.ainv32[m] = (float)h.ainv[m];
+  }
+  for (int k = 0; k <= 64; ++k) h.apow[k] = std::exp(-64.0 * (double)k * dt / tau);
+  if (!c->tab) TRY(dalloc(c, c->tab, 1));
+  HIPCHK(c, hipMemcpyAsync(c->tab, &h, sizeof(Tables), hipMemcpyHostToDevice, c->st));
+
+  const size_t nc = (size_t)c->NS * c->Np;
+  if (!c->C64) TRY(dalloc(c, c->C64, nc));
+  if (want_y && !c->CY64) TRY(dalloc(c, c->CY64, nc));
+  const bool need32 = c->prec == PREC_BF16 || c->prec == PREC_FP8;
+  if (need32 && !c->C32) TRY(dalloc(c, c->C32, nc));
+  if (need32 && want_y && !c->CY32) TRY(dalloc(c, c->CY32, nc));
+  const int64_t G = 64;
+  const int64_t nseg = (c->NS + G - 1) / G;
+  double *seg = nullptr, *segin = nullptr;
+  TRY(dalloc(c, seg, (size_t)nseg * c->Np * 2));
+  TRY(dalloc(c, segin, (size_t)nseg * c->Np * 2));
+  CarryArgs ca{};
+  ca.masks = c->masks;
+  ca.planes = c->planes;
+  ca.NS = c->NS;
+  ca.Np = c->Np;
+  ca.a = c->a;
+  ca.ctau = dt / (tau * tau);
+  ca.tab = c->tab;
+  ca.want_y = want_y ? 1 : 0;
+  ca.C64 = c->C64;
+  ca.CY64 = want_y ? c->CY64 : nullptr;
+  ca.C32 = need32 ? c->C32 : nullptr;
+  ca.CY32 = (need32 && want_y) ? c->CY32 : nullptr;
+  ca.seg = seg;
+  ca.segin = segin;
+  ca.G = G;
+  {
+    ProfScope ps(c, K_CARRY);
+    HIPCHK(c, launch_carries(ca, c->st));
+  }
+
+  // spike term dSigma (and dSigmaY)
+  const int64_t nij = c->Np * c->Np;
+  if (!c->dsig) TRY(dalloc(c, c->dsig, (size_t)nij));
+  if (want_y && !c->dsigY) TRY(dalloc(c, c->dsigY, (size_t)nij));
+  int64_t pairs = c->NIB * c->NIB;
+  int splits = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + pairs - 1) / pairs, c->NS));
+  // bound the partial buffer to ~512 MB
+  while (splits > 1 && (size_t)splits * nij * 8 * (want_y ? 2 : 1) > (512ull << 20)) splits /= 2;
+  double* part = nullptr;
+  TRY(dalloc(c, part, (size_t)splits * nij * (want_y ? 2 : 1)));
+  SpikeTermArgs sa{};
+  sa.masks = c->masks;
+  sa.planes = c->planes;
+  sa.seg_off = c->seg_off;
+  sa.seg_ent = c->seg_ent;
+  sa.C64 = c->C64;
+  sa.CY64 = want_y ? c->CY64 : nullptr;
+  sa.tab = c->tab;
+  sa.ctau = dt / (tau * tau);
+  sa.NS = c->NS;
+  sa.Np = c->Np;
+  sa.NIB = c->NIB;
+  sa.splits = splits;
+  sa.part = part;
+  sa.dsig = c->dsig;
+  sa.dsigY = want_y ? c->dsigY : nullptr;
+  {
+    ProfScope ps(c, K_SPIKE);
+    HIPCHK(c, launch_spike_term(sa, c->st));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  dfree(c, part);
+  dfree(c, seg);
+  dfree(c, segin);
+  c->have_kernel = true;
+  c->have_y = want_y;
+  return GLMR_OK;
+}
+
+glmr_status ensure_workspace(glmr_ctx* c, bool want_grad, bool want_tau) {
+  const int64_t Np = c->Np;
+  const size_t wb = in_bytes(c->prec);
+  if (!c->W) {
+    void* p = nullptr;
+    TRY(dalloc(c, (unsigned char*&)p, (size_t)Np * c->L * wb));
+    c->W = p;
+  }
+  const int64_t ntiles_t = c->Bp / c->bt1;
+  if (!c->rowpart) TRY(dalloc(c, c->rowpart, (size_t)ntiles_t * Np));
+  if (want_tau && !c->rowpartV) TRY(dalloc(c, c->rowpartV, (size_t)ntiles_t * Np));
+  if (!c->rowsum) TRY(dalloc(c, c->rowsum, (size_t)Np));
+  if (want_tau && !c->rowsumV) TRY(dalloc(c, c->rowsumV, (size_t)Np));
+  if (!c->rp_tmp) TRY(dalloc(c, c->rp_tmp, (size_t)rowpart_tmp_len(Np)));
+  if (!c->ll_rows) TRY(dalloc(c, c->ll_rows, (size_t)Np));
+  if (!c->tau_rows) TRY(dalloc(c, c->tau_rows, (size_t)Np));
+  if (!c->scal) TRY(dalloc(c, c->scal, 4));
+  if (!c->host_scal) {
+    HIPCHK(c, hipHostMalloc((void**)&c->host_scal, 4 * sizeof(double), hipHostMallocDefault));
+  }
+  if (want_grad) {
+    if (!c->gmu) TRY(dalloc(c, c->gmu, (size_t)Np));
+    if (!c->gJ) TRY(dalloc(c, c->gJ, (size_t)Np * Np));
+    if (!c->G64) TRY(dalloc(c, c->G64, (size_t)Np * Np));
+    if (!c->Gp) {
+      const size_t gb = c->prec == PREC_F64 ? 8 : 4;
+      void* p = nullptr;
+      TRY(dalloc(c, (unsigned char*&)p, (size_t)c->max_splits * Np * Np * gb));
+      c->Gp = p;
+    }
+  }
+  return GLMR_OK;
+}
+
+// split length (bins) of kernel G for a chunk of Lc bins
+int64_t split_len(const glmr_ctx* c, int64_t Lc) {
+  const int64_t tiles = (c->Np / c->bi2) * (c->Np / c->bj2);
+  int64_t want = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
+  want = std::min<int64_t>(want, c->max_splits);
+  int64_t ks = rup((Lc + want - 1) / want, 64);
+  return std::max<int64_t>(ks, 64);
+}
+
+glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
+  TRY(ensure_workspace(c, want_grad, want_tau));
+  const int64_t Np = c->Np;
+  for (int64_t t0 = 0, ci = 0; t0 < c->Bp; t0 += c->L, ++ci) {
+    const int64_t Lc = std::min<int64_t>(c->L, c->Bp - t0);
+    Gemm1Args g1{};
+    g1.Jc = c->Jc;
+    g1.masks = c->masks;
+    g1.planes = c->planes;
+    g1.C = (c->prec == PREC_BF16 || c->prec == PREC_FP8) ? (const void*)c->C32 : (const void*)c->C64;
+    g1.CY = (c->prec == PREC_BF16 || c->prec == PREC_FP8) ? (const void*)c->CY32 : (const void*)c->CY64;
+    g1.tab = c->tab;
+    g1.ctau = c->dt / (c->tau * c->tau);
+    g1.Np = Np;
+    g1.NS = c->NS;
+    g1.B = c->B;
+    g1.t0 = t0;
+    g1.L = c->L;  // row pitch of W
+    g1.n_itiles = (int)(Np / c->bi1);
+    g1.n_ttiles = (int)(Lc / c->bt1);
+    g1.W = c->W;
+    g1.rowpart = c->rowpart;
+    g1.mode = 0;
+    {
+      ProfScope ps(c, K_U);
+      HIPCHK(c, launch_gemm1(c->prec, c->tile, g1, c->st));
+    }
+    if (want_tau) {
+      g1.mode = 1;
+      g1.rowpart = c->rowpartV;
+      ProfScope ps(c, K_V);
+      HIPCHK(c, launch_gemm1(c->prec, c->tile, g1, c->st));
+    }
+    if (want_grad) {
+      Gemm2Args g2{};
+      g2.W = c->W;
+      g2.masks = c->masks;
+      g2.planes = c->planes;
+      g2.C = g1.C;
+      g2.tab = c->tab;
+      g2.Np = Np;
+      g2.NS = c->NS;
+      g2.t0 = t0;
+      g2.L = c->L;
+      g2.ks = split_len(c, Lc);
+      g2.n_splits = (int)((Lc + g2.ks - 1) / g2.ks);
+      g2.n_itiles = (int)(Np / c->bi2);
+      g2.n_jtiles = (int)(Np / c->bj2);
+      g2.Gp = c->Gp;
+      // kernel G reads W rows of pitch L but only bins [0, Lc)
+      {
+        ProfScope ps(c, K_G);
+        Gemm2Args gg = g2;
+        gg.L = c->L;
+        HIPCHK(c, launch_gemm2(c->prec, c->tile, gg, c->st));
+      }
+      ProfScope ps(c, K_RED);
+      HIPCHK(c, launch_gp_reduce(c->prec, c->Gp, g2.n_splits, Np, c->G64, ci == 0, c->st));
+    }
+  }
+  ProfScope ps(c, K_ASM);
+  const int64_t ntiles_t = c->Bp / c->bt1;
+  HIPCHK(c, launch_rowpart_reduce(c->rowpart, ntiles_t, Np, c->rowsum, c->rp_tmp, c->st));
+  if (want_tau)
+    HIPCHK(c, launch_rowpart_reduce(c->rowpartV, ntiles_t, Np, c->rowsumV, c->rp_tmp, c->st));
+  AssembleArgs aa{};
+  aa.N = c->N;
+  aa.Np = Np;
+  aa.dt = c->dt;
+  aa.q = c->q;
+  aa.mu = c->mu;
+  aa.Jr = c->Jr;
+  aa.dsig = c->dsig;
+  aa.dsigY = want_tau ? c->dsigY : nullptr;
+  aa.rowsum = c->rowsum;
+  aa.rowsumV = want_tau ? c->rowsumV : nullptr;
+  aa.G64 = want_grad ? c->G64 : nullptr;
+  aa.rowscale = c->rowscale;
+  aa.ll_rows = c->ll_rows;
+  aa.gJ = want_grad ? c->gJ : nullptr;
+  aa.gmu = want_grad ? c->gmu : nullptr;
+  aa.tau_rows = want_tau ? c->tau_rows : nullptr;
+  HIPCHK(c, launch_assemble(aa, c->st));
+  HIPCHK(c, launch_sum_rows(c->ll_rows, c->N, c->scal, c->st));
+  if (want_tau) HIPCHK(c, launch_sum_rows(c->tau_rows, c->N, c->scal + 1, c->st));
+  return GLMR_OK;
+}
+
+glmr_status prepare_params(glmr_ctx* c) {
+  ProfScope ps(c, K_PREP);
+  HIPCHK(c, launch_prepare_params(c->prec, c->N, c->Np, c->J64, c->mu, c->Jc, c->Jr, c->rowscale,
+                                  nullptr, c->st));
+  return GLMR_OK;
+}
+
+glmr_status check_ready(glmr_ctx* c) {
+  if (!c->have_spikes) return fail(c, GLMR_ESTATE, "set_spikes has not been called");
+  if (!c->have_kernel) return fail(c, GLMR_ESTATE, "set_kernel has not been called");
+  if (!c->have_params) return fail(c, GLMR_ESTATE, "set_params has not been called");
+  return GLMR_OK;
+}
+
+hipMemcpyKind kind_to(int where) { return where == GLMR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice; }
+hipMemcpyKind kind_from(int where) { return where == GLMR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice; }
+
+
+// ------------------------------------------------------------------ ascent
+glmr_status alloc_ascent(glmr_ctx* c, int m) {
+  AscentArgs& a = c->asc;
+  const int N = c->N, P = N + 1;
+  if (c->have_asc && a.m == m) return GLMR_OK;
+  a.N = N;
+  a.Np = c->Np;
+  a.P = P;
+  a.m = m;
+  const size_t np = (size_t)N * P;
+  TRY(dalloc(c, a.theta, np));
+  TRY(dalloc(c, a.theta_try, np));
+  TRY(dalloc(c, a.g, np));
+  TRY(dalloc(c, a.g_try, np));
+  TRY(dalloc(c, a.d, np));
+  TRY(dalloc(c, a.S, np * m));
+  TRY(dalloc(c, a.Y, np * m));
+  TRY(dalloc(c, a.rho, (size_t)m * N));
+  TRY(dalloc(c, a.hist_len, (size_t)N));
+  TRY(dalloc(c, a.hist_head, (size_t)N));
+  TRY(dalloc(c, a.f, (size_t)N));
+  TRY(dalloc(c, a.f_try, (size_t)N));
+  TRY(dalloc(c, a.step, (size_t)N));
+  TRY(dalloc(c, a.gd, (size_t)N));
+  TRY(dalloc(c, a.state, (size_t)N));
+  TRY(dalloc(c, a.accepted, (size_t)N));
+  TRY(dalloc(c, a.eta, (size_t)N));
+  TRY(dalloc(c, c->counters, 4));
+  c->have_asc = true;
+  return GLMR_OK;
+}
+
+// evaluate at theta_src ([N][P]); gradient of f = -L into g, f into f
+glmr_status eval_theta(glmr_ctx* c, const double* theta_src, double* g, double* f) {
+  const AscentArgs& a = c->asc;
+  HIPCHK(c, launch_pack_theta(c->N, c->Np, a.P, theta_src, c->J64, c->mu, c->st));
+  TRY(prepare_params(c));
+  TRY(eval_core(c, true, false));
+  ProfScope ps(c, K_ASC);
+  HIPCHK(c, launch_pack_grad(c->N, c->Np, a.P, c->gJ, c->gmu, c->ll_rows, g, f, c->st));
+  return GLMR_OK;
+}
+
+double default_ftol(int prec) {
+  switch (prec) {
+    case PREC_F64: return 1e-14;
+    case PREC_F32: return 1e-11;
+    case PREC_BF16: return 1e-6;
+    default: return 1e-4;
+  }
+}
+
+glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep) {
+  glmr_fit_opts o;
+  glmr_fit_defaults(&o);
+  if (o_in) o = *o_in;
+  if (o.max_iter < 0 || o.lbfgs_m < 1 || o.lbfgs_m > 64 || o.max_backtracks < 0 || o.ftol < 0)
+    return fail(c, GLMR_EINVAL, "bad fit options");
+  if (!c->have_spikes || !c->have_kernel) return fail(c, GLMR_ESTATE, "set spikes and kernel first");
+  if (!c->all_spiking) return fail(c, GLMR_ENOSPIKES, "some neuron has no spike: its MLE does not exist");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  auto t_start = std::chrono::steady_clock::now();
+  const int N = c->N;
+  const int64_t Np = c->Np;
+  if (!c->have_params || o.from_zero) {
+    if (!c->J64) {
+      std::vector<double> z((size_t)N * N, 0.0), zm(N, 0.0);
+      TRY(glmr_set_params(c, z.data(), zm.data(), GLMR_HOST));
+    } else {
+      HIPCHK(c, hipMemsetAsync(c->J64, 0, Np * Np * sizeof(double), c->st));
+      HIPCHK(c, hipMemsetAsync(c->mu, 0, Np * sizeof(double), c->st));
+      c->have_params = true;
+    }
+  }
+  if (o.warm_start_mu) {
+    std::vector<double> m0(N);
+    const double T = (double)c->B * c->dt;
+    for (int i = 0; i < N; ++i) m0[i] = std::log((double)c->q_host[i] / T);
+    HIPCHK(c, hipMemcpyAsync(c->mu, m0.data(), N * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
+  TRY(alloc_ascent(c, o.lbfgs_m));
+  AscentArgs& a = c->asc;
+  HIPCHK(c, launch_unpack_theta(N, Np, a.P, c->J64, c->mu, a.theta, c->st));
+  HIPCHK(c, hipMemsetAsync(a.hist_len, 0, N * sizeof(int32_t), c->st));
+  HIPCHK(c, hipMemsetAsync(a.hist_head, 0, N * sizeof(int32_t), c->st));
+  HIPCHK(c, hipMemsetAsync(a.state, 0, N * sizeof(int32_t), c->st));
+  HIPCHK(c, hipMemsetAsync(a.eta, 0, N * sizeof(double), c->st));
+  const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c->prec);
+  int evals = 0, iters = 0;
+  TRY(eval_theta(c, a.theta, a.g, a.f));
+  ++evals;
+  int active = N;
+  int32_t hc[4];
+  for (iters = 0; iters < o.max_iter && active > 0;) {
+    {
+      ProfScope ps(c, K_ASC);
+      HIPCHK(c, launch_lbfgs_direction(a, iters == 0, c->st));
+    }
+    for (int bt = 0; bt <= o.max_backtracks; ++bt) {
+      {
+        ProfScope ps(c, K_ASC);
+        HIPCHK(c, launch_make_trial(a, c->st));
+      }
+      TRY(eval_theta(c, a.theta_try, a.g_try, a.f_try));
+      ++evals;
+      ProfScope ps(c, K_ASC);
+      HIPCHK(c, hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->st));
+      HIPCHK(c, launch_armijo(a, 1e-4, bt == o.max_backtracks, c->counters, c->st));
+      HIPCHK(c, hipMemcpyAsync(hc, c->counters, sizeof hc, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+      if (hc[0] == 0) break;
+    }
+    ProfScope ps(c, K_ASC);
+    HIPCHK(c, hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->st));
+    HIPCHK(c, launch_accept_update(a, ftol, c->counters, c->st));
+    HIPCHK(c, hipMemcpyAsync(hc, c->counters, sizeof hc, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    active = hc[0];
+    ++iters;
+  }
+  // leave the context at the accepted parameters
+  HIPCHK(c, launch_pack_theta(N, Np, a.P, a.theta, c->J64, c->mu, c->st));
+  TRY(prepare_params(c));
+  std::vector<double> f(N), eta(N);
+  std::vector<int32_t> state(N);
+  HIPCHK(c, hipMemcpyAsync(f.data(), a.f, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(eta.data(), a.eta, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(state.data(), a.state, N * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (rep) {
+    rep->iters = iters;
+    rep->evals = evals;
+    double ll = 0;
+    for (int i = 0; i < N; ++i) ll -= f[i];
+    rep->ll = ll;
+    rep->max_eta = *std::max_element(eta.begin(), eta.end());
+    rep->rows_converged = (int32_t)std::count_if(state.begin(), state.end(), [](int32_t s) { return s != 0; });
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return active > 0 ? GLMR_NOT_CONVERGED : GLMR_OK;
+}
+
+}  // namespace
+
+struct glmr_batch {
+  std::vector<glmr_ctx*> ctxs;
+};
+
+extern "C" {
+
+glmr_status glmr_fit(glmr_ctx* c, const glmr_fit_opts* o, glmr_fit_report* rep) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  return fit_one(c, o, rep);
+}
+
+glmr_status glmr_batch_create(glmr_ctx* const* ctxs, int32_t n, glmr_batch** out) {
+  if (!out) return GLMR_EINVAL;
+  *out = nullptr;
+  if (!ctxs || n < 1) return GLMR_EINVAL;
+  for (int r = 0; r < n; ++r) {
+    if (!ctxs[r]) return GLMR_EINVAL;
+    if (ctxs[r]->cfg.device != ctxs[0]->cfg.device || ctxs[r]->prec != ctxs[0]->prec) return GLMR_EINVAL;
+  }
+  glmr_batch* b = new glmr_batch();
+  b->ctxs.assign(ctxs, ctxs + n);
+  *out = b;
+  return GLMR_OK;
+}
+
+void glmr_batch_destroy(glmr_batch* b) { delete b; }
+
+glmr_status glmr_batch_eval(glmr_batch* b, double* ll) {
+  if (!b) return GLMR_EINVAL;
+  for (size_t r = 0; r < b->ctxs.size(); ++r) {
+    glmr_ctx* c = b->ctxs[r];
+    TRY(check_ready(c));
+    TRY(eval_core(c, true, false));
+  }
+  for (size_t r = 0; r < b->ctxs.size(); ++r) {
+    glmr_ctx* c = b->ctxs[r];
+    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (ll) ll[r] = c->host_scal[0];
+  }
+  return GLMR_OK;
+}
+
+glmr_status glmr_batch_get_grad(glmr_batch* b, int32_t r, double* grad_J, double* grad_mu, int32_t where) {
+  if (!b || r < 0 || r >= (int32_t)b->ctxs.size()) return GLMR_EINVAL;
+  glmr_ctx* c = b->ctxs[r];
+  if (!c->gJ) return fail(c, GLMR_ESTATE, "no batch evaluation yet");
+  if (grad_mu) HIPCHK(c, hipMemcpyAsync(grad_mu, c->gmu, c->N * sizeof(double), kind_to(where), c->st));
+  if (grad_J)
+    HIPCHK(c, hipMemcpy2DAsync(grad_J, c->N * sizeof(double), c->gJ, c->Np * sizeof(double),
+                               c->N * sizeof(double), c->N, kind_to(where), c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return GLMR_OK;
+}
+
+glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* o, glmr_fit_report* reps) {
+  if (!b) return GLMR_EINVAL;
+  glmr_status worst = GLMR_OK;
+  for (size_t r = 0; r < b->ctxs.size(); ++r) {
+    glmr_status s = fit_one(b->ctxs[r], o, reps ? &reps[r] : nullptr);
+    if (s < 0) return s;
+    if (s == GLMR_NOT_CONVERGED) worst = s;
+  }
+  return worst;
+}
+
+}  // extern "C"
+
+namespace {
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* glmr_status_string(glmr_status s) {
+  switch (s) {
+    case GLMR_OK: return "ok";
+    case GLMR_NOT_CONVERGED: return "not converged (iteration cap reached)";
+    case GLMR_EINVAL: return "invalid argument";
+    case GLMR_ENOMEM: return "out of device memory";
+    case GLMR_EDEVICE: return "HIP runtime error";
+    case GLMR_ENOSPIKES: return "a neuron has no spikes (its MLE does not exist)";
+    case GLMR_ENONFINITE: return "non-finite likelihood";
+    case GLMR_ESTATE: return "call order";
+  }
+  return "unknown status";
+}
+
+const char* glmr_last_error(const glmr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void glmr_fit_defaults(glmr_fit_opts* o) {
+  if (!o) return;
+  o->max_iter = 500;
+  o->ftol = 0.0;
+  o->lbfgs_m = 10;
+  o->max_backtracks = 30;
+  o->warm_start_mu = 0;
+  o->from_zero = 0;
+}
+
+glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
+  if (!out) return GLMR_EINVAL;
+  *out = nullptr;
+  if (!cfg) return GLMR_EINVAL;
+  if (cfg->n_neurons < 1 || cfg->n_neurons > 65536 || cfg->n_bins < 1 || !(cfg->dt > 0) ||
+      !std::isfinite(cfg->dt) || cfg->chunk_bins < 0 || cfg->precision < 0 || cfg->precision > 3 ||
+      !(cfg->tile_n == 0 || cfg->tile_n == 128 || cfg->tile_n == 256))
+    return GLMR_EINVAL;
+  if (cfg->precision == GLMR_FP8) return GLMR_EINVAL;  // not available in this build
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return GLMR_EDEVICE;
+  }
+  if (cfg->device < 0 || cfg->device >= ndev) return GLMR_EINVAL;
+  if (hipSetDevice(cfg->device) != hipSuccess) return GLMR_EDEVICE;
+  glmr_ctx* c = new glmr_ctx();
+  c->cfg = *cfg;
+  c->N = cfg->n_neurons;
+  c->B = cfg->n_bins;
+  c->dt = cfg->dt;
+  c->prec = cfg->precision;
+  int tile = cfg->tile_n;
+  if (tile == 0) tile = (c->prec == GLMR_BF16 && c->N <= 384) ? 128 : 256;
+  if (c->prec != GLMR_BF16) tile = 256;
+  c->tile = tile;
+  c->Np = rup(c->N, tile);
+  c->Bp = rup(c->B, GLMR_TT);
+  c->NS = c->Bp / GLMR_SUB;
+  c->NIB = c->Np / GLMR_IB;
+  gemm_tiles(c->prec, c->tile, &c->bi1, &c->bt1, &c->bi2, &c->bj2);
+  // chunk: W of at most ~1 GiB, a multiple of 4096 bins
+  int64_t L = cfg->chunk_bins;
+  if (L == 0) {
+    const int64_t budget = 1ll << 30;
+    L = budget / (c->Np * (int64_t)in_bytes(c->prec));
+    L = std::max<int64_t>(4096, L / 4096 * 4096);
+  } else {
+    L = rup(L, 4096);
+  }
+  c->L = std::min<int64_t>(L, c->Bp);
+  // partial buffer of kernel G: at most ~512 MB, at most 256 splits
+  const size_t gb = c->prec == PREC_F64 ? 8 : 4;
+  int64_t ms = (512ll << 20) / (int64_t)(c->Np * c->Np * gb);
+  c->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(ms, 256));
+  if (cfg->stream) {
+    c->st = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreate(&c->st) != hipSuccess) {
+      delete c;
+      return GLMR_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return GLMR_OK;
+}
+
+void glmr_destroy(glmr_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->cfg.device);
+  hipStreamSynchronize(c->st);
+  for (void* p : c->allocs) hipFree(p);
+  if (c->host_scal) hipHostFree(c->host_scal);
+  for (auto& r : c->pending) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  if (c->own_stream) hipStreamDestroy(c->st);
+  delete c;
+}
+
+glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neuron, int64_t n,
+                            int32_t where) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (n < 0 || n >= (1ll << 31)) return fail(c, GLMR_EINVAL, "n_spikes must be in [0, 2^31)");
+  if (n > 0 && (!bin || !neuron)) return fail(c, GLMR_EINVAL, "null spike arrays");
+  if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  ProfScope ps(c, K_INGEST);
+  const int64_t nseg = c->NS * c->NIB;
+  IngestBufs b{};
+  b.n = n;
+  b.N = c->N;
+  b.B = c->B;
+  b.NS = c->NS;
+  b.NIB = c->NIB;
+  int64_t* dbin = nullptr;
+  int32_t* dneu = nullptr;
+  if (where == GLMR_HOST && n > 0) {
+    TRY(dalloc(c, dbin, (size_t)n));
+    TRY(dalloc(c, dneu, (size_t)n));
+    HIPCHK(c, hipMemcpyAsync(dbin, bin, n * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(dneu, neuron, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    b.bin = dbin;
+    b.neu = dneu;
+  } else {
+    b.bin = bin;
+    b.neu = neuron;
+  }
+  unsigned long long* bad = nullptr;
+  int32_t *cnt = nullptr, *cursor = nullptr, *maxmult = nullptr;
+  int64_t* scan_tmp = nullptr;
+  TRY(dalloc(c, bad, 2));
+  TRY(dalloc(c, cnt, (size_t)nseg + 1));
+  TRY(dalloc(c, cursor, (size_t)nseg + 1));
+  TRY(dalloc(c, maxmult, 1));
+  TRY(dalloc(c, scan_tmp, (size_t)ingest_scan_tmp_len(nseg)));
+  TRY(dalloc(c, c->seg_off, (size_t)nseg + 1));
+  TRY(dalloc(c, c->seg_ent, (size_t)std::max<int64_t>(n, 1)));
+  TRY(dalloc(c, c->q, (size_t)c->Np));
+  HIPCHK(c, hipMemsetAsync(bad, 0, sizeof(unsigned long long), c->st));
+  HIPCHK(c, hipMemsetAsync(bad + 1, 0xff, sizeof(unsigned long long), c->st));
+  HIPCHK(c, hipMemsetAsync(cnt, 0, (nseg + 1) * sizeof(int32_t), c->st));
+  HIPCHK(c, hipMemsetAsync(cursor, 0, (nseg + 1) * sizeof(int32_t), c->st));
+  HIPCHK(c, hipMemsetAsync(maxmult, 0, sizeof(int32_t), c->st));
+  HIPCHK(c, hipMemsetAsync(c->q, 0, c->Np * sizeof(int64_t), c->st));
+  b.bad = bad;
+  b.cnt = cnt;
+  b.off = c->seg_off;
+  b.cursor = cursor;
+  b.ent = c->seg_ent;
+  b.q = c->q;
+  b.maxmult = maxmult;
+  b.scan_tmp = scan_tmp;
+  c->have_spikes = false;
+  c->have_kernel = false;
+  unsigned long long hbad[2] = {0, 0};
+  if (n > 0) HIPCHK(c, launch_ingest_count(b, c->st));
+  HIPCHK(c, hipMemcpyAsync(hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (hbad[0] > 0) {
+    dfree(c, dbin);
+    dfree(c, dneu);
+    return fail(c, GLMR_EINVAL, "%llu spikes out of range; first at index %llu", hbad[0], hbad[1]);
+  }
+  HIPCHK(c, launch_ingest_scan(b, c->st));
+  if (n > 0) HIPCHK(c, launch_ingest_scatter(b, c->st));
+  HIPCHK(c, launch_ingest_sort(b, c->st));
+  int32_t hmax = 0;
+  HIPCHK(c, hipMemcpyAsync(&hmax, maxmult, sizeof hmax, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->planes = std::max(1, (int)hmax);
+  const size_t nm = (size_t)c->planes * c->NS * c->Np;
+  TRY(dalloc(c, c->masks, nm));
+  HIPCHK(c, hipMemsetAsync(c->masks, 0, nm * sizeof(uint64_t), c->st));
+  HIPCHK(c, launch_ingest_masks(b, c->masks, c->planes, c->Np, c->st));
+  c->q_host.assign(c->Np, 0);
+  HIPCHK(c, hipMemcpyAsync(c->q_host.data(), c->q, c->Np * sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  dfree(c, dbin);
+  dfree(c, dneu);
+  dfree(c, bad);
+  dfree(c, cnt);
+  dfree(c, cursor);
+  dfree(c, maxmult);
+  dfree(c, scan_tmp);
+  c->nspk = n;
+  c->have_spikes = true;
+  c->all_spiking = true;
+  for (int i = 0; i < c->N; ++i)
+    if (c->q_host[i] == 0) c->all_spiking = false;
+  if (c->tau > 0) TRY(build_kernel_caches(c, false));
+  if (!c->all_spiking) return fail(c, GLMR_ENOSPIKES, "some neuron has no spike");
+  return GLMR_OK;
+}
+
+glmr_status glmr_set_kernel(glmr_ctx* c, double tau) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(c, GLMR_EINVAL, "tau must be positive");
+  if (tau < c->dt) return fail(c, GLMR_EINVAL, "tau must be >= dt");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  c->tau = tau;
+  c->a = std::exp(-c->dt / tau);
+  c->have_kernel = false;
+  if (!c->have_spikes) return GLMR_OK;  // caches are built when the spikes arrive
+  return build_kernel_caches(c, false);
+}
+
+glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int32_t where) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (!J || !mu) return fail(c, GLMR_EINVAL, "null parameter arrays");
+  if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const int64_t Np = c->Np;
+  if (!c->J64) {
+    TRY(dalloc(c, c->J64, (size_t)Np * Np));
+    HIPCHK(c, hipMemsetAsync(c->J64, 0, Np * Np * sizeof(double), c->st));
+    TRY(dalloc(c, c->mu, (size_t)Np));
+    HIPCHK(c, hipMemsetAsync(c->mu, 0, Np * sizeof(double), c->st));
+    void* p = nullptr;
+    TRY(dalloc(c, (unsigned char*&)p, (size_t)Np * Np * in_bytes(c->prec)));
+    c->Jc = p;
+    TRY(dalloc(c, c->Jr, (size_t)Np * Np));
+    TRY(dalloc(c, c->rowscale, (size_t)Np));
+  }
+  HIPCHK(c, hipMemcpy2DAsync(c->J64, Np * sizeof(double), J, c->N * sizeof(double),
+                             c->N * sizeof(double), c->N, kind_from(where), c->st));
+  HIPCHK(c, hipMemcpyAsync(c->mu, mu, c->N * sizeof(double), kind_from(where), c->st));
+  TRY(prepare_params(c));
+  if (where == GLMR_HOST) HIPCHK(c, hipStreamSynchronize(c->st));
+  c->have_params = true;
+  return GLMR_OK;
+}
+
+glmr_status glmr_get_params(glmr_ctx* c, double* J, double* mu, double* tau, int32_t where) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
+  if (tau) *tau = c->tau;
+  if ((J || mu) && !c->have_params) return fail(c, GLMR_ESTATE, "no parameters set");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  if (J)
+    HIPCHK(c, hipMemcpy2DAsync(J, c->N * sizeof(double), c->J64, c->Np * sizeof(double),
+                               c->N * sizeof(double), c->N, kind_to(where), c->st));
+  if (mu) HIPCHK(c, hipMemcpyAsync(mu, c->mu, c->N * sizeof(double), kind_to(where), c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return GLMR_OK;
+}
+
+glmr_status glmr_eval(glmr_ctx* c, double* ll, double* ll_rows, double* grad_J, double* grad_mu,
+                      double* grad_tau, int32_t where) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
+  TRY(check_ready(c));
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const bool want_grad = grad_J || grad_mu;
+  const bool want_tau = grad_tau != nullptr;
+  if (want_tau && !c->have_y) TRY(build_kernel_caches(c, true));
+  TRY(eval_core(c, want_grad, want_tau));
+  if (ll_rows)
+    HIPCHK(c, hipMemcpyAsync(ll_rows, c->ll_rows, c->N * sizeof(double), kind_to(where), c->st));
+  if (grad_mu) HIPCHK(c, hipMemcpyAsync(grad_mu, c->gmu, c->N * sizeof(double), kind_to(where), c->st));
+  if (grad_J)
+    HIPCHK(c, hipMemcpy2DAsync(grad_J, c->N * sizeof(double), c->gJ, c->Np * sizeof(double),
+                               c->N * sizeof(double), c->N, kind_to(where), c->st));
+  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (ll) *ll = c->host_scal[0];
+  if (grad_tau) *grad_tau = c->host_scal[1];
+  if (!std::isfinite(c->host_scal[0])) return fail(c, GLMR_ENONFINITE, "log-likelihood is not finite");
+  return GLMR_OK;
+}
+
+glmr_status glmr_prof_enable(glmr_ctx* c, int32_t on) {
+  if (!c) return GLMR_EINVAL;
+  c->prof = on != 0;
+  return GLMR_OK;
+}
+
+void glmr_prof_reset(glmr_ctx* c) {
+  if (!c) return;
+  prof_collect(c);
+  for (int k = 0; k < K_NKIND; ++k) {
+    c->prof_ms[k] = 0;
+    c->prof_n[k] = 0;
+  }
+}
+
+int32_t glmr_prof_get(glmr_ctx* c, const char** names, double* total_ms, int64_t* launches, int32_t cap) {
+  if (!c) return 0;
+  prof_collect(c);
+  int32_t n = 0;
+  for (int k = 0; k < K_NKIND; ++k) {
+    if (c->prof_n[k] == 0) continue;
+    if (n < cap) {
+      if (names) names[n] = kKindNames[k];
+      if (total_ms) total_ms[n] = c->prof_ms[k];
+      if (launches) launches[n] = c->prof_n[k];
+    }
+    ++n;
+  }
+  return n;
+}
+
+glmr_status glmr_query(const glmr_ctx* c, int64_t* n_pad, int64_t* b_pad, int64_t* chunk_bins,
+                       int32_t* planes, int32_t* tile_n) {
+  if (!c) return GLMR_EINVAL;
+  if (n_pad) *n_pad = c->Np;
+  if (b_pad) *b_pad = c->Bp;
+  if (chunk_bins) *chunk_bins = c->L;
+  if (planes) *planes = c->planes;
+  if (tile_n) *tile_n = c->tile;
+  return GLMR_OK;
+}
+
+}  // extern "C"

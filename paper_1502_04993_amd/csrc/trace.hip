@@ -1,0 +1,182 @@
+// Parameter-free parts of the likelihood, computed once per kernel time
+// constant tau (Sec. 2.3.3 notes dSigma needs computing only once; Sec. 2.6.1
+// caches everything that does not depend on theta):
+//
+//  * carries C[s][j] = x_j[64 s], the trace at every subtile start, and
+//    CY[s][j] = dx_j/dtau at the same bins.  Over one subtile
+//      C[s+1]  = A C[s] + D[s],               A = a^64,
+//      CY[s+1] = A (CY[s] + 64 c C[s]) + DY[s],  c = dt / tau^2,
+//    with D[s] = sum_b a^(63-b), DY[s] = c sum_b (63-b) a^(63-b) over the
+//    spikes of subtile s (the grid form of Eq. (8)/(13)).  The scan runs in
+//    FP64 in three passes: local segments of 64 subtiles, a sequential pass
+//    over segment aggregates, and a fix-up that adds the carried-in state
+//    (after k subtiles: C += A^k C_in, CY += A^k CY_in + 64 k c A^k C_in).
+//
+//  * dSigma[i][j] = sum_t s_i[t] x_j[t] (Eq. (12)) and dSigmaY[i][j] =
+//    sum_t s_i[t] y_j[t] in FP64, from the spike segments: one wavefront per
+//    (64 presynaptic j) x (64 postsynaptic i) x time split, lane = j, walking
+//    the spikes of the i-block in bin order and advancing each lane's
+//    running sum over its own mask bits; accumulators in LDS; partials per
+//    split reduced in a fixed order.
+#include "common.h"
+
+namespace {
+
+__global__ void k_carry_local(CarryArgs c) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t g = blockIdx.y;
+  if (j >= c.Np) return;
+  const int64_t s0 = g * c.G;
+  const int64_t s1 = (s0 + c.G < c.NS) ? s0 + c.G : c.NS;
+  const double A = c.tab->apow[1];
+  double x = 0.0, y = 0.0;
+  for (int64_t s = s0; s < s1; ++s) {
+    c.C64[s * c.Np + j] = x;
+    if (c.want_y) c.CY64[s * c.Np + j] = y;
+    double D = 0.0, DY = 0.0;
+    for (int p = 0; p < c.planes; ++p) {
+      uint64_t mk = c.masks[((int64_t)p * c.NS + s) * c.Np + j];
+      while (mk) {
+        int b = __builtin_ctzll(mk);
+        mk &= mk - 1;
+        const double w = c.tab->pw[63 - b];
+        D += w;
+        DY += (double)(63 - b) * w;
+      }
+    }
+    y = A * (y + 64.0 * c.ctau * x) + c.ctau * DY;
+    x = A * x + D;
+  }
+  c.seg[(g * c.Np + j) * 2 + 0] = x;
+  c.seg[(g * c.Np + j) * 2 + 1] = y;
+}
+
+__global__ void k_carry_scan(CarryArgs c, int64_t nseg) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= c.Np) return;
+  double cin = 0.0, cyin = 0.0;
+  for (int64_t g = 0; g < nseg; ++g) {
+    c.segin[(g * c.Np + j) * 2 + 0] = cin;
+    c.segin[(g * c.Np + j) * 2 + 1] = cyin;
+    const int64_t s0 = g * c.G;
+    const int64_t len = (s0 + c.G < c.NS) ? c.G : c.NS - s0;
+    const double AG = c.tab->apow[len];
+    const double xe = c.seg[(g * c.Np + j) * 2 + 0];
+    const double ye = c.seg[(g * c.Np + j) * 2 + 1];
+    cyin = AG * cyin + 64.0 * (double)len * c.ctau * AG * cin + ye;
+    cin = AG * cin + xe;
+  }
+}
+
+__global__ void k_carry_apply(CarryArgs c) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t g = blockIdx.y;
+  if (j >= c.Np) return;
+  const int64_t s0 = g * c.G;
+  const int64_t s1 = (s0 + c.G < c.NS) ? s0 + c.G : c.NS;
+  const double cin = c.segin[(g * c.Np + j) * 2 + 0];
+  const double cyin = c.segin[(g * c.Np + j) * 2 + 1];
+  for (int64_t s = s0; s < s1; ++s) {
+    const int64_t k = s - s0;
+    const double Ak = c.tab->apow[k];
+    const double x = c.C64[s * c.Np + j] + Ak * cin;
+    c.C64[s * c.Np + j] = x;
+    if (c.C32) c.C32[s * c.Np + j] = (float)x;
+    if (c.want_y) {
+      const double y = c.CY64[s * c.Np + j] + Ak * cyin + 64.0 * (double)k * c.ctau * Ak * cin;
+      c.CY64[s * c.Np + j] = y;
+      if (c.CY32) c.CY32[s * c.Np + j] = (float)y;
+    }
+  }
+}
+
+// ------------------------------------------------------------ spike term
+__global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
+  __shared__ double acc[64][64];
+  __shared__ double accy[64][64];
+  const int lane = threadIdx.x;
+  const int64_t jb = blockIdx.x, ib = blockIdx.y, split = blockIdx.z;
+  const int64_t j = jb * 64 + lane;
+  const bool want_y = a.CY64 != nullptr;
+  for (int r = 0; r < 64; ++r) {
+    acc[r][lane] = 0.0;
+    accy[r][lane] = 0.0;
+  }
+  const int64_t per = (a.NS + a.splits - 1) / a.splits;
+  const int64_t sb = split * per;
+  const int64_t se = (sb + per < a.NS) ? sb + per : a.NS;
+  const double ctau = a.ctau;
+  for (int64_t s = sb; s < se; ++s) {
+    const int64_t sg = s * a.NIB + ib;
+    const int32_t e0 = a.seg_off[sg], e1 = a.seg_off[sg + 1];
+    if (e0 == e1) continue;
+    const double C = a.C64[s * a.Np + j];
+    const double CY = want_y ? a.CY64[s * a.Np + j] : 0.0;
+    uint64_t mk[4];
+    const int np = a.planes < 4 ? a.planes : 4;
+    for (int p = 0; p < np; ++p) mk[p] = a.masks[((int64_t)p * a.NS + s) * a.Np + j];
+    double run = C, P0 = 0.0, P1 = 0.0;
+    int bcur = 0;
+    for (int32_t e = e0; e < e1; ++e) {
+      const uint16_t v = a.seg_ent[e];
+      const int il = v & 63, b = v >> 6;
+      if (b > bcur) {
+        const uint64_t win = (b >= 64 ? ~0ull : ((1ull << b) - 1)) & ~((1ull << bcur) - 1);
+        for (int p = 0; p < a.planes; ++p) {
+          uint64_t m = (p < 4 ? mk[p] : a.masks[((int64_t)p * a.NS + s) * a.Np + j]) & win;
+          while (m) {
+            const int bb = __builtin_ctzll(m);
+            m &= m - 1;
+            const double w = a.tab->ainv[bb];
+            run += w;
+            P0 += w;
+            P1 += (double)(bb + 1) * w;
+          }
+        }
+        bcur = b;
+      }
+      const double pw = a.tab->pw[b];
+      acc[il][lane] += pw * run;
+      if (want_y) accy[il][lane] += pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
+    }
+  }
+  double* out = a.part + split * a.Np * a.Np;
+  for (int r = 0; r < 64; ++r) out[(ib * 64 + r) * a.Np + j] = acc[r][lane];
+  if (want_y) {
+    double* outy = a.part + ((int64_t)a.splits + split) * a.Np * a.Np;
+    for (int r = 0; r < 64; ++r) outy[(ib * 64 + r) * a.Np + j] = accy[r][lane];
+  }
+}
+
+__global__ void k_split_reduce(const double* part, int splits, int64_t n, double* out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int sp = 0; sp < splits; ++sp) v += part[sp * n + k];
+    out[k] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_carries(const CarryArgs& c, hipStream_t st) {
+  const int64_t nseg = (c.NS + c.G - 1) / c.G;
+  dim3 grid((unsigned)((c.Np + 255) / 256), (unsigned)nseg);
+  hipLaunchKernelGGL(k_carry_local, grid, dim3(256), 0, st, c);
+  hipLaunchKernelGGL(k_carry_scan, dim3((unsigned)((c.Np + 63) / 64)), dim3(64), 0, st, c, nseg);
+  hipLaunchKernelGGL(k_carry_apply, grid, dim3(256), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_spike_term(const SpikeTermArgs& a, hipStream_t st) {
+  dim3 grid((unsigned)a.NIB, (unsigned)a.NIB, (unsigned)a.splits);
+  hipLaunchKernelGGL(k_spike_term, grid, dim3(64), 0, st, a);
+  const int64_t n = a.Np * a.Np;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_split_reduce, dim3(blocks), dim3(256), 0, st, a.part, a.splits, n, a.dsig);
+  if (a.CY64 && a.dsigY)
+    hipLaunchKernelGGL(k_split_reduce, dim3(blocks), dim3(256), 0, st, a.part + a.splits * n,
+                       a.splits, n, a.dsigY);
+  return hipGetLastError();
+}

@@ -1,0 +1,254 @@
+"""Parity of the HIP likelihood path against the FP64 oracle (needs an MI355X).
+
+Tolerances (relative to the oracle at the same parameters; the parameters are
+chosen representable in the compute precision, since each mode evaluates the
+likelihood of the parameters rounded to it):
+  FP64: L 1e-12, gradient 1e-10
+  FP32: L 1e-10 at the N = 1000 workloads (the stated target), gradient 1e-6.
+        The FP32 error of L is the FP32 accumulation of U = sum_j J_ij x_j,
+        random in sign, so its relative size falls as 1/sqrt(B N); on the
+        tiny cases here (B N ~ 1e5-1e6) the bound is 1e-10 * sqrt(2e6 / (B N)).
+  BF16: L 1e-3, gradient 1e-3 (at theta = 0 and near the truth).
+Gradient error = ||g - g_oracle||_2 / ||g_oracle||_2 over (dL/dmu, dL/dJ).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import glm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-6), "bf16": (1e-3, 1e-3)}
+
+
+def ll_tol(prec, rec):
+    tl = TOL[prec][0]
+    if prec == "fp32":
+        tl *= max(1.0, (2e6 / (rec.n_bins * rec.n_neurons)) ** 0.5)
+    return tl
+
+
+def _G():
+    import paper_1502_04993_amd as G
+    return G
+
+
+def _round(J, prec):
+    if prec == "fp32":
+        return J.astype(np.float32).astype(np.float64)
+    if prec == "bf16":
+        import torch
+        return torch.tensor(J).to(torch.bfloat16).to(torch.float64).numpy()
+    return J
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _gvec(r):
+    return np.concatenate([r["gmu"], r["gJ"].ravel()])
+
+
+def run_gpu(rec, J, mu, prec, tau=None, want_tau=False, **kw):
+    G = _G()
+    ctx = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision=prec, **kw)
+    ctx.set_spikes_allow_silent(rec.bins, rec.neurons)
+    ctx.set_kernel(rec.tau if tau is None else tau)
+    ctx.set_params(J, mu)
+    out = ctx.eval(grad=True, want_tau=want_tau)
+    out["query"] = ctx.query()
+    ctx.close()
+    return out
+
+
+def report(tag, got, ref):
+    rl = abs(got["ll"] - ref["ll"]) / abs(ref["ll"])
+    rg = _rel(_gvec(got), _gvec(ref))
+    rr = float(np.max(np.abs(got["ll_rows"] - ref["ll_rows"]) / np.maximum(np.abs(ref["ll_rows"]), 1e-300)))
+    print(f"[{tag}] rel_ll={rl:.3e} rel_grad={rg:.3e} max_rel_row={rr:.3e}", flush=True)
+    sys.stdout.flush()
+    return rl, rg, rr
+
+
+_REC = {}
+
+
+def small_rec():
+    if "small" not in _REC:
+        _REC["small"] = synth.balanced(N=37, B=5000, in_frac=0.2, seed=11)
+    return _REC["small"]
+
+
+def theta_for(rec, prec, scale=0.05, seed=0):
+    rng = np.random.default_rng(seed)
+    J = rec.J + rng.normal(0, scale, rec.J.shape)
+    return _round(J, prec), rec.mu.copy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_parity_small_ragged(prec):
+    rec = small_rec()
+    J, mu = theta_for(rec, prec)
+    ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, J, mu)
+    got = run_gpu(rec, J, mu, prec)
+    rl, rg, rr = report(f"small {prec}", got, ref)
+    assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_parity_at_zero_coupling(prec):
+    rec = small_rec()
+    N = rec.n_neurons
+    J = np.zeros((N, N))
+    mu = np.zeros(N)
+    ref = O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, rec.tau, J, mu)
+    got = run_gpu(rec, J, mu, prec)
+    rl, rg, rr = report(f"zero {prec}", got, ref)
+    assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multichunk_multisplit(prec):
+    rec = synth.balanced(N=70, B=20_000, seed=5)
+    J, mu = theta_for(rec, prec, seed=1)
+    ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, J, mu)
+    got = run_gpu(rec, J, mu, prec, chunk_bins=4096)
+    assert got["query"]["chunk_bins"] == 4096
+    rl, rg, rr = report(f"chunks {prec}", got, ref)
+    assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
+
+
+def test_multiple_spikes_per_bin():
+    rng = np.random.default_rng(3)
+    N, B = 20, 3000
+    S = rng.poisson(0.03, (B, N))
+    S[100, 3] = 4
+    t, i = np.nonzero(S)
+    bins = np.repeat(t, S[t, i]).astype(np.int64)
+    neu = np.repeat(i, S[t, i]).astype(np.int32)
+    perm = rng.permutation(bins.shape[0])  # any input order
+    rec = synth.Recording("multi", N, B, 0.001, 0.01, bins[perm], neu[perm], np.zeros((N, N)),
+                          np.full(N, np.log(20.0)), 16, 0)
+    J = rng.normal(0, 0.3, (N, N))
+    mu = rec.mu
+    ref = O.loglik(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, J, mu)
+    got = run_gpu(rec, J, mu, "fp64")
+    assert got["query"]["planes"] == 4
+    rl, rg, rr = report("multi fp64", got, ref)
+    assert rl <= 1e-12 and rg <= 1e-10
+
+
+def test_edges_first_last_bin_and_silent_neuron():
+    N, B = 9, 1000
+    bins = np.array([0, 0, 999, 500, 998, 3, 700, 1, 999], np.int64)
+    neu = np.array([0, 1, 2, 3, 4, 5, 6, 7, 2], np.int32)  # neuron 8 never fires
+    rec = synth.Recording("edges", N, B, 0.001, 0.005, bins, neu, np.zeros((N, N)), np.zeros(N), 7, 0)
+    rng = np.random.default_rng(0)
+    J = rng.normal(0, 0.5, (N, N))
+    mu = rng.normal(1.0, 0.2, N)
+    G = _G()
+    ctx = G.Context(N, B, 0.001, precision="fp64")
+    with pytest.raises(G.GlmrError) as e:
+        ctx.set_spikes(bins, neu)
+    assert e.value.status == -4  # ENOSPIKES, raster kept
+    ctx.set_kernel(0.005)
+    ctx.set_params(J, mu)
+    got = ctx.eval(grad=True)
+    with pytest.raises(G.GlmrError):
+        ctx.fit(max_iter=2)  # MLE of the silent neuron does not exist
+    ctx.close()
+    ref = O.loglik(bins, neu, N, B, 0.001, 0.005, J, mu)
+    rl, rg, rr = report("edges fp64", got, ref)
+    assert rl <= 1e-12 and rg <= 1e-10
+
+
+def test_rejects_out_of_range_spikes():
+    G = _G()
+    ctx = G.Context(5, 100, 0.001, precision="fp32")
+    with pytest.raises(G.GlmrError) as e:
+        ctx.set_spikes(np.array([3, 100], np.int64), np.array([0, 1], np.int32))
+    assert e.value.status == -1 and "index 1" in str(e.value)
+    with pytest.raises(G.GlmrError):
+        ctx.set_spikes(np.array([3], np.int64), np.array([5], np.int32))
+    with pytest.raises(G.GlmrError):
+        ctx.set_kernel(0.0005)  # tau < dt
+    with pytest.raises(G.GlmrError) as e:
+        ctx.eval()
+    assert e.value.status == -6  # call order
+    ctx.close()
+
+
+def test_empty_raster():
+    N, B = 4, 600
+    G = _G()
+    ctx = G.Context(N, B, 0.001, precision="fp64")
+    st = ctx.set_spikes_allow_silent(np.zeros(0, np.int64), np.zeros(0, np.int32))
+    assert st == -4
+    ctx.set_kernel(0.01)
+    mu = np.log(np.array([2.0, 3.0, 4.0, 5.0]))
+    ctx.set_params(np.zeros((N, N)), mu)
+    got = ctx.eval(grad=True)
+    ctx.close()
+    # no spikes: L_i = -T e^{mu_i}
+    assert np.allclose(got["ll_rows"], -B * 0.001 * np.exp(mu), rtol=1e-14)
+    assert np.allclose(got["gJ"], 0.0)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6)])
+def test_tau_gradient(prec, tol):
+    rec = synth.balanced(N=40, B=6000, tau=0.008, seed=8)
+    J, mu = theta_for(rec, prec, seed=2)
+    tau = 0.012
+    ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, tau, J, mu, want_tau=True)
+    got = run_gpu(rec, J, mu, prec, tau=tau, want_tau=True)
+    r = abs(got["gtau"] - ref["gtau"]) / abs(ref["gtau"])
+    print(f"[tau {prec}] gtau={got['gtau']:.8e} ref={ref['gtau']:.8e} rel={r:.2e}", flush=True)
+    assert r <= tol
+
+
+def test_determinism_bitwise():
+    rec = small_rec()
+    J, mu = theta_for(rec, "bf16")
+    a = run_gpu(rec, J, mu, "bf16")
+    b = run_gpu(rec, J, mu, "bf16")
+    assert a["ll"] == b["ll"] and np.array_equal(a["gJ"], b["gJ"])
+
+
+def test_config1_fp64():
+    rec = synth.config1(0)
+    N = rec.n_neurons
+    for tag, J, mu in (("zero", np.zeros((N, N)), np.zeros(N)), ("truth", rec.J, rec.mu)):
+        ref = O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, rec.tau, J, mu)
+        got = run_gpu(rec, J, mu, "fp64")
+        rl, rg, rr = report(f"config1 {tag}", got, ref)
+        assert rl <= 1e-12 and rg <= 1e-10
+
+
+_BIG = {}
+
+
+def big_rec():
+    """The N = 1000 balanced network of the headline workload, 131 s long
+    (131072 bins, two oracle chunks, so the FP64 oracle finishes in seconds)."""
+    if "big" not in _BIG:
+        _BIG["big"] = synth.config2(0, B=131_072)
+    return _BIG["big"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("where", ["zero", "truth"])
+def test_n1000_parity(prec, where):
+    rec = big_rec()
+    N = rec.n_neurons
+    if where == "zero":
+        J, mu = np.zeros((N, N)), np.zeros(N)
+    else:
+        J, mu = _round(rec.J, prec), rec.mu.copy()
+    ref = O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, rec.tau, J, mu)
+    got = run_gpu(rec, J, mu, prec)
+    rl, rg, rr = report(f"n1000 {where} {prec}", got, ref)
+    assert rl <= TOL[prec][0] and rg <= TOL[prec][1]

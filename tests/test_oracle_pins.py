@@ -345,3 +345,15 @@ def test_kmeans3_fixed_point():
     for k in range(3):
         assert abs(c[k] - v[lab == k].mean()) < 1e-12
     assert (lab[:200] == 0).all()
+
+
+def test_row_subset_is_the_same_definition():
+    bins, neu, S = tiny_raster(N=6, B=700, seed=29)
+    N, B = 6, 700
+    rng = np.random.default_rng(4)
+    J = rng.normal(0, 0.5, (N, N)); mu = rng.normal(2, 0.3, N)
+    full = O.loglik(bins, neu, N, B, 0.001, 0.01, J, mu, want_tau=True)
+    sub = O.loglik(bins, neu, N, B, 0.001, 0.01, J, mu, want_tau=True, rows=[4, 1])
+    assert np.array_equal(sub["ll_rows"], full["ll_rows"][[4, 1]])
+    assert np.allclose(sub["gJ"], full["gJ"][[4, 1]], rtol=1e-13, atol=1e-13)
+    assert np.array_equal(sub["gmu"], full["gmu"][[4, 1]])
