@@ -1,0 +1,212 @@
+"""Throughput of the likelihood + gradient evaluation on one MI355X.
+
+Workload: the N = 1000 balanced network (800 E / 200 I, fixed in-degree 100,
+J_E = +0.2, J_I = -1.0, base rates U[5, 10] Hz, tau = 10 ms) recorded for
+3600 s on a 1 ms grid (B = 3.6e6 bins), synthetic, seed 0.
+
+A step is one evaluation of L and its full gradient (dL/dJ, dL/dmu) at the
+current parameters: the trace rebuild from the spike masks inside both
+contractions, kernel U (V = J x, W = exp V, row sums), kernel G (W x^T split
+over time), the FP64 reductions and the assembly.  The per-recording and
+per-tau set-up (spike ingest, carries, spike term) runs once before the timed
+region and is reported as setup_ms; a short fit reports the ascent's
+iterations per second.  value = B * N^2 / (seconds per step), in bins*N^2/s.
+
+Prints one JSON line.  N > 1 GPUs is not supported (one-GPU build).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}  # dense MFMA, flop/s
+HBM_PEAK = 8.0e12
+
+
+def gemm_source_hash() -> str:
+    h = hashlib.sha1()
+    for f in ("gemm.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1502_04993_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def traffic_from_profile(kernel: str, launches_bins: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "kernel_U_traffic_balanced_n1000.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != gemm_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def time_steps(ctx, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        ctx.eval(grad=True, rows=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = ctx.eval(grad=True, rows=False)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, r
+
+
+def kernel_times(ctx, reps: int = 2):
+    ctx.prof_reset()
+    ctx.prof(True)
+    for _ in range(reps):
+        ctx.eval(grad=True, rows=False)
+    out = ctx.prof_get()
+    ctx.prof(False)
+    return {k: (ms / reps, n // reps) for k, (ms, n) in out.items()}
+
+
+def cpu_baseline(rec, sample_bins: int):
+    """The FP64 oracle on a bounded sample of the same workload (the first
+    `sample_bins` bins), scaled to bins*N^2/s."""
+    import numpy as np
+    from oracle import glm_oracle as O
+    n_threads = os.cpu_count() or 1
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        n_threads = max(i.get("num_threads", 1) for i in info if i.get("user_api") == "blas")
+    except Exception:
+        pass
+    N = rec.n_neurons
+    t0 = time.perf_counter()
+    O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, rec.tau, rec.J, rec.mu,
+             bin_range=(0, sample_bins))
+    dt = time.perf_counter() - t0
+    return {"value": sample_bins * N * N / dt, "unit": "bins*N^2/s", "cores": int(n_threads),
+            "kind": "oracle",
+            "sample": f"FP64 L + gradient over bins [0, {sample_bins}) of the same recording "
+                      f"(N = {N}); {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--bins", type=int, default=3_600_000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample-bins", type=int, default=1_572_864)
+    ap.add_argument("--fit-iters", type=int, default=5)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run a device-to-device copy of this many MiB (a known-size "
+                         "kernel for calibrating HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "see DESIGN.md for how the evaluation would shard", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1502_04993_amd as G
+
+    torch.cuda.init()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    rec = synth.cached("config2", seed=0, B=args.bins)
+    N, B = rec.n_neurons, rec.n_bins
+    units = float(B) * N * N
+
+    def run(prec):
+        ctx = G.Context(N, B, rec.dt, precision=prec)
+        t0 = time.perf_counter()
+        ctx.set_spikes(rec.bins, rec.neurons)
+        ctx.set_kernel(rec.tau)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        ctx.set_params(rec.J, rec.mu)
+        sec, r = time_steps(ctx, args.steps, args.warmup)
+        kt = kernel_times(ctx)
+        return ctx, setup, sec, r, kt
+
+    ctx, setup, sec, r, kt = run(args.precision)
+    q = ctx.query()
+    # dominant kernel of the step
+    dom = max(("kernel_U", "kernel_G"), key=lambda k: kt.get(k, (0, 0))[0])
+    ms_total, launches = kt[dom]
+    per_launch_s = ms_total / 1e3 / launches
+    flops_launch = 2.0 * N * N * B / launches  # 2 flops per bin*N^2 per contraction
+    achieved = flops_launch / per_launch_s
+    peak = PEAK[args.precision]
+    traffic = traffic_from_profile(dom, B)
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                "kernel": dom, "launch_ms": per_launch_s * 1e3, "launches_per_step": launches,
+                "issued_frac": achieved * (q["n_pad"] / N) ** 2 / peak,
+                "per_kernel_ms": {k: v[0] for k, v in kt.items()}}
+
+    # short fit from zero: the per-row L-BFGS ascent
+    fit_info = None
+    if args.fit_iters > 0:
+        t0 = time.perf_counter()
+        fr = ctx.fit(max_iter=args.fit_iters, from_zero=True)
+        fit_info = {"iters": fr["iters"], "evals": fr["evals"],
+                    "iters_per_s": fr["iters"] / (time.perf_counter() - t0)}
+    ctx.close()
+
+    extra = {}
+    if not args.no_fp32 and args.precision != "fp32":
+        c32, setup32, sec32, r32, kt32 = run("fp32")
+        c32.close()
+        extra = {"fp32_value": units / sec32, "fp32_ms_per_step": sec32 * 1e3,
+                 "bf16_over_fp32": sec32 / sec}
+
+    out = {
+        "metric": "LL+grad throughput (bins*N^2/s) at N=1000; BF16 vs FP32 at stated grad error",
+        "value": units / sec,
+        "unit": "bins*N^2/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "balanced_n1000_indeg100_t3600s_dt1ms", "n_neurons": N,
+                   "n_bins": B, "n_spikes": rec.n_spikes, "precision": args.precision,
+                   "chunk_bins": q["chunk_bins"], "n_pad": q["n_pad"]},
+        "roofline": roofline,
+        "setup_ms": setup * 1e3,
+        "ll": r["ll"],
+        "fit": fit_info,
+    }
+    out.update(extra)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(rec, min(args.cpu_sample_bins, B))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -13,10 +13,15 @@
 //       time split (no atomics; reduced in a fixed order in FP64).
 //
 // The trace x never exists in HBM: each workgroup rebuilds the tile it needs
-// in LDS from the spike bitmasks and the per-subtile carries,
-//   x_j[64 s + m] = a^m (C[s][j] + sum_{b < m, bit b of mask(s, j)} a^-(b+1)),
-// one wavefront per 64-bin subtile (lane = bin), so the per-column mask and
-// carry are wave-uniform scalar loads.
+// in LDS from the spike bitmasks and the per-subtile carries, in scaled form
+//   x_j[64 s + m] = a^m z_j[64 s + m],
+//   z_j[64 s + m] = C[s][j] + sum_{b < m, bit b of mask(s, j)} a^-(b+1),
+// one wavefront per 64-bin subtile (lane = bin m).  z is constant down the
+// subtile for a column without spikes, so rebuilding it costs one rounding per
+// element; the carry and mask of a column are wave-uniform scalar loads.  The
+// factor a^m is applied in kernel U's epilogue (V = a^m sum_j J z) and folded
+// into the weights it stores (W' = exp(V) a^m), so kernel G contracts W' with
+// z: sum_t W' z = sum_t exp(V) x.
 //
 // Both contractions are C[m][n] = sum_k A[m][k] B[n][k] with A and B staged in
 // LDS with k contiguous (rows padded by 16 bytes).  The MFMA shapes:
@@ -25,6 +30,17 @@
 // Each lane reads 16 contiguous bytes of k per operand and block; the k order
 // inside a 16-byte group is the same for A and B, so any permutation the
 // instruction applies inside the group cancels.
+//
+// Rounding of the rebuilt trace.  Trace values recur (a^m after every isolated
+// spike), so round-to-nearest would give the same error at every occurrence and
+// bias the sums; in FP32 and BF16 modes x is rounded stochastically with
+// random bits r(t, j) = t*0x9E3779B9 + j*0x6C8E9CF5 (mod 2^32), a function of
+// the bin and the column only, so both contractions see the identical rounded
+// trace.  Rounded values are unbiased and their errors average out over t.
+//
+// Pipelining: the J (or W) tile of the next step is fetched into registers
+// and the trace tile of the next step is rebuilt into the second LDS buffer
+// while the MFMAs of the current step run; one barrier per step.
 #include "common.h"
 
 namespace {
@@ -47,7 +63,7 @@ template <> struct Pol<PREC_F64> {
   __device__ static inline int row(int r, int lane) { return (lane >> 4) + 4 * r; }
   __device__ static inline int col(int lane) { return lane & 15; }
   __device__ static inline double lam(double v) { return exp(v); }
-  __device__ static inline in_t cvt(double x) { return x; }
+  __device__ static inline in_t cvt(double x, uint32_t) { return x; }
 };
 
 template <> struct Pol<PREC_F32> {
@@ -68,7 +84,34 @@ template <> struct Pol<PREC_F32> {
   __device__ static inline int col(int lane) { return lane & 31; }
   // exp in FP64: a biased FP32 exp would bias the integral term
   __device__ static inline double lam(float v) { return exp((double)v); }
-  __device__ static inline in_t cvt(double x) { return (float)x; }
+  // stochastic rounding FP64 -> FP32 of x >= 0: add 29 random bits below the
+  // FP32 mantissa, truncate
+  __device__ static inline in_t cvt(double x, uint32_t r) {
+    uint64_t b = (uint64_t)__double_as_longlong(x) + (uint64_t)(r >> 3);
+    b &= ~((1ull << 29) - 1);
+    return (float)__longlong_as_double((long long)b);
+  }
+};
+
+// FP32 mode, kernel U/V: FP32 operands (J and the trace rounded to FP32)
+// accumulated on the FP64 MFMA.  An FP32 accumulator absorbs the many tiny
+// products of decayed traces into large partial sums, a deterministic loss
+// that does not average out (2e-8 relative in L at N = 1000, measured); FP64
+// accumulation keeps the likelihood within its 1e-10 target.
+constexpr int PREC_F32U = 16;
+template <> struct Pol<PREC_F32U> {
+  using in_t = double;
+  using c_t = double;
+  using w_t = float;
+  using gp_t = float;
+  using acc_t = f64x4;
+  using frag_t = f64x2;
+  static constexpr int MB = 16, EPL = 2, NACC = 4;
+  __device__ static inline void mma(acc_t& c, frag_t a, frag_t b) { Pol<PREC_F64>::mma(c, a, b); }
+  __device__ static inline int row(int r, int lane) { return Pol<PREC_F64>::row(r, lane); }
+  __device__ static inline int col(int lane) { return Pol<PREC_F64>::col(lane); }
+  __device__ static inline double lam(double v) { return exp(v); }
+  __device__ static inline in_t cvt(double x, uint32_t r) { return (double)Pol<PREC_F32>::cvt(x, r); }
 };
 
 template <> struct Pol<PREC_BF16> {
@@ -85,7 +128,13 @@ template <> struct Pol<PREC_BF16> {
   __device__ static inline int row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
   __device__ static inline int col(int lane) { return lane & 31; }
   __device__ static inline float lam(float v) { return __expf(v); }
-  __device__ static inline in_t cvt(float x) { return (__bf16)x; }
+  // stochastic rounding FP32 -> BF16 (v_cvt_sr_bf16_f32)
+  __device__ static inline in_t cvt(float x, uint32_t r) {
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    bf16x2 v = {};
+    v = __builtin_amdgcn_cvt_sr_bf16_f32(v, x, r, false);
+    return v[0];
+  }
 };
 
 template <typename T> __device__ inline T tab_pw(const Tables* t, int m);
@@ -97,6 +146,8 @@ template <> __device__ inline float tab_ainv<float>(const Tables* t, int b) { re
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+constexpr uint32_t SR_T = 0x9E3779B9u, SR_J = 0x6C8E9CF5u;
+
 // XCD-aware block order: the hardware deals consecutive workgroups round-robin
 // over the 8 XCDs; renumber so that each XCD receives a contiguous range of
 // logical tiles (tiles that share an operand land on the same L2).
@@ -107,67 +158,12 @@ __device__ inline int64_t xcd_logical(int64_t bid, int64_t nblk) {
   return x * q + (x < r ? x : r) + idx;
 }
 
-// Trace value at lane bin m of subtile s for column j (C: carry at the subtile
-// start), from the mask bits below m.  T is the arithmetic type.
-template <typename T, typename CT>
-__device__ inline T trace_at(const CT* __restrict__ C, const uint64_t* __restrict__ masks,
-                             int planes, int64_t NS, int64_t Np, int64_t s, int64_t j, int m,
-                             T pw_m, const Tables* tab) {
-  T run = (T)C[s * Np + j];
-  for (int p = 0; p < planes; ++p) {
-    uint64_t mk = masks[((int64_t)p * NS + s) * Np + j];
-    while (mk) {
-      int b = __builtin_ctzll(mk);
-      mk &= mk - 1;
-      if (b < m) run += tab_ainv<T>(tab, b);
-    }
-  }
-  return pw_m * run;
-}
-
-// d x / d tau at lane bin m: a^m (CY + m c C + c sum_{b<m} (m-b-1) a^-(b+1))
-template <typename T, typename CT>
-__device__ inline T ytrace_at(const CT* __restrict__ C, const CT* __restrict__ CY,
-                              const uint64_t* __restrict__ masks, int planes, int64_t NS,
-                              int64_t Np, int64_t s, int64_t j, int m, T pw_m, T ctau,
-                              const Tables* tab) {
-  T acc = (T)CY[s * Np + j] + (T)m * ctau * (T)C[s * Np + j];
-  T inner = 0;
-  for (int p = 0; p < planes; ++p) {
-    uint64_t mk = masks[((int64_t)p * NS + s) * Np + j];
-    while (mk) {
-      int b = __builtin_ctzll(mk);
-      mk &= mk - 1;
-      if (b < m) inner += (T)(m - b - 1) * tab_ainv<T>(tab, b);
-    }
-  }
-  return pw_m * (acc + ctau * inner);
-}
-
-constexpr int PAD = 16;  // bytes of padding per LDS row
-
-// Wave-uniform copy of lane `l`'s value (v_readlane): the carry and mask of a
-// column are loaded once per step by one lane each (a coalesced vector load)
-// and broadcast column by column without a memory round trip.
-__device__ inline float bcast(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ inline double bcast(double v, int l) {
-  const int64_t b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
-}
-__device__ inline uint64_t bcast(uint64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(v & 0xffffffffu), l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// x at lane bin m from the column's carry c and plane-0 mask mk (uniform);
-// further planes (several spikes in one bin) are read directly.
+// Scaled trace at lane bin m of a subtile for one column:
+//   z = x / a^m = c + sum_{b < m, bit b of the masks} a^-(b+1)
+// c (the carry) and mk (plane-0 mask) are wave-uniform; further planes
+// (several spikes in one bin) are read here.
 template <typename T>
-__device__ inline T x_from(T c, uint64_t mk, int m, T pw_m, const Tables* tab,
+__device__ inline T z_from(T c, uint64_t mk, int m, const Tables* tab,
                            const uint64_t* __restrict__ masks, int planes, int64_t NS,
                            int64_t Np, int64_t s, int64_t j) {
   T run = c;
@@ -184,11 +180,31 @@ __device__ inline T x_from(T c, uint64_t mk, int m, T pw_m, const Tables* tab,
       if (b < m) run += tab_ainv<T>(tab, b);
     }
   }
-  return pw_m * run;
+  return run;
 }
 
+// Scaled tau-derivative of the trace: y / a^m = CY + m c C + c sum_{b<m} (m-b-1) a^-(b+1)
+template <typename T, typename CT>
+__device__ inline T zy_at(const CT* __restrict__ C, const CT* __restrict__ CY,
+                          const uint64_t* __restrict__ masks, int planes, int64_t NS, int64_t Np,
+                          int64_t s, int64_t j, int m, T ctau, const Tables* tab) {
+  T acc = (T)CY[s * Np + j] + (T)m * ctau * (T)C[s * Np + j];
+  T inner = 0;
+  for (int p = 0; p < planes; ++p) {
+    uint64_t mk = masks[((int64_t)p * NS + s) * Np + j];
+    while (mk) {
+      const int b = __builtin_ctzll(mk);
+      mk &= mk - 1;
+      if (b < m) inner += (T)(m - b - 1) * tab_ainv<T>(tab, b);
+    }
+  }
+  return acc + ctau * inner;
+}
+
+constexpr int PAD = 16;  // bytes of padding per LDS row
+
 // ---------------------------------------------------------------- kernel U/V
-template <int PREC, int BI, int BT, int WGM, int WGN>
+template <int PREC, int BI, int BT, int WGM, int WGN, int DB>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
   using P = Pol<PREC>;
   using in_t = typename P::in_t;
@@ -206,11 +222,12 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
   constexpr int GROUPS = BK / P::EPL;             // 16-byte column groups per row
   constexpr int SUBS = BT / 64;
   constexpr int KC = P::EPL * (64 / P::MB);       // k per MFMA chunk
+  constexpr int ABUF = BI * ROWB, BBUF = BT * ROWB;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned char* As = smem;                       // [BI][ROWB]   J tile
-  unsigned char* Bs = smem + BI * ROWB;           // [BT][ROWB]   x tile (row = bin)
-  double* red = (double*)(smem + (BI + BT) * ROWB);  // [WGN][BI]
+  unsigned char* As0 = smem;                      // [DB][BI][ROWB]  J tile
+  unsigned char* Bs0 = smem + DB * ABUF;          // [DB][BT][ROWB]  z tile (row = bin)
+  double* red = (double*)(smem + DB * (ABUF + BBUF));  // [WGN][BI]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
@@ -224,7 +241,6 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
   const in_t* __restrict__ Jc = (const in_t*)g.Jc;
   const c_t* __restrict__ C = (const c_t*)g.C;
   const c_t* __restrict__ CY = (const c_t*)g.CY;
-  const T pw_m = tab_pw<T>(g.tab, lane);
   const T ctau = (T)g.ctau;
 
   acc_t acc[WMB][WNB];
@@ -235,7 +251,8 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
 #pragma unroll
       for (int r = 0; r < P::NACC; ++r) acc[a][b][r] = 0;
 
-  constexpr int APIECES = BI * (BK * sizeof(in_t) / 16);
+  constexpr int RP = BK * (int)sizeof(in_t) / 16;
+  constexpr int APIECES = BI * RP;
   constexpr int APT = (APIECES + NT - 1) / NT;
   i32x4 areg[APT];
   auto load_a = [&](int64_t k0) {
@@ -243,58 +260,59 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
     for (int q = 0; q < APT; ++q) {
       int piece = tid + q * NT;
       if (piece < APIECES) {
-        int r = piece / (BK * (int)sizeof(in_t) / 16), c16 = piece % (BK * (int)sizeof(in_t) / 16);
+        int r = piece / RP, c16 = piece % RP;
         areg[q] = *(const i32x4*)((const unsigned char*)(Jc + (i0 + r) * g.Np + k0) + c16 * 16);
       }
     }
   };
-  auto store_a = [&]() {
+  auto store_a = [&](unsigned char* As) {
 #pragma unroll
     for (int q = 0; q < APT; ++q) {
       int piece = tid + q * NT;
       if (piece < APIECES) {
-        int r = piece / (BK * (int)sizeof(in_t) / 16), c16 = piece % (BK * (int)sizeof(in_t) / 16);
+        int r = piece / RP, c16 = piece % RP;
         *(i32x4*)(As + r * ROWB + c16 * 16) = areg[q];
       }
     }
   };
-
-  load_a(0);
-  for (int64_t k0 = 0; k0 < g.Np; k0 += BK) {
-    store_a();
-    // rebuild the trace tile: each wave owns one subtile (lane = bin) and a
-    // share of its 16-byte column groups
-    {
-      constexpr int WPS = NW >= SUBS ? NW / SUBS : 1;  // waves per subtile
-      for (int sub = wave / WPS; sub < SUBS; sub += NW / WPS) {
-        const int64_t s = s0 + sub;
-        const int64_t jl = k0 + (lane < BK ? lane : 0);
-        const c_t cv = C[s * g.Np + jl];
-        const uint64_t mv = g.masks[s * g.Np + jl];
-        const c_t cyv = (g.mode == 1) ? CY[s * g.Np + jl] : (c_t)0;
-        for (int grp = wave % WPS; grp < GROUPS; grp += WPS) {
-          in_t v[P::EPL];
+  // rebuild the scaled trace tile z for columns [k0, k0 + BK): each wave owns
+  // one subtile (lane = bin) and a share of its 16-byte column groups
+  auto build_z = [&](int64_t k0, unsigned char* Bs) {
+    constexpr int WPS = NW >= SUBS ? NW / SUBS : 1;  // waves per subtile
+    for (int sub = wave / WPS; sub < SUBS; sub += NW / WPS) {
+      const int64_t s = s0 + sub;
+      const uint32_t rt = (uint32_t)(tt0 + sub * 64 + lane) * SR_T;
+      for (int grp = wave % WPS; grp < GROUPS; grp += WPS) {
+        const int64_t jg = k0 + grp * P::EPL;
+        const c_t* __restrict__ cg = C + s * g.Np + jg;        // wave-uniform
+        const uint64_t* __restrict__ mg = g.masks + s * g.Np + jg;
+        in_t v[P::EPL];
+        if (g.mode == 0) {
+          c_t cz[P::EPL];
+          uint64_t mz[P::EPL];
+#pragma unroll
+          for (int e = 0; e < P::EPL; ++e) { cz[e] = cg[e]; mz[e] = mg[e]; }
 #pragma unroll
           for (int e = 0; e < P::EPL; ++e) {
-            const int col = grp * P::EPL + e;
-            const c_t c = bcast(cv, col);
-            const uint64_t mk = bcast(mv, col);
-            T x;
-            if (g.mode == 0) {
-              x = x_from<T>(c, mk, lane, pw_m, g.tab, g.masks, g.planes, g.NS, g.Np, s, k0 + col);
-            } else {
-              x = ytrace_at<T, c_t>(C, CY, g.masks, g.planes, g.NS, g.Np, s, k0 + col, lane, pw_m,
-                                    ctau, g.tab);
-              (void)cyv;
-            }
-            v[e] = P::cvt(x);
+            const int64_t j = jg + e;
+            T z = cz[e];
+            if (mz[e] != 0 || g.planes > 1)
+              z = z_from<T>(cz[e], mz[e], lane, g.tab, g.masks, g.planes, g.NS, g.Np, s, j);
+            v[e] = P::cvt(z, rt + (uint32_t)j * SR_J);
           }
-          *(frag_t*)(Bs + (sub * 64 + lane) * ROWB + grp * 16) = *(frag_t*)v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < P::EPL; ++e) {
+            const int64_t j = jg + e;
+            const T z = zy_at<T, c_t>(C, CY, g.masks, g.planes, g.NS, g.Np, s, j, lane, ctau, g.tab);
+            v[e] = P::cvt(z, rt + (uint32_t)j * SR_J);
+          }
         }
+        *(frag_t*)(Bs + (sub * 64 + lane) * ROWB + grp * 16) = *(frag_t*)v;
       }
     }
-    __syncthreads();
-    if (k0 + BK < g.Np) load_a(k0 + BK);  // prefetch the next J tile into registers
+  };
+  auto mma_step = [&](const unsigned char* As, const unsigned char* Bs) {
 #pragma unroll
     for (int kc = 0; kc < BK; kc += KC) {
       frag_t af[WMB], bfr[WNB];
@@ -310,11 +328,38 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
 #pragma unroll
         for (int b = 0; b < WNB; ++b) P::mma(acc[a][b], af[a], bfr[b]);
     }
-    __syncthreads();
+  };
+
+  const int nk = (int)(g.Np / BK);
+  load_a(0);
+  store_a(As0);
+  build_z(0, Bs0);
+  __syncthreads();
+  for (int ks = 0; ks < nk; ++ks) {
+    const int cur = (DB == 2) ? (ks & 1) : 0;
+    const bool more = ks + 1 < nk;
+    if (more) load_a((int64_t)(ks + 1) * BK);
+    mma_step(As0 + cur * ABUF, Bs0 + cur * BBUF);
+    if (DB == 2) {
+      if (more) {
+        build_z((int64_t)(ks + 1) * BK, Bs0 + (cur ^ 1) * BBUF);
+        store_a(As0 + (cur ^ 1) * ABUF);
+      }
+      __syncthreads();
+    } else {
+      __syncthreads();
+      if (more) {
+        store_a(As0);
+        build_z((int64_t)(ks + 1) * BK, Bs0);
+      }
+      __syncthreads();
+    }
   }
 
-  // epilogue: W = exp(V) (mode 0) or sum W V (mode 1); per-row FP64 sums,
-  // one block-row at a time
+  // epilogue, mode 0: V = a^m acc, W = exp(V) (0 for padded bins), store
+  // W' = W a^m, sum W per row.  Mode 1: acc = sum_j J zy, and
+  // sum_t W V_y = sum_t W' acc (the a^m factors cancel).  FP64 row sums, one
+  // block-row at a time.
   w_t* __restrict__ W = (w_t*)g.W;
 #pragma unroll
   for (int a = 0; a < WMB; ++a) {
@@ -322,22 +367,24 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
 #pragma unroll
     for (int r = 0; r < P::NACC; ++r) rs[r] = 0.0;
 #pragma unroll
-    for (int b = 0; b < WNB; ++b)
+    for (int b = 0; b < WNB; ++b) {
+      const int tl = wn * WN + b * P::MB + P::col(lane);
+      const T pw = tab_pw<T>(g.tab, tl & 63);
+      const bool valid = (tt0 + tl) < g.B;
 #pragma unroll
       for (int r = 0; r < P::NACC; ++r) {
         const int il = wm * WM + a * P::MB + P::row(r, lane);
-        const int tl = wn * WN + b * P::MB + P::col(lane);
-        const bool valid = (tt0 + tl) < g.B;
         w_t* wp = W + (i0 + il) * g.L + (tl0 + tl);
         if (g.mode == 0) {
-          auto lam = P::lam(acc[a][b][r]);
+          auto lam = P::lam(pw * acc[a][b][r]);
           if (!valid) lam = 0;
-          *wp = (w_t)lam;
+          *wp = (w_t)(lam * pw);
           rs[r] += (double)lam;
         } else {
           rs[r] += (double)(*wp) * (double)acc[a][b][r];
         }
       }
+    }
     // reduce over the lanes holding the same row (the column lanes)
 #pragma unroll
     for (int r = 0; r < P::NACC; ++r) {
@@ -357,7 +404,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
 }
 
 // ---------------------------------------------------------------- kernel G
-template <int PREC, int BI, int BJ, int WGM, int WGN>
+template <int PREC, int BI, int BJ, int WGM, int WGN, int DB>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
   using P = Pol<PREC>;
   using in_t = typename P::in_t;
@@ -374,10 +421,14 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
   constexpr int WM = BI / WGM, WN = BJ / WGN;
   constexpr int WMB = WM / P::MB, WNB = WN / P::MB;
   constexpr int KC = P::EPL * (64 / P::MB);
+  constexpr int ABUF = BI * ROWB, BBUF = BJ * ROWB;
+  constexpr int CPW = BJ / NW;  // trace columns rebuilt per wave
+  constexpr int CG = 8;         // columns per scalar-load group
+  static_assert(CPW % CG == 0, "column groups");
 
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned char* As = smem;                 // [BI][ROWB]  W tile (row = neuron i)
-  unsigned char* Bs = smem + BI * ROWB;     // [BJ][ROWB]  x tile (row = neuron j)
+  unsigned char* As0 = smem;                 // [DB][BI][ROWB]  W' tile (row = neuron i)
+  unsigned char* Bs0 = smem + DB * ABUF;     // [DB][BJ][ROWB]  z tile (row = neuron j)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
@@ -390,7 +441,6 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
   const int64_t te = (tb + g.ks < g.L) ? tb + g.ks : g.L;
   const w_t* __restrict__ W = (const w_t*)g.W;
   const c_t* __restrict__ C = (const c_t*)g.C;
-  const T pw_m = tab_pw<T>(g.tab, lane);
 
   acc_t acc[WMB][WNB];
 #pragma unroll
@@ -414,7 +464,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
       }
     }
   };
-  auto store_a = [&]() {
+  auto store_a = [&](unsigned char* As) {
 #pragma unroll
     for (int q = 0; q < APT; ++q) {
       int piece = tid + q * NT;
@@ -424,26 +474,30 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
       }
     }
   };
-
-  if (tb < te) load_a(tb);
-  for (int64_t tk = tb; tk < te; tk += BK) {
-    store_a();
-    const int64_t s = (g.t0 + tk) / 64;
-    {
-      constexpr int CPW = BJ / NW;  // columns per wave (<= 64)
-      static_assert(CPW <= 64, "one column per lane in the preload");
-      const int64_t jw = j0 + wave * CPW;
-      const int64_t jl = jw + (lane < CPW ? lane : 0);
-      const c_t cv = C[s * g.Np + jl];
-      const uint64_t mv = g.masks[s * g.Np + jl];
-      for (int col = 0; col < CPW; ++col) {
-        const T x = x_from<T>(bcast(cv, col), bcast(mv, col), lane, pw_m, g.tab, g.masks, g.planes,
-                              g.NS, g.Np, s, jw + col);
-        *(in_t*)(Bs + (wave * CPW + col) * ROWB + lane * sizeof(in_t)) = P::cvt(x);
+  auto build_z = [&](int64_t tk, unsigned char* Bs) {
+    const int64_t tg = g.t0 + tk;                 // global first bin of the step
+    const int64_t s = tg / 64;
+    const uint32_t rt = (uint32_t)(tg + lane) * SR_T;
+    for (int cgi = 0; cgi < CPW; cgi += CG) {
+      const int64_t jg = j0 + wave * CPW + cgi;
+      const c_t* __restrict__ cg = C + s * g.Np + jg;         // wave-uniform
+      const uint64_t* __restrict__ mg = g.masks + s * g.Np + jg;
+      c_t cz[CG];
+      uint64_t mz[CG];
+#pragma unroll
+      for (int e = 0; e < CG; ++e) { cz[e] = cg[e]; mz[e] = mg[e]; }
+#pragma unroll
+      for (int e = 0; e < CG; ++e) {
+        const int64_t j = jg + e;
+        T z = cz[e];
+        if (mz[e] != 0 || g.planes > 1)
+          z = z_from<T>(cz[e], mz[e], lane, g.tab, g.masks, g.planes, g.NS, g.Np, s, j);
+        *(in_t*)(Bs + (wave * CPW + cgi + e) * ROWB + lane * sizeof(in_t)) =
+            P::cvt(z, rt + (uint32_t)j * SR_J);
       }
     }
-    __syncthreads();
-    if (tk + BK < te) load_a(tk + BK);
+  };
+  auto mma_step = [&](const unsigned char* As, const unsigned char* Bs) {
 #pragma unroll
     for (int kc = 0; kc < BK; kc += KC) {
       frag_t af[WMB], bfr[WNB];
@@ -459,7 +513,34 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
 #pragma unroll
         for (int b = 0; b < WNB; ++b) P::mma(acc[a][b], af[a], bfr[b]);
     }
-    __syncthreads();
+  };
+
+  if (tb < te) {
+    load_a(tb);
+    store_a(As0);
+    build_z(tb, Bs0);
+  }
+  __syncthreads();
+  int it = 0;
+  for (int64_t tk = tb; tk < te; tk += BK, ++it) {
+    const int cur = (DB == 2) ? (it & 1) : 0;
+    const bool more = tk + BK < te;
+    if (more) load_a(tk + BK);
+    mma_step(As0 + cur * ABUF, Bs0 + cur * BBUF);
+    if (DB == 2) {
+      if (more) {
+        build_z(tk + BK, Bs0 + (cur ^ 1) * BBUF);
+        store_a(As0 + (cur ^ 1) * ABUF);
+      }
+      __syncthreads();
+    } else {
+      __syncthreads();
+      if (more) {
+        store_a(As0);
+        build_z(tk + BK, Bs0);
+      }
+      __syncthreads();
+    }
   }
 
   using gp_t = typename P::gp_t;
@@ -476,13 +557,13 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
       }
 }
 
-template <int PREC, int BI, int BT, int WGM, int WGN>
+template <int PREC, int BI, int BT, int WGM, int WGN, int DB>
 hipError_t run_gemm1(const Gemm1Args& a, hipStream_t st) {
   using P = Pol<PREC>;
   constexpr int BK = 128 / sizeof(typename P::in_t);
   constexpr int ROWB = BK * sizeof(typename P::in_t) + PAD;
-  size_t lds = (size_t)(BI + BT) * ROWB + (size_t)WGN * BI * sizeof(double);
-  auto kern = k_gemm1<PREC, BI, BT, WGM, WGN>;
+  size_t lds = (size_t)DB * (BI + BT) * ROWB + (size_t)WGN * BI * sizeof(double);
+  auto kern = k_gemm1<PREC, BI, BT, WGM, WGN, DB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int64_t nblk = (int64_t)a.n_itiles * a.n_ttiles;
@@ -490,12 +571,12 @@ hipError_t run_gemm1(const Gemm1Args& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int PREC, int BI, int BJ, int WGM, int WGN>
+template <int PREC, int BI, int BJ, int WGM, int WGN, int DB>
 hipError_t run_gemm2(const Gemm2Args& a, hipStream_t st) {
   using P = Pol<PREC>;
   constexpr int ROWB = 64 * sizeof(typename P::in_t) + PAD;
-  size_t lds = (size_t)(BI + BJ) * ROWB;
-  auto kern = k_gemm2<PREC, BI, BJ, WGM, WGN>;
+  size_t lds = (size_t)DB * (BI + BJ) * ROWB;
+  auto kern = k_gemm2<PREC, BI, BJ, WGM, WGN, DB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int64_t nblk = (int64_t)a.n_splits * a.n_itiles * a.n_jtiles;
@@ -509,31 +590,31 @@ hipError_t run_gemm2(const Gemm2Args& a, hipStream_t st) {
 // neuron tile of the context (the padding unit of N).
 hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st) {
   switch (prec) {
-    case PREC_F64: return run_gemm1<PREC_F64, 128, 128, 2, 2>(a, st);
-    case PREC_F32: return run_gemm1<PREC_F32, 128, 256, 2, 2>(a, st);
+    case PREC_F64: return run_gemm1<PREC_F64, 128, 128, 2, 2, 2>(a, st);
+    case PREC_F32: return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2>(a, st);
     case PREC_BF16:
-      if (tile == 128) return run_gemm1<PREC_BF16, 128, 256, 2, 2>(a, st);
-      return run_gemm1<PREC_BF16, 256, 256, 2, 2>(a, st);
+      if (tile == 128) return run_gemm1<PREC_BF16, 128, 256, 2, 4, 2>(a, st);
+      return run_gemm1<PREC_BF16, 256, 256, 2, 4, 2>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_gemm2(int prec, int tile, const Gemm2Args& a, hipStream_t st) {
   switch (prec) {
-    case PREC_F64: return run_gemm2<PREC_F64, 128, 128, 2, 2>(a, st);
-    case PREC_F32: return run_gemm2<PREC_F32, 128, 128, 2, 2>(a, st);
+    case PREC_F64: return run_gemm2<PREC_F64, 128, 128, 2, 2, 1>(a, st);
+    case PREC_F32: return run_gemm2<PREC_F32, 128, 128, 2, 4, 2>(a, st);
     case PREC_BF16:
-      if (tile == 128) return run_gemm2<PREC_BF16, 128, 128, 2, 2>(a, st);
-      return run_gemm2<PREC_BF16, 256, 256, 2, 2>(a, st);
+      if (tile == 128) return run_gemm2<PREC_BF16, 128, 128, 2, 4, 2>(a, st);
+      return run_gemm2<PREC_BF16, 256, 256, 2, 4, 2>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 // Tile sizes the runtime must respect (rows of the neuron tile, bins of the time tile).
-extern "C++" void gemm_tiles(int prec, int tile, int* bi1, int* bt1, int* bi2, int* bj2) {
+void gemm_tiles(int prec, int tile, int* bi1, int* bt1, int* bi2, int* bj2) {
   switch (prec) {
     case PREC_F64: *bi1 = 128; *bt1 = 128; *bi2 = 128; *bj2 = 128; break;
-    case PREC_F32: *bi1 = 128; *bt1 = 256; *bi2 = 128; *bj2 = 128; break;
+    case PREC_F32: *bi1 = 128; *bt1 = 128; *bi2 = 128; *bj2 = 128; break;
     default:
       if (tile == 128) { *bi1 = 128; *bt1 = 256; *bi2 = 128; *bj2 = 128; }
       else { *bi1 = 256; *bt1 = 256; *bi2 = 256; *bj2 = 256; }

@@ -131,6 +131,19 @@ __global__ void k_prepare(int N, int64_t Np, const double* J64, const double* mu
   }
 }
 
+__global__ void k_prepare_f32u(int N, int64_t Np, const double* J64, const double* mu, double* Jc,
+                               double* Jr, double* rowscale) {
+  const int64_t n = Np * Np;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = k / Np, j = k % Np;
+    const double v = (i < N && j < N) ? (double)(float)J64[k] : 0.0;
+    Jc[k] = v;
+    Jr[k] = v;
+    if (j == 0) rowscale[i] = (i < N) ? exp(mu[i]) : 0.0;
+  }
+}
+
 __global__ void k_copy_out(const double* src, int64_t ld, double* dst, int rows, int cols) {
   const int64_t n = (int64_t)rows * cols;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
@@ -382,8 +395,8 @@ hipError_t launch_prepare_params(int prec, int N, int64_t Np, const double* J64,
       hipLaunchKernelGGL(k_prepare<double>, dim3(g), dim3(256), 0, st, N, Np, J64, mu, (double*)Jc, Jr,
                          rowscale);
       break;
-    case PREC_F32:
-      hipLaunchKernelGGL(k_prepare<float>, dim3(g), dim3(256), 0, st, N, Np, J64, mu, (float*)Jc, Jr,
+    case PREC_F32:  // FP32 values, staged as FP64 for the FP64-accumulated contraction
+      hipLaunchKernelGGL(k_prepare_f32u, dim3(g), dim3(256), 0, st, N, Np, J64, mu, (double*)Jc, Jr,
                          rowscale);
       break;
     case PREC_BF16:

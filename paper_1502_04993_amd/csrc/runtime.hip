@@ -223,6 +223,8 @@ void prof_collect(glmr_ctx* c) {
 int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 size_t in_bytes(int prec) { return prec == PREC_F64 ? 8 : prec == PREC_F32 ? 4 : prec == PREC_BF16 ? 2 : 1; }
+// bytes of the staged weight copy Jc (FP32 mode stages FP32 values as FP64)
+size_t jc_bytes(int prec) { return prec == PREC_F32 ? 8 : in_bytes(prec); }
 
 // ---------------------------------------------------------------- kernel caches
 glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
@@ -275,7 +277,7 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
   if (!c->dsig) TRY(dalloc(c, c->dsig, (size_t)nij));
   if (want_y && !c->dsigY) TRY(dalloc(c, c->dsigY, (size_t)nij));
   int64_t pairs = c->NIB * c->NIB;
-  int splits = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + pairs - 1) / pairs, c->NS));
+  int splits = (int)std::max<int64_t>(1, std::min<int64_t>((8192 + pairs - 1) / pairs, c->NS));
   // bound the partial buffer to ~512 MB
   while (splits > 1 && (size_t)splits * nij * 8 * (want_y ? 2 : 1) > (512ull << 20)) splits /= 2;
   double* part = nullptr;
@@ -899,7 +901,7 @@ glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int3
     TRY(dalloc(c, c->mu, (size_t)Np));
     HIPCHK(c, hipMemsetAsync(c->mu, 0, Np * sizeof(double), c->st));
     void* p = nullptr;
-    TRY(dalloc(c, (unsigned char*&)p, (size_t)Np * Np * in_bytes(c->prec)));
+    TRY(dalloc(c, (unsigned char*&)p, (size_t)Np * Np * jc_bytes(c->prec)));
     c->Jc = p;
     TRY(dalloc(c, c->Jr, (size_t)Np * Np));
     TRY(dalloc(c, c->rowscale, (size_t)Np));

@@ -91,16 +91,18 @@ __global__ void k_carry_apply(CarryArgs c) {
 }
 
 // ------------------------------------------------------------ spike term
+__device__ inline int lane_bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+template <bool WANT_Y>
 __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
   __shared__ double acc[64][64];
-  __shared__ double accy[64][64];
+  __shared__ double accy[WANT_Y ? 64 : 1][64];
   const int lane = threadIdx.x;
   const int64_t jb = blockIdx.x, ib = blockIdx.y, split = blockIdx.z;
   const int64_t j = jb * 64 + lane;
-  const bool want_y = a.CY64 != nullptr;
   for (int r = 0; r < 64; ++r) {
     acc[r][lane] = 0.0;
-    accy[r][lane] = 0.0;
+    if (WANT_Y) accy[r][lane] = 0.0;
   }
   const int64_t per = (a.NS + a.splits - 1) / a.splits;
   const int64_t sb = split * per;
@@ -110,39 +112,50 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
     const int64_t sg = s * a.NIB + ib;
     const int32_t e0 = a.seg_off[sg], e1 = a.seg_off[sg + 1];
     if (e0 == e1) continue;
+    // this lane's column: carry and masks of subtile s
     const double C = a.C64[s * a.Np + j];
-    const double CY = want_y ? a.CY64[s * a.Np + j] : 0.0;
-    uint64_t mk[4];
-    const int np = a.planes < 4 ? a.planes : 4;
-    for (int p = 0; p < np; ++p) mk[p] = a.masks[((int64_t)p * a.NS + s) * a.Np + j];
+    const double CY = WANT_Y ? a.CY64[s * a.Np + j] : 0.0;
+    const uint64_t m0 = a.masks[s * a.Np + j];
     double run = C, P0 = 0.0, P1 = 0.0;
     int bcur = 0;
-    for (int32_t e = e0; e < e1; ++e) {
-      const uint16_t v = a.seg_ent[e];
-      const int il = v & 63, b = v >> 6;
-      if (b > bcur) {
-        const uint64_t win = (b >= 64 ? ~0ull : ((1ull << b) - 1)) & ~((1ull << bcur) - 1);
-        for (int p = 0; p < a.planes; ++p) {
-          uint64_t m = (p < 4 ? mk[p] : a.masks[((int64_t)p * a.NS + s) * a.Np + j]) & win;
+    for (int32_t eb = e0; eb < e1; eb += 64) {
+      // one entry per lane, then walk them in order (bin order within the segment)
+      const int cnt = (e1 - eb < 64) ? e1 - eb : 64;
+      const int mine = lane < cnt ? (int)a.seg_ent[eb + lane] : 0;
+      for (int k = 0; k < cnt; ++k) {
+        const int v = lane_bcast(mine, k);
+        const int il = v & 63, b = v >> 6;
+        if (b > bcur) {
+          const uint64_t win = ((1ull << b) - 1) & ~((1ull << bcur) - 1);
+          uint64_t m = m0 & win;
           while (m) {
             const int bb = __builtin_ctzll(m);
             m &= m - 1;
             const double w = a.tab->ainv[bb];
             run += w;
-            P0 += w;
-            P1 += (double)(bb + 1) * w;
+            if (WANT_Y) { P0 += w; P1 += (double)(bb + 1) * w; }
           }
+          for (int p = 1; p < a.planes; ++p) {
+            uint64_t mp = a.masks[((int64_t)p * a.NS + s) * a.Np + j] & win;
+            while (mp) {
+              const int bb = __builtin_ctzll(mp);
+              mp &= mp - 1;
+              const double w = a.tab->ainv[bb];
+              run += w;
+              if (WANT_Y) { P0 += w; P1 += (double)(bb + 1) * w; }
+            }
+          }
+          bcur = b;
         }
-        bcur = b;
+        const double pw = a.tab->pw[b];
+        acc[il][lane] += pw * run;
+        if (WANT_Y) accy[il][lane] += pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
       }
-      const double pw = a.tab->pw[b];
-      acc[il][lane] += pw * run;
-      if (want_y) accy[il][lane] += pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
     }
   }
   double* out = a.part + split * a.Np * a.Np;
   for (int r = 0; r < 64; ++r) out[(ib * 64 + r) * a.Np + j] = acc[r][lane];
-  if (want_y) {
+  if (WANT_Y) {
     double* outy = a.part + ((int64_t)a.splits + split) * a.Np * a.Np;
     for (int r = 0; r < 64; ++r) outy[(ib * 64 + r) * a.Np + j] = accy[r][lane];
   }
@@ -170,7 +183,10 @@ hipError_t launch_carries(const CarryArgs& c, hipStream_t st) {
 
 hipError_t launch_spike_term(const SpikeTermArgs& a, hipStream_t st) {
   dim3 grid((unsigned)a.NIB, (unsigned)a.NIB, (unsigned)a.splits);
-  hipLaunchKernelGGL(k_spike_term, grid, dim3(64), 0, st, a);
+  if (a.CY64)
+    hipLaunchKernelGGL(k_spike_term<true>, grid, dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_spike_term<false>, grid, dim3(64), 0, st, a);
   const int64_t n = a.Np * a.Np;
   int blocks = (int)((n + 255) / 256);
   if (blocks > 65536) blocks = 65536;

@@ -258,3 +258,36 @@ def config5_recording(kind, N, B, seed) -> Recording:
     if kind == "balanced":
         return balanced(N=N, B=B, seed=seed, name=f"balanced_n{N}_b{B}")
     return synfire(N=N, B=B, seed=seed, name=f"synfire_n{N}_b{B}")
+
+
+# ------------------------------------------------------------------ cache
+
+CACHE_VERSION = 1
+
+
+def cached(name: str, **kw) -> Recording:
+    """Call workload function `name` (e.g. "config2") with kw, memoised on disk
+    under $SYNTH_CACHE_DIR (default /tmp/synth_cache) so that several
+    processes of one session share a generated raster."""
+    import json
+    import hashlib
+    d = os.environ.get("SYNTH_CACHE_DIR", "/tmp/synth_cache")
+    key = hashlib.sha1(json.dumps([CACHE_VERSION, name, sorted(kw.items())],
+                                  default=str).encode()).hexdigest()[:16]
+    path = os.path.join(d, f"{name}_{key}.npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        meta = json.loads(str(z["meta"]))
+        return Recording(meta["name"], meta["n_neurons"], meta["n_bins"], meta["dt"], meta["tau"],
+                         z["bins"], z["neurons"], z["J"], z["mu"], meta["n_exc"], meta["seed"],
+                         z["group_of"] if "group_of" in z.files else None)
+    rec = globals()[name](**kw)
+    os.makedirs(d, exist_ok=True)
+    meta = dict(name=rec.name, n_neurons=rec.n_neurons, n_bins=rec.n_bins, dt=rec.dt, tau=rec.tau,
+                n_exc=rec.n_exc, seed=rec.seed)
+    extra = {"group_of": rec.group_of} if rec.group_of is not None else {}
+    tmp = path + f".{os.getpid()}.tmp.npz"
+    np.savez(tmp, bins=rec.bins, neurons=rec.neurons, J=rec.J, mu=rec.mu,
+             meta=np.array(json.dumps(meta)), **extra)
+    os.replace(tmp, path)
+    return rec
