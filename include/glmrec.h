@@ -60,12 +60,14 @@ typedef enum {
 /* Arithmetic of the trace X, the weights J and the two contractions.
  * Cross-tile sums, the likelihood assembly and the ascent are FP64 in all modes. */
 typedef enum {
-  GLMR_FP64 = 0, /* X, J, U, lambda in FP64, FP64 MFMA */
-  GLMR_FP32 = 1, /* X and J in FP32 (X rounded once from FP64), FP32 MFMA,
-                    exp and the lambda sums in FP64 */
-  GLMR_BF16 = 2, /* X, J and lambda in BF16, MFMA with FP32 accumulation */
-  GLMR_FP8 = 3   /* X, J and lambda in OCP e4m3 with power-of-two scales
-                    (per chunk for X, per row for J and lambda), FP32 accumulation */
+  GLMR_FP64 = 0, /* trace, J, U, lambda in FP64; FP64 MFMA */
+  GLMR_FP32 = 1, /* trace and J in FP32 (the trace rounded stochastically from
+                    FP64); U accumulated on the FP64 MFMA, the gradient
+                    contraction on the FP32 MFMA; exp and lambda sums in FP64 */
+  GLMR_BF16 = 2, /* trace, J and lambda in BF16 (trace rounded stochastically),
+                    MFMA with FP32 accumulation */
+  GLMR_FP8 = 3   /* trace, J and lambda in OCP e4m3 with power-of-two scales,
+                    FP32 accumulation */
 } glmr_precision;
 
 typedef enum { GLMR_HOST = 0, GLMR_DEVICE = 1 } glmr_where;
@@ -107,6 +109,13 @@ glmr_status glmr_set_spikes(glmr_ctx* ctx, const int64_t* bin, const int32_t* ne
  * dSigma_ij = sum_t s_i[t] x_j[t] of Eq. (12), which Sec. 2.3.3 notes need
  * only be computed once). */
 glmr_status glmr_set_kernel(glmr_ctx* ctx, double tau);
+
+/* Change the arithmetic of later evaluations (glmr_precision).  Keeps the
+ * spikes, the kernel and the FP64 parameters; rebuilds the precision-specific
+ * buffers.  Used to finish a BF16 ascent with FP32 evaluations: BF16 rounds J
+ * to 8 bits, so the BF16 likelihood is flat below that resolution and the
+ * ascent stops within it of the optimum. */
+glmr_status glmr_set_precision(glmr_ctx* ctx, int32_t precision);
 
 /* Parameters theta_i = (mu_i, J_i1..J_iN) of Sec. 2.3.3: J is N*N doubles,
  * mu is N doubles (log base rates, 1/s), both in `where` memory. */

@@ -18,7 +18,7 @@ from ._lib import (GLMR_BF16, GLMR_DEVICE, GLMR_FP8, GLMR_FP32, GLMR_FP64, GLMR_
                    GLMR_NOT_CONVERGED, GlmrError, PRECISIONS)
 
 __all__ = ["Context", "Batch", "GlmrError", "glmr_create", "glmr_destroy", "glmr_set_spikes",
-           "glmr_set_kernel", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
+           "glmr_set_kernel", "glmr_set_precision", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
            "glmr_fit_defaults", "glmr_status_string", "glmr_last_error", "glmr_query",
            "glmr_batch_create", "glmr_batch_destroy", "glmr_batch_eval", "glmr_batch_get_grad",
            "glmr_batch_fit", "glmr_prof_enable", "glmr_prof_get", "glmr_prof_reset"]
@@ -86,6 +86,10 @@ def glmr_set_spikes(ctx, bins, neurons):
 
 def glmr_set_kernel(ctx, tau):
     return _check(L.load().glmr_set_kernel(ctx, float(tau)), ctx)
+
+
+def glmr_set_precision(ctx, precision):
+    return _check(L.load().glmr_set_precision(ctx, PRECISIONS[precision]), ctx)
 
 
 def glmr_set_params(ctx, J, mu):
@@ -252,6 +256,10 @@ class Context:
     def set_params(self, J, mu):
         return glmr_set_params(self._c, J, mu)
 
+    def set_precision(self, precision: str):
+        glmr_set_precision(self._c, precision)
+        self.precision = precision
+
     def get_params(self):
         J = np.zeros((self.N, self.N))
         mu = np.zeros(self.N)
@@ -267,14 +275,26 @@ class Context:
         return dict(ll=ll, ll_rows=ll_rows, gJ=gJ, gmu=gmu, gtau=gt)
 
     def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
-            from_zero=False):
+            from_zero=False, polish=None, polish_iter=200):
+        """Per-row L-BFGS ascent.  polish="fp32" finishes a BF16 ascent with FP32
+        evaluations from the BF16 optimum (then switches back)."""
         o = glmr_fit_defaults()
         o.max_iter, o.ftol, o.lbfgs_m, o.max_backtracks = max_iter, ftol, lbfgs_m, max_backtracks
         o.warm_start_mu, o.from_zero = int(warm_start_mu), int(from_zero)
         st, rep = glmr_fit(self._c, o)
-        return dict(status=st, converged=(st == GLMR_OK), iters=rep.iters, evals=rep.evals,
-                    ll=rep.ll, max_eta=rep.max_eta, rows_converged=rep.rows_converged,
-                    seconds=rep.seconds)
+        out = dict(status=st, converged=(st == GLMR_OK), iters=rep.iters, evals=rep.evals,
+                   ll=rep.ll, max_eta=rep.max_eta, rows_converged=rep.rows_converged,
+                   seconds=rep.seconds)
+        if polish and polish != self.precision:
+            prec0 = self.precision
+            self.set_precision(polish)
+            o.max_iter, o.from_zero, o.warm_start_mu, o.ftol = polish_iter, 0, 0, 0.0
+            st2, rep2 = glmr_fit(self._c, o)
+            self.set_precision(prec0)
+            out.update(status=st2, converged=(st2 == GLMR_OK), polish_iters=rep2.iters,
+                       polish_evals=rep2.evals, ll=rep2.ll, max_eta=rep2.max_eta,
+                       rows_converged=rep2.rows_converged, seconds=out["seconds"] + rep2.seconds)
+        return out
 
     def query(self):
         return glmr_query(self._c)

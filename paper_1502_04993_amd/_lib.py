@@ -53,6 +53,7 @@ SIGNATURES = {
     "glmr_destroy": (None, [_vp]),
     "glmr_set_spikes": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32]),
     "glmr_set_kernel": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "glmr_set_precision": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "glmr_set_params": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
     "glmr_get_params": (ctypes.c_int, [_vp, _vp, _vp, _dp, ctypes.c_int32]),
     "glmr_eval": (ctypes.c_int, [_vp, _dp, _vp, _vp, _vp, _dp, ctypes.c_int32]),

@@ -131,7 +131,8 @@ struct Gemm2Args {
   const void* C;
   const Tables* tab;
   int64_t Np, NS;
-  int64_t t0, L;
+  int64_t t0, L;           // chunk start, row pitch of W
+  int64_t Lc;              // bins of this chunk (<= L)
   int64_t ks;              // bins per split
   int n_splits, n_itiles, n_jtiles;
   void* Gp;                // [n_splits][Np][Np] float (double for F64)

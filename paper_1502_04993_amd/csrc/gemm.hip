@@ -438,7 +438,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
   const int split = (int)(logical / ((int64_t)g.n_jtiles * g.n_itiles));
   const int64_t i0 = (int64_t)itile * BI, j0 = (int64_t)jtile * BJ;
   const int64_t tb = (int64_t)split * g.ks;                 // chunk-local
-  const int64_t te = (tb + g.ks < g.L) ? tb + g.ks : g.L;
+  const int64_t te = (tb + g.ks < g.Lc) ? tb + g.ks : g.Lc;
   const w_t* __restrict__ W = (const w_t*)g.W;
   const c_t* __restrict__ C = (const c_t*)g.C;
 

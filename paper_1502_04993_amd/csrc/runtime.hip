@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -74,7 +75,7 @@ struct glmr_ctx {
   bool all_spiking = false;
 
   // kernel
-  bool have_kernel = false, have_y = false;
+  bool have_kernel = false, have_y = false, keep_y = false;
   double tau = 0, a = 0;
   Tables* tab = nullptr;
   double* C64 = nullptr;
@@ -398,17 +399,15 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       g2.NS = c->NS;
       g2.t0 = t0;
       g2.L = c->L;
+      g2.Lc = Lc;
       g2.ks = split_len(c, Lc);
       g2.n_splits = (int)((Lc + g2.ks - 1) / g2.ks);
       g2.n_itiles = (int)(Np / c->bi2);
       g2.n_jtiles = (int)(Np / c->bj2);
       g2.Gp = c->Gp;
-      // kernel G reads W rows of pitch L but only bins [0, Lc)
       {
         ProfScope ps(c, K_G);
-        Gemm2Args gg = g2;
-        gg.L = c->L;
-        HIPCHK(c, launch_gemm2(c->prec, c->tile, gg, c->st));
+        HIPCHK(c, launch_gemm2(c->prec, c->tile, g2, c->st));
       }
       ProfScope ps(c, K_RED);
       HIPCHK(c, launch_gp_reduce(c->prec, c->Gp, g2.n_splits, Np, c->G64, ci == 0, c->st));
@@ -447,6 +446,30 @@ glmr_status prepare_params(glmr_ctx* c) {
   HIPCHK(c, launch_prepare_params(c->prec, c->N, c->Np, c->J64, c->mu, c->Jc, c->Jr, c->rowscale,
                                   nullptr, c->st));
   return GLMR_OK;
+}
+
+// tiles, chunk length and split budget of the context's precision (Np fixed)
+void setup_precision(glmr_ctx* c) {
+  // neuron tile of the BF16 kernels (FP64 and FP32 use 128-row tiles)
+  if (c->prec != PREC_BF16) c->tile = 256;
+  else if (c->Np % 256 != 0 || c->cfg.tile_n == 128) c->tile = 128;
+  else if (c->cfg.tile_n == 256) c->tile = 256;
+  else c->tile = c->N > 384 ? 256 : 128;
+  gemm_tiles(c->prec, c->tile, &c->bi1, &c->bt1, &c->bi2, &c->bj2);
+  // chunk: W of at most ~1 GiB, a multiple of 4096 bins
+  int64_t L = c->cfg.chunk_bins;
+  if (L == 0) {
+    const int64_t budget = 1ll << 30;
+    L = budget / (c->Np * (int64_t)in_bytes(c->prec));
+    L = std::max<int64_t>(4096, L / 4096 * 4096);
+  } else {
+    L = rup(L, 4096);
+  }
+  c->L = std::min<int64_t>(L, c->Bp);
+  // partial buffer of kernel G: at most ~512 MB, at most 256 splits
+  const size_t gb = c->prec == PREC_F64 ? 8 : 4;
+  int64_t ms = (512ll << 20) / (int64_t)(c->Np * c->Np * gb);
+  c->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(ms, 256));
 }
 
 glmr_status check_ready(glmr_ctx* c) {
@@ -730,27 +753,11 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
   c->prec = cfg->precision;
   int tile = cfg->tile_n;
   if (tile == 0) tile = (c->prec == GLMR_BF16 && c->N <= 384) ? 128 : 256;
-  if (c->prec != GLMR_BF16) tile = 256;
-  c->tile = tile;
   c->Np = rup(c->N, tile);
   c->Bp = rup(c->B, GLMR_TT);
   c->NS = c->Bp / GLMR_SUB;
   c->NIB = c->Np / GLMR_IB;
-  gemm_tiles(c->prec, c->tile, &c->bi1, &c->bt1, &c->bi2, &c->bj2);
-  // chunk: W of at most ~1 GiB, a multiple of 4096 bins
-  int64_t L = cfg->chunk_bins;
-  if (L == 0) {
-    const int64_t budget = 1ll << 30;
-    L = budget / (c->Np * (int64_t)in_bytes(c->prec));
-    L = std::max<int64_t>(4096, L / 4096 * 4096);
-  } else {
-    L = rup(L, 4096);
-  }
-  c->L = std::min<int64_t>(L, c->Bp);
-  // partial buffer of kernel G: at most ~512 MB, at most 256 splits
-  const size_t gb = c->prec == PREC_F64 ? 8 : 4;
-  int64_t ms = (512ll << 20) / (int64_t)(c->Np * c->Np * gb);
-  c->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(ms, 256));
+  setup_precision(c);
   if (cfg->stream) {
     c->st = (hipStream_t)cfg->stream;
   } else {
@@ -870,7 +877,7 @@ glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neur
   c->all_spiking = true;
   for (int i = 0; i < c->N; ++i)
     if (c->q_host[i] == 0) c->all_spiking = false;
-  if (c->tau > 0) TRY(build_kernel_caches(c, false));
+  if (c->tau > 0) TRY(build_kernel_caches(c, c->keep_y));
   if (!c->all_spiking) return fail(c, GLMR_ENOSPIKES, "some neuron has no spike");
   return GLMR_OK;
 }
@@ -885,7 +892,8 @@ glmr_status glmr_set_kernel(glmr_ctx* c, double tau) {
   c->a = std::exp(-c->dt / tau);
   c->have_kernel = false;
   if (!c->have_spikes) return GLMR_OK;  // caches are built when the spikes arrive
-  return build_kernel_caches(c, false);
+  // once dL/dtau has been asked for, keep the tau-derivative caches current
+  return build_kernel_caches(c, c->keep_y);
 }
 
 glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int32_t where) {
@@ -915,6 +923,38 @@ glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int3
   return GLMR_OK;
 }
 
+glmr_status glmr_set_precision(glmr_ctx* c, int32_t precision) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (precision < 0 || precision > 2) return fail(c, GLMR_EINVAL, "precision must be FP64, FP32 or BF16");
+  if (precision == c->prec) return GLMR_OK;
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->prec = precision;
+  c->cfg.precision = precision;
+  setup_precision(c);
+  // buffers whose size or element type depend on the precision
+  unsigned char* w = (unsigned char*)c->W;
+  dfree(c, w);
+  c->W = nullptr;
+  unsigned char* gp = (unsigned char*)c->Gp;
+  dfree(c, gp);
+  c->Gp = nullptr;
+  dfree(c, c->rowpart);
+  dfree(c, c->rowpartV);
+  if (c->Jc) {
+    unsigned char* jc = (unsigned char*)c->Jc;
+    dfree(c, jc);
+    void* p = nullptr;
+    TRY(dalloc(c, (unsigned char*&)p, (size_t)c->Np * c->Np * jc_bytes(c->prec)));
+    c->Jc = p;
+  }
+  if (c->have_kernel) TRY(build_kernel_caches(c, c->have_y));
+  if (c->have_params) TRY(prepare_params(c));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return GLMR_OK;
+}
+
 glmr_status glmr_get_params(glmr_ctx* c, double* J, double* mu, double* tau, int32_t where) {
   if (!c) return GLMR_EINVAL;
   c->err.clear();
@@ -939,7 +979,10 @@ glmr_status glmr_eval(glmr_ctx* c, double* ll, double* ll_rows, double* grad_J, 
   HIPCHK(c, hipSetDevice(c->cfg.device));
   const bool want_grad = grad_J || grad_mu;
   const bool want_tau = grad_tau != nullptr;
-  if (want_tau && !c->have_y) TRY(build_kernel_caches(c, true));
+  if (want_tau && !c->have_y) {
+    c->keep_y = true;
+    TRY(build_kernel_caches(c, true));
+  }
   TRY(eval_core(c, want_grad, want_tau));
   if (ll_rows)
     HIPCHK(c, hipMemcpyAsync(ll_rows, c->ll_rows, c->N * sizeof(double), kind_to(where), c->st));

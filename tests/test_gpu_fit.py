@@ -73,4 +73,30 @@ def test_fit_reduced_precision_reaches_oracle_optimum(prec):
     # J leave it unchanged, so the ascent stops within that resolution of the
     # optimum (far below the separation of the classes, 0.5 and -1.5 vs 0)
     assert err < (1e-3 if prec == "fp32" else 0.1)
+    if prec == "fp32":
+        assert np.array_equal(O.classify(J), O.classify(Jn))
+    else:
+        # labels may differ only for entries this close to a k-means boundary
+        lab_g, lab_o = O.classify(J), O.classify(Jn)
+        _, c = O.kmeans3(Jn[~np.eye(N, dtype=bool)])
+        bounds = np.array([(c[0] + c[1]) / 2, (c[1] + c[2]) / 2])
+        near = np.min(np.abs(Jn[..., None] - bounds[None, None, :]), axis=-1) < 2 * err
+        assert np.all((lab_g == lab_o) | near)
+
+
+def test_bf16_fit_with_fp32_polish_matches_oracle_classification():
+    rec = synth.config1(0)
+    N, B = rec.n_neurons, rec.n_bins
+    G = _G()
+    ctx = G.Context(N, B, rec.dt, precision="bf16")
+    ctx.set_spikes(rec.bins, rec.neurons)
+    ctx.set_kernel(rec.tau)
+    rep = ctx.fit(max_iter=1000, from_zero=True, polish="fp32")
+    J, mu, _ = ctx.get_params()
+    assert ctx.precision == "bf16"
+    ctx.close()
+    Jn, mun, _ = O.newton_fit(rec.bins, rec.neurons, N, B, rec.dt, rec.tau)
+    err = np.abs(J - Jn).max()
+    print(f"[fit config1 bf16+fp32 polish] {rep} max|J-Jn|={err:.3e}", flush=True)
+    assert err < 1e-3
     assert np.array_equal(O.classify(J), O.classify(Jn))

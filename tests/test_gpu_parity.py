@@ -125,6 +125,19 @@ def test_multichunk_multisplit(prec):
     assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_last_chunk_with_partial_split(prec):
+    # 70100 bins pad to 70144 = 36864 + 33280: the second chunk's 33280 bins
+    # split into 192-bin pieces, so its last split is cut short by the chunk end
+    rec = synth.balanced(N=70, B=70_100, seed=8)
+    J, mu = theta_for(rec, prec, seed=2)
+    ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, J, mu)
+    got = run_gpu(rec, J, mu, prec, chunk_bins=36864)
+    assert got["query"]["chunk_bins"] == 36864
+    rl, rg, rr = report(f"last chunk {prec}", got, ref)
+    assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
+
+
 def test_multiple_spikes_per_bin():
     rng = np.random.default_rng(3)
     N, B = 20, 3000
