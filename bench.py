@@ -5,12 +5,15 @@ J_E = +0.2, J_I = -1.0, base rates U[5, 10] Hz, tau = 10 ms) recorded for
 3600 s on a 1 ms grid (B = 3.6e6 bins), synthetic, seed 0.
 
 A step is one evaluation of L and its full gradient (dL/dJ, dL/dmu) at the
-current parameters: the trace rebuild from the spike masks inside both
-contractions, kernel U (V = J x, W = exp V, row sums), kernel G (W x^T split
-over time), the FP64 reductions and the assembly.  The per-recording and
-per-tau set-up (spike ingest, carries, spike term) runs once before the timed
-region and is reported as setup_ms; a short fit reports the ascent's
-iterations per second.  value = B * N^2 / (seconds per step), in bins*N^2/s.
+current parameters: kernel U (V = J x, W = exp V, row sums), kernel G (W x^T
+split over time), the FP64 reductions and the assembly.  The trace x depends
+on the spikes and tau only; in BF16 it is resident by default (built once per
+tau, "trace": "resident"), otherwise ("--trace recompute", and in FP32/FP64)
+both contractions rebuild its tiles from the spike masks inside the step.
+The per-recording and per-tau set-up (spike ingest, carries, spike term,
+resident trace) runs once before the timed region and is reported as
+setup_ms; a short fit reports the ascent's iterations per second.
+value = B * N^2 / (seconds per step), in bins*N^2/s.
 
 Prints one JSON line.  N > 1 GPUs is not supported (one-GPU build).
 """
@@ -32,7 +35,7 @@ HBM_PEAK = 8.0e12
 
 def gemm_source_hash() -> str:
     h = hashlib.sha1()
-    for f in ("gemm.hip", "common.h"):
+    for f in ("gemm.hip", "gemm_res.hip", "common.h"):
         with open(os.path.join(ROOT, "paper_1502_04993_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
@@ -55,22 +58,31 @@ def traffic_from_profile(kernel: str, launches_bins: int):
 
 
 def time_steps(ctx, steps: int, warmup: int):
+    """Seconds per evaluation of L and the full gradient; the gradient stays in
+    device memory (where the ascent consumes it), L comes back to the host."""
     import torch
+    import paper_1502_04993_amd as G
+    gJ = torch.empty((ctx.N, ctx.N), dtype=torch.float64, device="cuda")
+    gmu = torch.empty(ctx.N, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
-        ctx.eval(grad=True, rows=False)
+        G.glmr_eval(ctx.handle, None, gJ, gmu)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        r = ctx.eval(grad=True, rows=False)
+        ll, _ = G.glmr_eval(ctx.handle, None, gJ, gmu)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, r
+    return (time.perf_counter() - t0) / steps, {"ll": ll}
 
 
 def kernel_times(ctx, reps: int = 2):
     ctx.prof_reset()
     ctx.prof(True)
+    import torch
+    import paper_1502_04993_amd as G
+    gJ = torch.empty((ctx.N, ctx.N), dtype=torch.float64, device="cuda")
+    gmu = torch.empty(ctx.N, dtype=torch.float64, device="cuda")
     for _ in range(reps):
-        ctx.eval(grad=True, rows=False)
+        G.glmr_eval(ctx.handle, None, gJ, gmu)
     out = ctx.prof_get()
     ctx.prof(False)
     return {k: (ms / reps, n // reps) for k, (ms, n) in out.items()}
@@ -106,6 +118,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--bins", type=int, default=3_600_000)
+    ap.add_argument("--trace", default="auto", choices=["auto", "resident", "recompute"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-bins", type=int, default=1_572_864)
@@ -138,7 +151,7 @@ def main():
     units = float(B) * N * N
 
     def run(prec):
-        ctx = G.Context(N, B, rec.dt, precision=prec)
+        ctx = G.Context(N, B, rec.dt, precision=prec, trace=args.trace if prec == "bf16" else "auto")
         t0 = time.perf_counter()
         ctx.set_spikes(rec.bins, rec.neurons)
         ctx.set_kernel(rec.tau)
@@ -196,7 +209,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "balanced_n1000_indeg100_t3600s_dt1ms", "n_neurons": N,
                    "n_bins": B, "n_spikes": rec.n_spikes, "precision": args.precision,
-                   "chunk_bins": q["chunk_bins"], "n_pad": q["n_pad"]},
+                   "chunk_bins": q["chunk_bins"], "n_pad": q["n_pad"],
+                   "trace": "resident" if q["trace_resident"] else "recompute"},
         "roofline": roofline,
         "setup_ms": setup * 1e3,
         "ll": r["ll"],

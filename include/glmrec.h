@@ -82,7 +82,16 @@ typedef struct {
   int32_t device;      /* HIP device ordinal */
   void* stream;        /* hipStream_t to run on, or NULL for the library's own stream */
   int32_t tile_n;      /* neuron tile (128 or 256); 0 = automatic */
+  int32_t trace;       /* where the BF16 trace lives (glmr_trace_mode); other
+                          precisions always rebuild it inside the contractions */
 } glmr_config;
+
+/* The trace x depends on the spikes and tau only.  GLMR_TRACE_RESIDENT builds
+ * it once per tau and keeps it in HBM (4 * Bp * Np bytes: two BF16 layouts);
+ * GLMR_TRACE_RECOMPUTE rebuilds its tiles from the spike bitmasks inside every
+ * contraction (no storage beyond the raster).  GLMR_TRACE_AUTO keeps it
+ * resident when it fits in free device memory with 4 GiB to spare. */
+typedef enum { GLMR_TRACE_AUTO = 0, GLMR_TRACE_RESIDENT = 1, GLMR_TRACE_RECOMPUTE = 2 } glmr_trace_mode;
 
 typedef struct glmr_ctx glmr_ctx;
 
@@ -207,9 +216,11 @@ int32_t glmr_prof_get(glmr_ctx* ctx, const char** names, double* total_ms, int64
 void glmr_prof_reset(glmr_ctx* ctx);
 
 /* Layout facts of a context (for tests and the bench): padded neuron count,
- * padded bin count, chunk bins, spike planes, neuron tile. */
+ * padded bin count, chunk bins, spike planes, neuron tile, and whether the
+ * trace is resident (1) or rebuilt inside the contractions (0).  Any pointer
+ * may be NULL. */
 glmr_status glmr_query(const glmr_ctx* ctx, int64_t* n_pad, int64_t* b_pad, int64_t* chunk_bins,
-                       int32_t* planes, int32_t* tile_n);
+                       int32_t* planes, int32_t* tile_n, int32_t* trace_resident);
 
 #ifdef __cplusplus
 }

@@ -59,10 +59,10 @@ def _check(status: int, ctx=None):
 # ---------------------------------------------------------------- C names
 
 def glmr_create(n_neurons, n_bins, dt, precision="fp32", device=0, stream=None, chunk_bins=0,
-                tile_n=0):
+                tile_n=0, trace="auto"):
     lib = L.load()
     cfg = L.glmr_config(n_neurons, n_bins, dt, chunk_bins, PRECISIONS[precision], device,
-                        ctypes.c_void_p(stream) if stream else None, tile_n)
+                        ctypes.c_void_p(stream) if stream else None, tile_n, L.TRACE_MODES[trace])
     out = ctypes.c_void_p()
     _check(lib.glmr_create(ctypes.byref(cfg), ctypes.byref(out)))
     return out
@@ -150,11 +150,11 @@ def glmr_last_error(ctx):
 
 def glmr_query(ctx):
     n_pad, b_pad, chunk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    planes, tile = ctypes.c_int32(), ctypes.c_int32()
+    planes, tile, resident = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(L.load().glmr_query(ctx, ctypes.byref(n_pad), ctypes.byref(b_pad), ctypes.byref(chunk),
-                               ctypes.byref(planes), ctypes.byref(tile)), ctx)
+                               ctypes.byref(planes), ctypes.byref(tile), ctypes.byref(resident)), ctx)
     return dict(n_pad=n_pad.value, b_pad=b_pad.value, chunk_bins=chunk.value, planes=planes.value,
-                tile_n=tile.value)
+                tile_n=tile.value, trace_resident=bool(resident.value))
 
 
 def glmr_prof_enable(ctx, on=True):
@@ -219,9 +219,11 @@ class Context:
     """One recording: N neurons, B bins of width dt, one precision."""
 
     def __init__(self, n_neurons: int, n_bins: int, dt: float, precision: str = "fp32",
-                 device: int = 0, stream=None, chunk_bins: int = 0, tile_n: int = 0):
+                 device: int = 0, stream=None, chunk_bins: int = 0, tile_n: int = 0,
+                 trace: str = "auto"):
         self.N, self.B, self.dt, self.precision = int(n_neurons), int(n_bins), float(dt), precision
-        self._c = glmr_create(self.N, self.B, self.dt, precision, device, stream, chunk_bins, tile_n)
+        self._c = glmr_create(self.N, self.B, self.dt, precision, device, stream, chunk_bins, tile_n,
+                              trace)
 
     def close(self):
         if self._c is not None and self._c.value:

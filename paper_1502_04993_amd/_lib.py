@@ -23,6 +23,8 @@ GLMR_ESTATE = -6
 
 GLMR_FP64, GLMR_FP32, GLMR_BF16, GLMR_FP8 = 0, 1, 2, 3
 GLMR_HOST, GLMR_DEVICE = 0, 1
+GLMR_TRACE_AUTO, GLMR_TRACE_RESIDENT, GLMR_TRACE_RECOMPUTE = 0, 1, 2
+TRACE_MODES = {"auto": GLMR_TRACE_AUTO, "resident": GLMR_TRACE_RESIDENT, "recompute": GLMR_TRACE_RECOMPUTE}
 
 PRECISIONS = {"fp64": GLMR_FP64, "fp32": GLMR_FP32, "bf16": GLMR_BF16, "fp8": GLMR_FP8}
 
@@ -30,7 +32,8 @@ PRECISIONS = {"fp64": GLMR_FP64, "fp32": GLMR_FP32, "bf16": GLMR_BF16, "fp8": GL
 class glmr_config(ctypes.Structure):
     _fields_ = [("n_neurons", ctypes.c_int32), ("n_bins", ctypes.c_int64), ("dt", ctypes.c_double),
                 ("chunk_bins", ctypes.c_int64), ("precision", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("tile_n", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("tile_n", ctypes.c_int32),
+                ("trace", ctypes.c_int32)]
 
 
 class glmr_fit_opts(ctypes.Structure):
@@ -72,7 +75,7 @@ SIGNATURES = {
     "glmr_prof_reset": (None, [_vp]),
     "glmr_query": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
-                                  ctypes.POINTER(ctypes.c_int32)]),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None

@@ -121,6 +121,7 @@ struct Gemm1Args {
   const float* xscale;     // FP8: per-chunk X scale (power of two); J row scale
   const float* jscale;
   int mode;                // 0: U -> W, 1: V = Y J^T -> sum W V
+  int w_plain;             // mode 1: W holds exp(V) (resident trace) instead of exp(V) a^m
 };
 hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st);
 
@@ -140,6 +141,45 @@ struct Gemm2Args {
   const float* wscale;
 };
 hipError_t launch_gemm2(int prec, int tile, const Gemm2Args& a, hipStream_t st);
+
+// Resident trace (BF16): x built once per tau in two layouts -----------------
+struct ResXArgs {
+  const double* C64;       // [NS][Np]
+  const uint64_t* masks;
+  int planes;
+  const Tables* tab;
+  int64_t Np, NS, Bp;
+  void* Xtj;               // [Bp][Np] bf16
+  void* Xjt;               // [Np][Bp] bf16
+};
+hipError_t launch_build_x(const ResXArgs& a, hipStream_t st);
+
+struct ResUArgs {
+  const void* Jc;          // [Np][Np] bf16
+  const void* Xtj;         // [Bp][Np] bf16
+  int64_t Np, B;
+  int64_t t0;              // first bin of this chunk
+  int64_t L;               // row pitch of W (bins)
+  int n_itiles, n_ttiles;  // neuron tiles, 256-bin tiles of this chunk
+  void* W;                 // [Np][L] bf16: exp(V)
+  double* rowpart;         // [Bp/256][Np]
+};
+struct ResGArgs {
+  const void* W;           // [Np][L] bf16
+  const void* Xjt;         // [Np][Bp] bf16
+  int64_t Np, Bp;
+  int64_t t0, L, Lc;       // chunk start, W pitch, bins of this chunk
+  int64_t ks;              // bins per split (multiple of 64)
+  int n_splits, n_itiles, n_jtiles;
+  void* Gp;                // [n_splits][Np][Np] float
+};
+struct ResShape {
+  int bm;                  // neuron tile (kernel U: bm x 256 bins; kernel G: bm x bm)
+  int wgm, wgn;            // wave grid
+};
+const ResShape* res_shapes(int* n);
+hipError_t launch_res_u(int shape, const ResUArgs& a, hipStream_t st);
+hipError_t launch_res_g(int shape, const ResGArgs& a, hipStream_t st);
 
 // Reductions and assembly (FP64) -------------------------------------------
 hipError_t launch_gp_reduce(int prec, const void* Gp, int n_splits, int64_t Np, double* G64,

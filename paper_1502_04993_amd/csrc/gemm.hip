@@ -358,7 +358,8 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
 
   // epilogue, mode 0: V = a^m acc, W = exp(V) (0 for padded bins), store
   // W' = W a^m, sum W per row.  Mode 1: acc = sum_j J zy, and
-  // sum_t W V_y = sum_t W' acc (the a^m factors cancel).  FP64 row sums, one
+  // sum_t W V_y = sum_t W' acc (the a^m factors cancel); when the weights come
+  // from the resident-trace kernel U they hold W itself and take the factor a^m.  FP64 row sums, one
   // block-row at a time.
   w_t* __restrict__ W = (w_t*)g.W;
 #pragma unroll
@@ -381,7 +382,8 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
           *wp = (w_t)(lam * pw);
           rs[r] += (double)lam;
         } else {
-          rs[r] += (double)(*wp) * (double)acc[a][b][r];
+          const double wv = g.w_plain ? (double)(*wp) * (double)pw : (double)(*wp);
+          rs[r] += wv * (double)acc[a][b][r];
         }
       }
     }

@@ -42,9 +42,11 @@ struct ProfRec {
 
 const char* const kKindNames[] = {"ingest",       "carries",     "spike_term", "kernel_U",
                                   "kernel_V",     "kernel_G",    "reduce_G",   "assemble",
-                                  "prepare",      "ascent",      "batch_U",    "batch_G"};
+                                  "prepare",      "ascent",      "batch_U",    "batch_G",
+                                  "trace_build"};
 enum {
-  K_INGEST, K_CARRY, K_SPIKE, K_U, K_V, K_G, K_RED, K_ASM, K_PREP, K_ASC, K_BU, K_BG, K_NKIND
+  K_INGEST, K_CARRY, K_SPIKE, K_U, K_V, K_G, K_RED, K_ASM, K_PREP, K_ASC, K_BU, K_BG, K_XBUILD,
+  K_NKIND
 };
 
 }  // namespace
@@ -84,6 +86,11 @@ struct glmr_ctx {
   float* CY32 = nullptr;
   double* dsig = nullptr;
   double* dsigY = nullptr;
+  // resident trace (BF16): Xtj [Bp][Np] and Xjt [Np][Bp], rebuilt per tau
+  bool resident = false;
+  unsigned char* Xtj = nullptr;
+  unsigned char* Xjt = nullptr;
+  int res_shape_u = 1, res_shape_g = 1;  // indices into res_shapes()
 
   // parameters (padded FP64 masters and the compute-precision copy)
   bool have_params = false;
@@ -228,6 +235,45 @@ size_t in_bytes(int prec) { return prec == PREC_F64 ? 8 : prec == PREC_F32 ? 4 :
 size_t jc_bytes(int prec) { return prec == PREC_F32 ? 8 : in_bytes(prec); }
 
 // ---------------------------------------------------------------- kernel caches
+// Whether the BF16 trace is kept in HBM (see glmr_trace_mode).
+bool want_resident(glmr_ctx* c) {
+  if (c->prec != PREC_BF16 || c->cfg.trace == GLMR_TRACE_RECOMPUTE) return false;
+  if (c->cfg.trace == GLMR_TRACE_RESIDENT) return true;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const size_t have = c->Xtj ? 4 * (size_t)c->Bp * c->Np : 0;  // already held
+  return 4 * (size_t)c->Bp * c->Np + (4ull << 30) <= fr + have;
+}
+
+// Build (or drop) the resident trace for the current tau; needs C64 and tab.
+glmr_status build_resident_trace(glmr_ctx* c) {
+  c->resident = want_resident(c);
+  if (!c->resident) {
+    dfree(c, c->Xtj);
+    dfree(c, c->Xjt);
+    return GLMR_OK;
+  }
+  const size_t n = (size_t)c->Bp * c->Np * 2;
+  if (!c->Xtj) TRY(dalloc(c, c->Xtj, n));
+  if (!c->Xjt) TRY(dalloc(c, c->Xjt, n));
+  ResXArgs xa{};
+  xa.C64 = c->C64;
+  xa.masks = c->masks;
+  xa.planes = c->planes;
+  xa.tab = c->tab;
+  xa.Np = c->Np;
+  xa.NS = c->NS;
+  xa.Bp = c->Bp;
+  xa.Xtj = c->Xtj;
+  xa.Xjt = c->Xjt;
+  ProfScope ps(c, K_XBUILD);
+  HIPCHK(c, launch_build_x(xa, c->st));
+  return GLMR_OK;
+}
+
 glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
   const double dt = c->dt, tau = c->tau;
   Tables h{};
@@ -272,6 +318,7 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
     ProfScope ps(c, K_CARRY);
     HIPCHK(c, launch_carries(ca, c->st));
   }
+  TRY(build_resident_trace(c));
 
   // spike term dSigma (and dSigmaY)
   const int64_t nij = c->Np * c->Np;
@@ -346,13 +393,23 @@ glmr_status ensure_workspace(glmr_ctx* c, bool want_grad, bool want_tau) {
   return GLMR_OK;
 }
 
-// split length (bins) of kernel G for a chunk of Lc bins
-int64_t split_len(const glmr_ctx* c, int64_t Lc) {
-  const int64_t tiles = (c->Np / c->bi2) * (c->Np / c->bj2);
+// split length (bins) of kernel G for a chunk of Lc bins: about 2048
+// workgroups over `tiles` output tiles, at most max_splits partials
+int64_t split_len_tiles(const glmr_ctx* c, int64_t Lc, int64_t tiles) {
   int64_t want = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
   want = std::min<int64_t>(want, c->max_splits);
   int64_t ks = rup((Lc + want - 1) / want, 64);
   return std::max<int64_t>(ks, 64);
+}
+
+int64_t split_len(const glmr_ctx* c, int64_t Lc) {
+  return split_len_tiles(c, Lc, (c->Np / c->bi2) * (c->Np / c->bj2));
+}
+
+ResShape res_shape(int k) {
+  int n = 0;
+  const ResShape* s = res_shapes(&n);
+  return s[(k >= 0 && k < n) ? k : 0];
 }
 
 glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
@@ -378,12 +435,28 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
     g1.W = c->W;
     g1.rowpart = c->rowpart;
     g1.mode = 0;
-    {
+    const ResShape su = res_shape(c->res_shape_u), sg = res_shape(c->res_shape_g);
+    if (c->resident) {
+      ResUArgs ua{};
+      ua.Jc = c->Jc;
+      ua.Xtj = c->Xtj;
+      ua.Np = Np;
+      ua.B = c->B;
+      ua.t0 = t0;
+      ua.L = c->L;
+      ua.n_itiles = (int)(Np / su.bm);
+      ua.n_ttiles = (int)(Lc / GLMR_TT);
+      ua.W = c->W;
+      ua.rowpart = c->rowpart;
+      ProfScope ps(c, K_U);
+      HIPCHK(c, launch_res_u(c->res_shape_u, ua, c->st));
+    } else {
       ProfScope ps(c, K_U);
       HIPCHK(c, launch_gemm1(c->prec, c->tile, g1, c->st));
     }
     if (want_tau) {
       g1.mode = 1;
+      g1.w_plain = c->resident ? 1 : 0;
       g1.rowpart = c->rowpartV;
       ProfScope ps(c, K_V);
       HIPCHK(c, launch_gemm1(c->prec, c->tile, g1, c->st));
@@ -405,7 +478,24 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       g2.n_itiles = (int)(Np / c->bi2);
       g2.n_jtiles = (int)(Np / c->bj2);
       g2.Gp = c->Gp;
-      {
+      if (c->resident) {
+        ResGArgs ga{};
+        ga.W = c->W;
+        ga.Xjt = c->Xjt;
+        ga.Np = Np;
+        ga.Bp = c->Bp;
+        ga.t0 = t0;
+        ga.L = c->L;
+        ga.Lc = Lc;
+        ga.n_itiles = (int)(Np / sg.bm);
+        ga.n_jtiles = (int)(Np / sg.bm);
+        ga.ks = split_len_tiles(c, Lc, (int64_t)ga.n_itiles * ga.n_jtiles);
+        ga.n_splits = (int)((Lc + ga.ks - 1) / ga.ks);
+        ga.Gp = c->Gp;
+        g2.n_splits = ga.n_splits;
+        ProfScope ps(c, K_G);
+        HIPCHK(c, launch_res_g(c->res_shape_g, ga, c->st));
+      } else {
         ProfScope ps(c, K_G);
         HIPCHK(c, launch_gemm2(c->prec, c->tile, g2, c->st));
       }
@@ -456,6 +546,17 @@ void setup_precision(glmr_ctx* c) {
   else if (c->cfg.tile_n == 256) c->tile = 256;
   else c->tile = c->N > 384 ? 256 : 128;
   gemm_tiles(c->prec, c->tile, &c->bi1, &c->bt1, &c->bi2, &c->bj2);
+  // resident-trace shapes: 256-neuron tiles when the padding allows
+  c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 1 : 3;
+  if (const char* e = std::getenv("GLMR_RES_SHAPE")) {
+    int u = -1, g = -1, n = 0;
+    const ResShape* sh = res_shapes(&n);
+    if (std::sscanf(e, "%d,%d", &u, &g) == 2 && u >= 0 && u < n && g >= 0 && g < n &&
+        c->Np % sh[u].bm == 0 && c->Np % sh[g].bm == 0) {
+      c->res_shape_u = u;
+      c->res_shape_g = g;
+    }
+  }
   // chunk: W of at most ~1 GiB, a multiple of 4096 bins
   int64_t L = c->cfg.chunk_bins;
   if (L == 0) {
@@ -1030,13 +1131,14 @@ int32_t glmr_prof_get(glmr_ctx* c, const char** names, double* total_ms, int64_t
 }
 
 glmr_status glmr_query(const glmr_ctx* c, int64_t* n_pad, int64_t* b_pad, int64_t* chunk_bins,
-                       int32_t* planes, int32_t* tile_n) {
+                       int32_t* planes, int32_t* tile_n, int32_t* trace_resident) {
   if (!c) return GLMR_EINVAL;
   if (n_pad) *n_pad = c->Np;
   if (b_pad) *b_pad = c->Bp;
   if (chunk_bins) *chunk_bins = c->L;
   if (planes) *planes = c->planes;
   if (tile_n) *tile_n = c->tile;
+  if (trace_resident) *trace_resident = c->resident ? 1 : 0;
   return GLMR_OK;
 }
 

@@ -12,6 +12,8 @@ likelihood of the parameters rounded to it):
         The gradient contraction accumulates in FP32 per time split (FP64
         across splits); absorption of tiny products there leaves ~2e-5.
   BF16: L 1e-3, gradient 1e-3 (at theta = 0 and near the truth).
+"bf16" runs the resident trace (built once per tau, kept in HBM); "bf16-rc"
+rebuilds the trace inside the contractions.
 Gradient error = ||g - g_oracle||_2 / ||g_oracle||_2 over (dL/dmu, dL/dJ).
 """
 import sys
@@ -24,7 +26,8 @@ from oracle import glm_oracle as O
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4), "bf16": (1e-3, 1e-3)}
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4), "bf16": (1e-3, 1e-3), "bf16-rc": (1e-3, 1e-3)}
+ALL = ["fp64", "fp32", "bf16", "bf16-rc"]
 
 
 def ll_tol(prec, rec):
@@ -40,6 +43,7 @@ def _G():
 
 
 def _round(J, prec):
+    prec = prec.split("-")[0]
     if prec == "fp32":
         return J.astype(np.float32).astype(np.float64)
     if prec == "bf16":
@@ -58,6 +62,9 @@ def _gvec(r):
 
 def run_gpu(rec, J, mu, prec, tau=None, want_tau=False, **kw):
     G = _G()
+    if prec == "bf16-rc":
+        prec = "bf16"
+        kw.setdefault("trace", "recompute")
     ctx = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision=prec, **kw)
     ctx.set_spikes_allow_silent(rec.bins, rec.neurons)
     ctx.set_kernel(rec.tau if tau is None else tau)
@@ -65,6 +72,8 @@ def run_gpu(rec, J, mu, prec, tau=None, want_tau=False, **kw):
     out = ctx.eval(grad=True, want_tau=want_tau)
     out["query"] = ctx.query()
     ctx.close()
+    # BF16 keeps the trace resident unless asked not to (these inputs are small)
+    assert out["query"]["trace_resident"] == (prec == "bf16" and kw.get("trace", "auto") != "recompute")
     return out
 
 
@@ -92,7 +101,7 @@ def theta_for(rec, prec, scale=0.05, seed=0):
     return _round(J, prec), rec.mu.copy()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ALL)
 def test_parity_small_ragged(prec):
     rec = small_rec()
     J, mu = theta_for(rec, prec)
@@ -102,7 +111,7 @@ def test_parity_small_ragged(prec):
     assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ALL)
 def test_parity_at_zero_coupling(prec):
     rec = small_rec()
     N = rec.n_neurons
@@ -114,7 +123,7 @@ def test_parity_at_zero_coupling(prec):
     assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ALL)
 def test_multichunk_multisplit(prec):
     rec = synth.balanced(N=70, B=20_000, seed=5)
     J, mu = theta_for(rec, prec, seed=1)
@@ -125,7 +134,7 @@ def test_multichunk_multisplit(prec):
     assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ALL)
 def test_last_chunk_with_partial_split(prec):
     # 70100 bins pad to 70144 = 36864 + 33280: the second chunk's 33280 bins
     # split into 192-bin pieces, so its last split is cut short by the chunk end
@@ -214,7 +223,7 @@ def test_empty_raster():
     assert np.allclose(got["gJ"], 0.0)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("bf16", 1e-2), ("bf16-rc", 1e-2)])
 def test_tau_gradient(prec, tol):
     rec = synth.balanced(N=40, B=6000, tau=0.008, seed=8)
     J, mu = theta_for(rec, prec, seed=2)
@@ -226,11 +235,12 @@ def test_tau_gradient(prec, tol):
     assert r <= tol
 
 
-def test_determinism_bitwise():
+@pytest.mark.parametrize("prec", ["bf16", "bf16-rc"])
+def test_determinism_bitwise(prec):
     rec = small_rec()
-    J, mu = theta_for(rec, "bf16")
-    a = run_gpu(rec, J, mu, "bf16")
-    b = run_gpu(rec, J, mu, "bf16")
+    J, mu = theta_for(rec, prec)
+    a = run_gpu(rec, J, mu, prec)
+    b = run_gpu(rec, J, mu, prec)
     assert a["ll"] == b["ll"] and np.array_equal(a["gJ"], b["gJ"])
 
 
@@ -255,7 +265,7 @@ def big_rec():
     return _BIG["big"]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16-rc"])
 @pytest.mark.parametrize("where", ["zero", "truth"])
 def test_n1000_parity(prec, where):
     rec = big_rec()
