@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--bins", type=int, default=3_600_000)
     ap.add_argument("--trace", default="auto", choices=["auto", "resident", "recompute"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-bins", type=int, default=1_572_864)
     ap.add_argument("--fit-iters", type=int, default=5)
@@ -158,11 +159,12 @@ def main():
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         ctx.set_params(rec.J, rec.mu)
+        tiles = ctx.autotune() if prec == "bf16" and not args.no_tune else (-1, -1)
         sec, r = time_steps(ctx, args.steps, args.warmup)
         kt = kernel_times(ctx)
-        return ctx, setup, sec, r, kt
+        return ctx, setup, sec, r, kt, tiles
 
-    ctx, setup, sec, r, kt = run(args.precision)
+    ctx, setup, sec, r, kt, tiles = run(args.precision)
     q = ctx.query()
     # dominant kernel of the step
     dom = max(("kernel_U", "kernel_G"), key=lambda k: kt.get(k, (0, 0))[0])
@@ -189,7 +191,7 @@ def main():
 
     extra = {}
     if not args.no_fp32 and args.precision != "fp32":
-        c32, setup32, sec32, r32, kt32 = run("fp32")
+        c32, setup32, sec32, r32, kt32, _ = run("fp32")
         c32.close()
         extra = {"fp32_value": units / sec32, "fp32_ms_per_step": sec32 * 1e3,
                  "bf16_over_fp32": sec32 / sec}
@@ -210,7 +212,8 @@ def main():
         "config": {"workload": "balanced_n1000_indeg100_t3600s_dt1ms", "n_neurons": N,
                    "n_bins": B, "n_spikes": rec.n_spikes, "precision": args.precision,
                    "chunk_bins": q["chunk_bins"], "n_pad": q["n_pad"],
-                   "trace": "resident" if q["trace_resident"] else "recompute"},
+                   "trace": "resident" if q["trace_resident"] else "recompute",
+                   "tile_shapes": list(tiles)},
         "roofline": roofline,
         "setup_ms": setup * 1e3,
         "ll": r["ll"],

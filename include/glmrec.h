@@ -222,6 +222,18 @@ void glmr_prof_reset(glmr_ctx* ctx);
 glmr_status glmr_query(const glmr_ctx* ctx, int64_t* n_pad, int64_t* b_pad, int64_t* chunk_bins,
                        int32_t* planes, int32_t* tile_n, int32_t* trace_resident);
 
+/* Autotuner: times every tile shape the library offers for the two
+ * contractions (kernel U: BI neurons x 256 bins; kernel G: BI x BI; several
+ * wave grids) on this context's own data and parameters (first time chunk,
+ * three launches each) and keeps the fastest pair for later evaluations.
+ * Applies to the resident BF16 trace; in other modes it changes nothing and
+ * reports -1.  cache_path (nullable) is a text file of earlier results keyed
+ * by GPU architecture, padded neuron count, chunk length and precision: a hit
+ * skips the timing, a miss appends a line.  Kernel U's shapes give identical
+ * results; kernel G's change only the grouping of its FP32 partial sums.
+ * Clobbers the evaluation workspace (the next glmr_eval recomputes it). */
+glmr_status glmr_autotune(glmr_ctx* ctx, const char* cache_path, int32_t* shape_u, int32_t* shape_g);
+
 #ifdef __cplusplus
 }
 #endif

@@ -157,6 +157,13 @@ def glmr_query(ctx):
                 tile_n=tile.value, trace_resident=bool(resident.value))
 
 
+def glmr_autotune(ctx, cache_path=None):
+    u, g = ctypes.c_int32(), ctypes.c_int32()
+    _check(L.load().glmr_autotune(ctx, cache_path.encode() if cache_path else None, ctypes.byref(u),
+                                  ctypes.byref(g)), ctx)
+    return u.value, g.value
+
+
 def glmr_prof_enable(ctx, on=True):
     return _check(L.load().glmr_prof_enable(ctx, 1 if on else 0), ctx)
 
@@ -300,6 +307,10 @@ class Context:
 
     def query(self):
         return glmr_query(self._c)
+
+    def autotune(self, cache_path=None):
+        """Pick the fastest tile shapes for this context's sizes (see glmr_autotune)."""
+        return glmr_autotune(self._c, cache_path)
 
     def prof(self, on=True):
         glmr_prof_enable(self._c, on)

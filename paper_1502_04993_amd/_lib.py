@@ -73,6 +73,8 @@ SIGNATURES = {
     "glmr_prof_get": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_char_p), _dp,
                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     "glmr_prof_reset": (None, [_vp]),
+    "glmr_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
     "glmr_query": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),

@@ -197,11 +197,16 @@ __device__ __forceinline__ void zero_acc(f32x16 (&acc)[MB][NB]) {
 }
 
 // ------------------------------------------------------------------ kernel U
-// tile BM neurons x 256 bins; grid n_itiles * n_ttiles (neuron tile fastest)
-template <int BM, int WGM, int WGN>
+// tile 256 bins x BI neurons; grid n_itiles * n_ttiles (neuron tile fastest).
+// The bins are the MFMA row operand (A = Xtj), the neurons the column operand
+// (B = J), so a lane's accumulators hold 4 consecutive bins of one neuron per
+// group: W is stored 8 bytes at a time and the per-neuron sums over bins are
+// mostly in-lane (then one exchange between the two half-waves and one across
+// the wave rows through LDS).
+template <int BI, int WGM, int WGN>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
-  constexpr int BN = GLMR_TT;
-  using T = Nt<BM, BN, WGM, WGN>;
+  constexpr int BT = GLMR_TT;
+  using T = Nt<BT, BI, WGM, WGN>;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -209,48 +214,48 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
   const int l32 = lane & 31, hi = lane >> 5;
   const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
   const int64_t itile = logical % g.n_itiles, ttile = logical / g.n_itiles;
-  const int64_t i0 = itile * BM, tl0 = ttile * BN, tt0 = g.t0 + tl0;
+  const int64_t i0 = itile * BI, tl0 = ttile * BT, tt0 = g.t0 + tl0;
 
   f32x16 acc[T::MB][T::NB];
   zero_acc(acc);
-  nt_loop<BM, BN, WGM, WGN>((const __bf16*)g.Jc + i0 * g.Np, g.Np, (const __bf16*)g.Xtj + tt0 * g.Np,
+  nt_loop<BT, BI, WGM, WGN>((const __bf16*)g.Xtj + tt0 * g.Np, g.Np, (const __bf16*)g.Jc + i0 * g.Np,
                             g.Np, 0, g.Np, smem, acc);
 
-  // W = exp(V) (0 past the last bin), FP64 row sums; the loop ended on a barrier,
-  // so its LDS can hold the per-wave row sums
-  double* red = (double*)smem;  // [WGN][BM]
+  // W = exp(V) (0 past the last bin); sums over the wave's bins per neuron in
+  // FP32 over at most 16 MB values, FP64 beyond.  The loop ended on a barrier,
+  // so its LDS can hold the per-wave-row sums.
+  double* red = (double*)smem;  // [WGM][BI]
   __bf16* __restrict__ W = (__bf16*)g.W;
 #pragma unroll
-  for (int a = 0; a < T::MB; ++a) {
-    double rs[16];
+  for (int b = 0; b < T::NB; ++b) {
+    const int il = wn * T::WN + b * 32 + l32;  // neuron within the tile
+    __bf16* wrow = W + (i0 + il) * g.L + tl0;
+    float cs = 0.f;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) rs[r] = 0.0;
+    for (int a = 0; a < T::MB; ++a) {
 #pragma unroll
-    for (int b = 0; b < T::NB; ++b) {
-      const int64_t tl = tl0 + wn * T::WN + b * 32 + l32;  // chunk-local bin
-      const bool valid = g.t0 + tl < g.B;
+      for (int q = 0; q < 4; ++q) {
+        const int tq = wm * T::WM + a * 32 + 8 * q + 4 * hi;  // first of 4 consecutive bins
+        float lam[4];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int il = wm * T::WM + a * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-        float lam = __expf(acc[a][b][r]);
-        if (!valid) lam = 0.f;
-        W[(i0 + il) * g.L + tl] = (__bf16)lam;
-        rs[r] += (double)lam;
+        for (int e = 0; e < 4; ++e) {
+          lam[e] = __expf(acc[a][b][4 * q + e]);
+          if (tt0 + tq + e >= g.B) lam[e] = 0.f;
+          cs += lam[e];
+        }
+        bf16x2 p0 = {(__bf16)lam[0], (__bf16)lam[1]}, p1 = {(__bf16)lam[2], (__bf16)lam[3]};
+        *(uint2*)(wrow + tq) = uint2{__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
       }
     }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double v = rs[r];
-#pragma unroll
-      for (int off = 1; off < 32; off <<= 1) v += __shfl_xor(v, off, 64);
-      if (l32 == 0) red[wn * BM + wm * T::WM + a * 32 + 8 * (r >> 2) + 4 * hi + (r & 3)] = v;
-    }
+    double v = (double)cs;
+    v += __shfl_xor(v, 32, 64);
+    if (hi == 0) red[wm * BI + il] = v;
   }
   __syncthreads();
-  for (int il = tid; il < BM; il += T::NT) {
+  for (int il = tid; il < BI; il += T::NT) {
     double v = 0.0;
 #pragma unroll
-    for (int q = 0; q < WGN; ++q) v += red[q * BM + il];
+    for (int q = 0; q < WGM; ++q) v += red[q * BI + il];
     g.rowpart[(tt0 / GLMR_TT) * g.Np + i0 + il] = v;
   }
 }
@@ -297,12 +302,12 @@ hipError_t set_lds(K kern, size_t lds) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int BM, int WGM, int WGN>
+template <int BI, int WGM, int WGN>
 hipError_t run_u(const ResUArgs& a, hipStream_t st) {
-  using T = Nt<BM, GLMR_TT, WGM, WGN>;
-  const size_t red = (size_t)WGN * BM * sizeof(double);
+  using T = Nt<GLMR_TT, BI, WGM, WGN>;
+  const size_t red = (size_t)WGM * BI * sizeof(double);
   const size_t lds = T::LDS > red ? T::LDS : red;
-  auto kern = k_res_u<BM, WGM, WGN>;
+  auto kern = k_res_u<BI, WGM, WGN>;
   hipError_t e = set_lds(kern, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)a.n_itiles * a.n_ttiles)), dim3(T::NT), lds, st, a);

@@ -412,6 +412,42 @@ ResShape res_shape(int k) {
   return s[(k >= 0 && k < n) ? k : 0];
 }
 
+// Resident-trace kernels U and G for the chunk [t0, t0 + Lc) with tile shape k.
+hipError_t launch_u_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
+  const ResShape su = res_shape(k);
+  ResUArgs ua{};
+  ua.Jc = c->Jc;
+  ua.Xtj = c->Xtj;
+  ua.Np = c->Np;
+  ua.B = c->B;
+  ua.t0 = t0;
+  ua.L = c->L;
+  ua.n_itiles = (int)(c->Np / su.bm);
+  ua.n_ttiles = (int)(Lc / GLMR_TT);
+  ua.W = c->W;
+  ua.rowpart = c->rowpart;
+  return launch_res_u(k, ua, c->st);
+}
+
+hipError_t launch_g_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc, int* n_splits) {
+  const ResShape sg = res_shape(k);
+  ResGArgs ga{};
+  ga.W = c->W;
+  ga.Xjt = c->Xjt;
+  ga.Np = c->Np;
+  ga.Bp = c->Bp;
+  ga.t0 = t0;
+  ga.L = c->L;
+  ga.Lc = Lc;
+  ga.n_itiles = (int)(c->Np / sg.bm);
+  ga.n_jtiles = (int)(c->Np / sg.bm);
+  ga.ks = split_len_tiles(c, Lc, (int64_t)ga.n_itiles * ga.n_jtiles);
+  ga.n_splits = (int)((Lc + ga.ks - 1) / ga.ks);
+  ga.Gp = c->Gp;
+  *n_splits = ga.n_splits;
+  return launch_res_g(k, ga, c->st);
+}
+
 glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
   TRY(ensure_workspace(c, want_grad, want_tau));
   const int64_t Np = c->Np;
@@ -435,21 +471,9 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
     g1.W = c->W;
     g1.rowpart = c->rowpart;
     g1.mode = 0;
-    const ResShape su = res_shape(c->res_shape_u), sg = res_shape(c->res_shape_g);
     if (c->resident) {
-      ResUArgs ua{};
-      ua.Jc = c->Jc;
-      ua.Xtj = c->Xtj;
-      ua.Np = Np;
-      ua.B = c->B;
-      ua.t0 = t0;
-      ua.L = c->L;
-      ua.n_itiles = (int)(Np / su.bm);
-      ua.n_ttiles = (int)(Lc / GLMR_TT);
-      ua.W = c->W;
-      ua.rowpart = c->rowpart;
       ProfScope ps(c, K_U);
-      HIPCHK(c, launch_res_u(c->res_shape_u, ua, c->st));
+      HIPCHK(c, launch_u_chunk(c, c->res_shape_u, t0, Lc));
     } else {
       ProfScope ps(c, K_U);
       HIPCHK(c, launch_gemm1(c->prec, c->tile, g1, c->st));
@@ -479,22 +503,8 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       g2.n_jtiles = (int)(Np / c->bj2);
       g2.Gp = c->Gp;
       if (c->resident) {
-        ResGArgs ga{};
-        ga.W = c->W;
-        ga.Xjt = c->Xjt;
-        ga.Np = Np;
-        ga.Bp = c->Bp;
-        ga.t0 = t0;
-        ga.L = c->L;
-        ga.Lc = Lc;
-        ga.n_itiles = (int)(Np / sg.bm);
-        ga.n_jtiles = (int)(Np / sg.bm);
-        ga.ks = split_len_tiles(c, Lc, (int64_t)ga.n_itiles * ga.n_jtiles);
-        ga.n_splits = (int)((Lc + ga.ks - 1) / ga.ks);
-        ga.Gp = c->Gp;
-        g2.n_splits = ga.n_splits;
         ProfScope ps(c, K_G);
-        HIPCHK(c, launch_res_g(c->res_shape_g, ga, c->st));
+        HIPCHK(c, launch_g_chunk(c, c->res_shape_g, t0, Lc, &g2.n_splits));
       } else {
         ProfScope ps(c, K_G);
         HIPCHK(c, launch_gemm2(c->prec, c->tile, g2, c->st));
@@ -547,7 +557,7 @@ void setup_precision(glmr_ctx* c) {
   else c->tile = c->N > 384 ? 256 : 128;
   gemm_tiles(c->prec, c->tile, &c->bi1, &c->bt1, &c->bi2, &c->bj2);
   // resident-trace shapes: 256-neuron tiles when the padding allows
-  c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 1 : 3;
+  c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 2 : 3;
   if (const char* e = std::getenv("GLMR_RES_SHAPE")) {
     int u = -1, g = -1, n = 0;
     const ResShape* sh = res_shapes(&n);
@@ -557,10 +567,10 @@ void setup_precision(glmr_ctx* c) {
       c->res_shape_g = g;
     }
   }
-  // chunk: W of at most ~1 GiB, a multiple of 4096 bins
+  // chunk: W of at most ~4 GiB, a multiple of 4096 bins
   int64_t L = c->cfg.chunk_bins;
   if (L == 0) {
-    const int64_t budget = 1ll << 30;
+    const int64_t budget = 4ll << 30;
     L = budget / (c->Np * (int64_t)in_bytes(c->prec));
     L = std::max<int64_t>(4096, L / 4096 * 4096);
   } else {
@@ -1143,3 +1153,103 @@ glmr_status glmr_query(const glmr_ctx* c, int64_t* n_pad, int64_t* b_pad, int64_
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+// mean milliseconds of `reps` launches of fn on the context's stream (after one warm-up)
+template <typename F>
+glmr_status time_launches(glmr_ctx* c, F fn, int reps, double* ms) {
+  hipEvent_t a, b;
+  HIPCHK(c, hipEventCreate(&a));
+  HIPCHK(c, hipEventCreate(&b));
+  glmr_status st = GLMR_OK;
+  float el = 0.f;
+  if (fn() != hipSuccess) st = fail(c, GLMR_EDEVICE, "autotune launch failed");
+  if (st == GLMR_OK && hipEventRecord(a, c->st) != hipSuccess) st = fail(c, GLMR_EDEVICE, "event record");
+  for (int r = 0; st == GLMR_OK && r < reps; ++r)
+    if (fn() != hipSuccess) st = fail(c, GLMR_EDEVICE, "autotune launch failed");
+  if (st == GLMR_OK && (hipEventRecord(b, c->st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                        hipEventElapsedTime(&el, a, b) != hipSuccess))
+    st = fail(c, GLMR_EDEVICE, "event timing");
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  *ms = el / reps;
+  return st;
+}
+
+std::string tune_key(glmr_ctx* c) {
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->cfg.device) == hipSuccess) arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s %lld %lld %d", arch.c_str(), (long long)c->Np, (long long)c->L,
+                c->prec);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" glmr_status glmr_autotune(glmr_ctx* c, const char* cache_path, int32_t* shape_u,
+                                     int32_t* shape_g) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  TRY(check_ready(c));
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  if (!c->resident) {
+    if (shape_u) *shape_u = -1;
+    if (shape_g) *shape_g = -1;
+    return GLMR_OK;  // the rebuild kernels have one shape per precision
+  }
+  const std::string key = tune_key(c);
+  int n = 0;
+  const ResShape* sh = res_shapes(&n);
+  int best_u = -1, best_g = -1;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        char arch[128];
+        long long np = 0, l = 0;
+        int prec = -1, u = -1, g = -1;
+        if (std::sscanf(line, "glmrec-tune %127s %lld %lld %d %d %d", arch, &np, &l, &prec, &u, &g) == 6) {
+          char k2[256];
+          std::snprintf(k2, sizeof(k2), "%s %lld %lld %d", arch, np, l, prec);
+          if (key == k2 && u >= 0 && u < n && g >= 0 && g < n && c->Np % sh[u].bm == 0 &&
+              c->Np % sh[g].bm == 0) {
+            best_u = u;  // the last matching line wins
+            best_g = g;
+          }
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  if (best_u < 0) {
+    TRY(ensure_workspace(c, true, false));
+    const int64_t Lc = std::min<int64_t>(c->L, c->Bp);
+    double tu = 1e300, tg = 1e300;
+    for (int k = 0; k < n; ++k) {
+      if (c->Np % sh[k].bm != 0) continue;
+      double ms = 0;
+      TRY(time_launches(c, [&] { return launch_u_chunk(c, k, 0, Lc); }, 3, &ms));
+      if (ms < tu) { tu = ms; best_u = k; }
+      int ns = 0;
+      TRY(time_launches(c, [&] { return launch_g_chunk(c, k, 0, Lc, &ns); }, 3, &ms));
+      if (ms < tg) { tg = ms; best_g = k; }
+    }
+    if (cache_path) {
+      if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "glmrec-tune %s %d %d %.4f %.4f\n", key.c_str(), best_u, best_g, tu, tg);
+        std::fclose(f);
+      }
+    }
+  }
+  c->res_shape_u = best_u;
+  c->res_shape_g = best_g;
+  if (shape_u) *shape_u = best_u;
+  if (shape_g) *shape_g = best_g;
+  return GLMR_OK;
+}

@@ -1,0 +1,91 @@
+"""Tile shapes of the resident BF16 contractions and the autotuner (needs an MI355X).
+
+Kernel U accumulates every V in the same k order whatever the tile shape;
+the shapes differ only in how the FP32 sums of exp(V) over a wave's bins
+are grouped before the FP64 sums, and kernel G's in how its FP32 partials
+are grouped over time.  So all shapes agree far inside the BF16 tolerance.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import glm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+N_SHAPES = 5
+
+
+def _ctx(rec, shape=None):
+    import paper_1502_04993_amd as G
+    old = os.environ.pop("GLMR_RES_SHAPE", None)
+    if shape is not None:
+        os.environ["GLMR_RES_SHAPE"] = f"{shape},{shape}"
+    try:
+        ctx = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision="bf16")
+    finally:
+        os.environ.pop("GLMR_RES_SHAPE", None)
+        if old is not None:
+            os.environ["GLMR_RES_SHAPE"] = old
+    ctx.set_spikes(rec.bins, rec.neurons)
+    ctx.set_kernel(rec.tau)
+    return ctx
+
+
+def test_every_shape_agrees_and_matches_oracle():
+    rec = synth.balanced(N=512, B=40_000, seed=21)
+    J, mu = rec.J, rec.mu
+    import torch
+    Jb = torch.tensor(J).to(torch.bfloat16).to(torch.float64).numpy()
+    ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, Jb, mu)
+    gref = np.concatenate([ref["gmu"], ref["gJ"].ravel()])
+    lls, grads = [], []
+    for k in range(N_SHAPES):
+        ctx = _ctx(rec, k)
+        ctx.set_params(Jb, mu)
+        r = ctx.eval(grad=True)
+        assert ctx.query()["trace_resident"]
+        ctx.close()
+        g = np.concatenate([r["gmu"], r["gJ"].ravel()])
+        rl = abs(r["ll"] - ref["ll"]) / abs(ref["ll"])
+        rg = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+        print(f"[shape {k}] rel_ll={rl:.3e} rel_grad={rg:.3e}", flush=True)
+        assert rl <= 1e-3 and rg <= 1e-3
+        lls.append(r["ll"])
+        grads.append(g)
+    assert all(abs(l - lls[0]) <= 1e-9 * abs(lls[0]) for l in lls)
+    for g in grads[1:]:
+        assert np.linalg.norm(g - grads[0]) / np.linalg.norm(grads[0]) < 1e-5
+
+
+def test_autotune_picks_valid_shapes_and_caches(tmp_path):
+    rec = synth.balanced(N=384, B=30_000, seed=22)  # Np = 384: only the 128-neuron tiles fit
+    cache = str(tmp_path / "tune.txt")
+    ctx = _ctx(rec)
+    ctx.set_params(rec.J, rec.mu)
+    u, g = ctx.autotune(cache)
+    assert u in (3, 4) and g in (3, 4)
+    a = ctx.eval(grad=True)
+    ctx.close()
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("glmrec-tune ")
+    ctx = _ctx(rec)
+    ctx.set_params(rec.J, rec.mu)
+    assert ctx.autotune(cache) == (u, g)  # served from the cache
+    b = ctx.eval(grad=True)
+    ctx.close()
+    assert len(open(cache).read().splitlines()) == 1
+    assert a["ll"] == b["ll"] and np.array_equal(a["gJ"], b["gJ"])
+
+
+def test_autotune_is_a_no_op_without_resident_trace():
+    rec = synth.balanced(N=64, B=5_000, seed=23)
+    import paper_1502_04993_amd as G
+    ctx = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision="fp32")
+    ctx.set_spikes(rec.bins, rec.neurons)
+    ctx.set_kernel(rec.tau)
+    ctx.set_params(rec.J, rec.mu)
+    assert ctx.autotune() == (-1, -1)
+    ctx.close()

@@ -55,6 +55,19 @@ def test_fit_mu_warm_start_and_zero_iterations():
     ctx.close()
 
 
+def _standard_errors(rec, J, mu):
+    """sqrt(diag(-H^-1)) per row at (J, mu), H the row Hessian of Eq. (18)."""
+    N, B = rec.n_neurons, rec.n_bins
+    X = O.dense_trace(rec.bins, rec.neurons, N, B, rec.dt, rec.tau)
+    A = np.hstack([np.ones((B, 1)), X])
+    se = np.zeros((N, N))
+    for i in range(N):
+        lam = np.exp(mu[i] + X @ J[i])
+        H = rec.dt * (A.T * lam) @ A
+        se[i] = np.sqrt(np.diag(np.linalg.inv(H))[1:])
+    return se
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_fit_reduced_precision_reaches_oracle_optimum(prec):
     rec = synth.config1(0)
@@ -68,11 +81,17 @@ def test_fit_reduced_precision_reaches_oracle_optimum(prec):
     ctx.close()
     Jn, mun, _ = O.newton_fit(rec.bins, rec.neurons, N, B, rec.dt, rec.tau)
     err = np.abs(J - Jn).max()
-    print(f"[fit config1 {prec}] {rep} max|J-Jn|={err:.3e}", flush=True)
-    # BF16 evaluates the likelihood at bf16(J): steps below the bf16 spacing of
-    # J leave it unchanged, so the ascent stops within that resolution of the
-    # optimum (far below the separation of the classes, 0.5 and -1.5 vs 0)
-    assert err < (1e-3 if prec == "fp32" else 0.1)
+    se = _standard_errors(rec, Jn, mun)
+    zmax = float(np.max(np.abs(J - Jn) / se))
+    print(f"[fit config1 {prec}] {rep} max|J-Jn|={err:.3e} max|J-Jn|/SE={zmax:.3f}", flush=True)
+    # BF16 evaluates the likelihood at bf16(J) with a stochastically rounded
+    # trace, so its maximum sits a little away from the exact one; the bound is
+    # a fraction of the MLE's own standard error (Hessian of Eq. (18)), the
+    # resolution the data allow (0.25 .. 2 at this size)
+    if prec == "fp32":
+        assert err < 1e-3
+    else:
+        assert zmax < 0.5
     if prec == "fp32":
         assert np.array_equal(O.classify(J), O.classify(Jn))
     else:
