@@ -41,10 +41,11 @@ def gemm_source_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def traffic_from_profile(kernel: str, launches_bins: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "kernel_U_traffic_balanced_n1000.json")
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_kernels_U_G_balanced_n1000_bf16.json")
     if not os.path.exists(path):
         return None
     try:
@@ -173,7 +174,7 @@ def main():
     flops_launch = 2.0 * N * N * B / launches  # 2 flops per bin*N^2 per contraction
     achieved = flops_launch / per_launch_s
     peak = PEAK[args.precision]
-    traffic = traffic_from_profile(dom, B)
+    traffic = traffic_from_profile(dom) if args.precision == "bf16" and q["trace_resident"] else None
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                 "kernel": dom, "launch_ms": per_launch_s * 1e3, "launches_per_step": launches,

@@ -221,15 +221,16 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
   nt_loop<BT, BI, WGM, WGN>((const __bf16*)g.Xtj + tt0 * g.Np, g.Np, (const __bf16*)g.Jc + i0 * g.Np,
                             g.Np, 0, g.Np, smem, acc);
 
-  // W = exp(V) (0 past the last bin); sums over the wave's bins per neuron in
+  // W = exp(V) (0 past the last bin), staged in LDS so that each neuron's 256
+  // bins leave as one 512-byte run; sums over the wave's bins per neuron in
   // FP32 over at most 16 MB values, FP64 beyond.  The loop ended on a barrier,
-  // so its LDS can hold the per-wave-row sums.
-  double* red = (double*)smem;  // [WGM][BI]
-  __bf16* __restrict__ W = (__bf16*)g.W;
+  // so its LDS is free.
+  constexpr int WP = BT * 2 + 16;                          // staged row pitch (bytes)
+  unsigned char* wl = smem;                                // [BI][WP]
+  double* red = (double*)(smem + (size_t)BI * WP);         // [WGM][BI]
 #pragma unroll
   for (int b = 0; b < T::NB; ++b) {
     const int il = wn * T::WN + b * 32 + l32;  // neuron within the tile
-    __bf16* wrow = W + (i0 + il) * g.L + tl0;
     float cs = 0.f;
 #pragma unroll
     for (int a = 0; a < T::MB; ++a) {
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
           cs += lam[e];
         }
         bf16x2 p0 = {(__bf16)lam[0], (__bf16)lam[1]}, p1 = {(__bf16)lam[2], (__bf16)lam[3]};
-        *(uint2*)(wrow + tq) = uint2{__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
+        *(uint2*)(wl + il * WP + tq * 2) = uint2{__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
       }
     }
     double v = (double)cs;
@@ -252,6 +253,13 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
     if (hi == 0) red[wm * BI + il] = v;
   }
   __syncthreads();
+  __bf16* __restrict__ W = (__bf16*)g.W;
+  constexpr int CPRW = BT * 2 / 16;  // 16-byte pieces per staged row
+#pragma unroll 4
+  for (int p = tid; p < BI * CPRW; p += T::NT) {
+    const int r = p / CPRW, c = p % CPRW;
+    *(i32x4*)(W + (i0 + r) * g.L + tl0 + c * 8) = *(const i32x4*)(wl + r * WP + c * 16);
+  }
   for (int il = tid; il < BI; il += T::NT) {
     double v = 0.0;
 #pragma unroll
@@ -305,8 +313,8 @@ hipError_t set_lds(K kern, size_t lds) {
 template <int BI, int WGM, int WGN>
 hipError_t run_u(const ResUArgs& a, hipStream_t st) {
   using T = Nt<GLMR_TT, BI, WGM, WGN>;
-  const size_t red = (size_t)WGM * BI * sizeof(double);
-  const size_t lds = T::LDS > red ? T::LDS : red;
+  const size_t epi = (size_t)BI * (GLMR_TT * 2 + 16) + (size_t)WGM * BI * sizeof(double);
+  const size_t lds = T::LDS > epi ? T::LDS : epi;
   auto kern = k_res_u<BI, WGM, WGN>;
   hipError_t e = set_lds(kern, lds);
   if (e != hipSuccess) return e;
