@@ -29,7 +29,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}  # dense MFMA, flop/s
+PEAK = {"fp8": 5.0e15, "bf16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}  # dense MFMA, flop/s
 HBM_PEAK = 8.0e12
 
 
@@ -117,12 +117,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp8", "fp32", "fp64"])
     ap.add_argument("--bins", type=int, default=3_600_000)
     ap.add_argument("--trace", default="auto", choices=["auto", "resident", "recompute"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 comparison line")
     ap.add_argument("--cpu-sample-bins", type=int, default=1_572_864)
     ap.add_argument("--fit-iters", type=int, default=5)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -160,7 +161,7 @@ def main():
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         ctx.set_params(rec.J, rec.mu)
-        tiles = ctx.autotune() if prec == "bf16" and not args.no_tune else (-1, -1)
+        tiles = ctx.autotune() if prec in ("bf16", "fp8") and not args.no_tune else (-1, -1)
         sec, r = time_steps(ctx, args.steps, args.warmup)
         kt = kernel_times(ctx)
         return ctx, setup, sec, r, kt, tiles
@@ -191,11 +192,16 @@ def main():
     ctx.close()
 
     extra = {}
+    if not args.no_fp8 and args.precision == "bf16":
+        c8, setup8, sec8, r8, kt8, tiles8 = run("fp8")
+        c8.close()
+        extra.update({"fp8_value": units / sec8, "fp8_ms_per_step": sec8 * 1e3,
+                      "fp8_tile_shapes": list(tiles8)})
     if not args.no_fp32 and args.precision != "fp32":
         c32, setup32, sec32, r32, kt32, _ = run("fp32")
         c32.close()
-        extra = {"fp32_value": units / sec32, "fp32_ms_per_step": sec32 * 1e3,
-                 "bf16_over_fp32": sec32 / sec}
+        extra.update({"fp32_value": units / sec32, "fp32_ms_per_step": sec32 * 1e3,
+                      "bf16_over_fp32": sec32 / sec})
 
     out = {
         "metric": "LL+grad throughput (bins*N^2/s) at N=1000; BF16 vs FP32 at stated grad error",

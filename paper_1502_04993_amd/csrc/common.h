@@ -149,10 +149,14 @@ struct ResXArgs {
   int planes;
   const Tables* tab;
   int64_t Np, NS, Bp;
-  void* Xtj;               // [Bp][Np] bf16
-  void* Xjt;               // [Np][Bp] bf16
+  void* Xtj;               // [Bp][Np] bf16 (FP8: e4m3 bytes)
+  void* Xjt;               // [Np][Bp] bf16 (FP8: e4m3 bytes)
+  int64_t L;               // FP8: bins per scaling chunk (the evaluation's time chunk)
+  unsigned* xmax;          // FP8: [ceil(Bp / L)] chunk maxima (float bits), zero on entry
+  float* xscale;           // FP8: [ceil(Bp / L)] power-of-two chunk scales
 };
 hipError_t launch_build_x(const ResXArgs& a, hipStream_t st);
+hipError_t launch_build_x8(const ResXArgs& a, hipStream_t st);
 
 struct ResUArgs {
   const void* Jc;          // [Np][Np] bf16
@@ -161,8 +165,10 @@ struct ResUArgs {
   int64_t t0;              // first bin of this chunk
   int64_t L;               // row pitch of W (bins)
   int n_itiles, n_ttiles;  // neuron tiles, 256-bin tiles of this chunk
-  void* W;                 // [Np][L] bf16: exp(V)
+  void* W;                 // [Np][L] bf16: exp(V) (FP8: e5m2 bytes, exp(V) / 64)
   double* rowpart;         // [Bp/256][Np]
+  const float* xscale;     // FP8: this chunk's trace scale (one value)
+  const float* jscale;     // FP8: [Np] row scales of J
 };
 struct ResGArgs {
   const void* W;           // [Np][L] bf16
@@ -172,14 +178,16 @@ struct ResGArgs {
   int64_t ks;              // bins per split (multiple of 64)
   int n_splits, n_itiles, n_jtiles;
   void* Gp;                // [n_splits][Np][Np] float
+  const float* xscale;     // FP8: this chunk's trace scale (one value)
 };
 struct ResShape {
   int bm;                  // neuron tile (kernel U: bm x 256 bins; kernel G: bm x bm)
   int wgm, wgn;            // wave grid
+  int fp8_ok;              // usable for FP8 operands
 };
 const ResShape* res_shapes(int* n);
-hipError_t launch_res_u(int shape, const ResUArgs& a, hipStream_t st);
-hipError_t launch_res_g(int shape, const ResGArgs& a, hipStream_t st);
+hipError_t launch_res_u(int shape, int fp8, const ResUArgs& a, hipStream_t st);
+hipError_t launch_res_g(int shape, int fp8, const ResGArgs& a, hipStream_t st);
 
 // Reductions and assembly (FP64) -------------------------------------------
 hipError_t launch_gp_reduce(int prec, const void* Gp, int n_splits, int64_t Np, double* G64,

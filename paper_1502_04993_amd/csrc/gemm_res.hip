@@ -18,6 +18,18 @@
 // Trace rounding is stochastic with the bits r(t, j) = t*0x9E3779B9 +
 // j*0x6C8E9CF5, so each stored value is an unbiased estimate of x_j[t] and the
 // two layouts hold the identical rounded value.
+//
+// FP8 (OCP formats, v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales):
+//   trace  e4m3, times a power-of-two scale per time chunk, 2^floor(log2(448 /
+//          max x)), rounded stochastically with the same bits r(t, j);
+//   J      e4m3, times a power-of-two scale per row (set when the parameters
+//          are), rounded to nearest; the likelihood is that of the rounded J;
+//   W      e5m2, W' = exp(V) / 64 rounded stochastically (bits from (t, i)),
+//          whose range covers exp(V) for V in about [-7, 15] without a scale.
+// Scales are powers of two, so applying and removing them is exact; the row
+// sums of exp(V) are taken in FP32/FP64 before W is rounded.
+#include <type_traits>
+
 #include "common.h"
 
 namespace {
@@ -100,7 +112,123 @@ __global__ __launch_bounds__(256) void k_build_x(ResXArgs g) {
   }
 }
 
+// FP8 trace: the same FP64 values, a power-of-two scale per time chunk of L
+// bins (largest with max x * scale <= 448), stochastic rounding to e4m3.
+// trace_16: x at bins 16g .. 16g+15 of column j in subtile s (FP64).
+__device__ inline void trace_16(const ResXArgs& g, int64_t s, int64_t j, int m0, double (&xv)[16]) {
+  const double a = g.tab->pw[1];
+  double x = g.C64[s * g.Np + j] * g.tab->pw[m0];
+  uint32_t cnt[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) cnt[e] = 0;
+  for (int p = 0; p < g.planes; ++p) {
+    const uint64_t mk = g.masks[((int64_t)p * g.NS + s) * g.Np + j];
+    uint64_t below = (m0 == 0) ? 0ull : (mk & ((1ull << m0) - 1));
+    while (below) {
+      const int b = __builtin_ctzll(below);
+      below &= below - 1;
+      x += g.tab->pw[m0 - b - 1];
+    }
+    const uint32_t win = (uint32_t)((mk >> m0) & 0xffffu);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) cnt[e] += (win >> e) & 1u;
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    xv[e] = x;
+    x = a * x + (double)cnt[e];
+  }
+}
+
+// per-chunk maximum of the trace (as float bits; x >= 0, so integer order is float order)
+__global__ __launch_bounds__(256) void k_xmax8(ResXArgs g) {
+  const int64_t njb = g.Np / 64;
+  const int64_t s = blockIdx.x / njb, jb = blockIdx.x % njb;
+  const int tid = threadIdx.x, jj = tid & 63, gq = tid >> 6;
+  double xv[16];
+  trace_16(g, s, jb * 64 + jj, 16 * gq, xv);
+  float m = 0.f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) m = fmaxf(m, (float)xv[e]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((tid & 63) == 0) atomicMax(&g.xmax[(s * 64) / g.L], __float_as_uint(m));
+}
+
+__global__ void k_xscale8(ResXArgs g, int64_t nchunks) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= nchunks) return;
+  const float amax = __uint_as_float(g.xmax[c]);
+  float sc = 1.f;
+  if (amax > 0.f) {
+    int e = 0;
+    (void)frexpf(448.f / amax, &e);  // 448 / amax = f 2^e, f in [0.5, 1)
+    sc = ldexpf(1.f, e - 1);
+  }
+  g.xscale[c] = sc;
+}
+
+__global__ __launch_bounds__(256) void k_build_x8(ResXArgs g) {
+  __shared__ __align__(16) unsigned char tile[64 * 80];
+  const int64_t njb = g.Np / 64;
+  const int64_t s = blockIdx.x / njb, jb = blockIdx.x % njb;
+  const int tid = threadIdx.x, jj = tid & 63, gq = tid >> 6;
+  const int64_t j = jb * 64 + jj;
+  const int m0 = 16 * gq;
+  double xv[16];
+  trace_16(g, s, j, m0, xv);
+  const float sc = g.xscale[(s * 64) / g.L];
+  const uint32_t rj = (uint32_t)j * SR_J;
+  int w[4] = {0, 0, 0, 0};
+  const uint32_t rt = (uint32_t)(s * 64 + m0) * SR_T + rj;
+  auto q8 = [&](int e) { return fminf((float)xv[e] * sc, 448.f); };
+#pragma unroll
+  for (int g4 = 0; g4 < 4; ++g4) {
+    const int e = 4 * g4;
+    int v = 0;
+    v = __builtin_amdgcn_cvt_sr_fp8_f32(q8(e), rt + (uint32_t)e * SR_T, v, 0);
+    v = __builtin_amdgcn_cvt_sr_fp8_f32(q8(e + 1), rt + (uint32_t)(e + 1) * SR_T, v, 1);
+    v = __builtin_amdgcn_cvt_sr_fp8_f32(q8(e + 2), rt + (uint32_t)(e + 2) * SR_T, v, 2);
+    v = __builtin_amdgcn_cvt_sr_fp8_f32(q8(e + 3), rt + (uint32_t)(e + 3) * SR_T, v, 3);
+    w[g4] = v;
+  }
+  // Xjt[j][64 s + m0 .. + 16]
+  *(i32x4*)((unsigned char*)g.Xjt + j * g.Bp + s * 64 + m0) = i32x4{w[0], w[1], w[2], w[3]};
+  // Xtj through LDS (rows of 64 columns)
+#pragma unroll
+  for (int e = 0; e < 16; ++e) tile[(m0 + e) * 80 + jj] = (unsigned char)(w[e >> 2] >> (8 * (e & 3)));
+  __syncthreads();
+  const int row = tid >> 2, c16 = tid & 3;
+  *(i32x4*)((unsigned char*)g.Xtj + (s * 64 + row) * g.Np + jb * 64 + c16 * 16) =
+      *(const i32x4*)(tile + row * 80 + c16 * 16);
+}
+
 // ------------------------------------------------------------------ NT core
+// MFMA operand formats.  Both step through k in 128-byte row slices (64 BF16
+// or 128 FP8 values); a lane's fragment is LB contiguous bytes of its row at
+// byte offset KC * kc + LB * (lane / 32) of the slice.
+struct OpBF16 {
+  static constexpr int KC = 32, LB = 16;  // bytes of k per MFMA and per lane
+  using frag = bf16x8;
+  __device__ static frag load(const unsigned char* p) { return *(const bf16x8*)p; }
+  __device__ static void mma(f32x16& c, const frag& a, const frag& b) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+// FA / FB: 0 = e4m3, 1 = e5m2 (the instruction's A and B format codes)
+template <int FA, int FB>
+struct OpF8 {
+  static constexpr int KC = 64, LB = 32;
+  using frag = i32x8;
+  __device__ static frag load(const unsigned char* p) {
+    const i32x4 lo = *(const i32x4*)p, hi = *(const i32x4*)(p + 16);
+    return frag{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  }
+  __device__ static void mma(f32x16& c, const frag& a, const frag& b) {
+    c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, FA, FB, 0, 127, 0, 127);
+  }
+};
+
 template <int BM, int BN, int WGM, int WGN>
 struct Nt {
   static constexpr int NT = WGM * WGN * 64;
@@ -112,16 +240,17 @@ struct Nt {
   static_assert(APT >= 1 && BPT >= 1 && BM * 8 % NT == 0 && BN * 8 % NT == 0, "tile/thread mismatch");
 };
 
-// acc[a][b] += A[m0 + wave rows][kb:ke] B[n0 + wave cols][kb:ke]^T.  A and B
-// point at the tile's first row; lda/ldb are row pitches in elements; the k
-// range is a multiple of BK.  Acc element r of lane l of block (a, b) is row
-// 32a + 8(r/4) + 4(l/32) + r%4, column 32b + l%32 of the wave tile.
-template <int BM, int BN, int WGM, int WGN>
-__device__ __forceinline__ void nt_loop(const __bf16* __restrict__ A, int64_t lda,
-                                        const __bf16* __restrict__ Bt, int64_t ldb, int64_t kb,
+// acc[a][b] += A[m0 + wave rows][kb:ke] B[n0 + wave cols][kb:ke]^T in format Op.
+// A and B point at the tile's first row; lda/ldb and the k range [kb, ke) are
+// in bytes, the range a multiple of 128.  Acc element r of lane l of block
+// (a, b) is row 32a + 8(r/4) + 4(l/32) + r%4, column 32b + l%32 of the wave tile.
+template <int BM, int BN, int WGM, int WGN, typename Op>
+__device__ __forceinline__ void nt_loop(const unsigned char* __restrict__ A, int64_t lda,
+                                        const unsigned char* __restrict__ Bt, int64_t ldb, int64_t kb,
                                         int64_t ke, unsigned char* smem,
                                         f32x16 (&acc)[Nt<BM, BN, WGM, WGN>::MB][Nt<BM, BN, WGM, WGN>::NB]) {
   using T = Nt<BM, BN, WGM, WGN>;
+  constexpr int SB = BK * 2;  // bytes per row and step
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
@@ -134,12 +263,12 @@ __device__ __forceinline__ void nt_loop(const __bf16* __restrict__ A, int64_t ld
 #pragma unroll
     for (int q = 0; q < T::APT; ++q) {
       const int piece = tid + q * T::NT, r = piece >> 3, c = piece & 7;
-      ar[q] = *(const i32x4*)(A + r * lda + k0 + c * 8);
+      ar[q] = *(const i32x4*)(A + r * lda + k0 + c * 16);
     }
 #pragma unroll
     for (int q = 0; q < T::BPT; ++q) {
       const int piece = tid + q * T::NT, r = piece >> 3, c = piece & 7;
-      br[q] = *(const i32x4*)(Bt + r * ldb + k0 + c * 8);
+      br[q] = *(const i32x4*)(Bt + r * ldb + k0 + c * 16);
     }
   };
   auto lstore = [&](int buf) {
@@ -157,7 +286,7 @@ __device__ __forceinline__ void nt_loop(const __bf16* __restrict__ A, int64_t ld
     }
   };
 
-  const int nk = (int)((ke - kb) / BK);
+  const int nk = (int)((ke - kb) / SB);
   if (nk <= 0) return;
   gload(kb);
   lstore(0);
@@ -165,21 +294,20 @@ __device__ __forceinline__ void nt_loop(const __bf16* __restrict__ A, int64_t ld
   for (int ks = 0; ks < nk; ++ks) {
     const int cur = ks & 1;
     const bool more = ks + 1 < nk;
-    if (more) gload(kb + (int64_t)(ks + 1) * BK);
-    const unsigned char* As = As0 + cur * T::ABUF + (wm * T::WM + l32) * ROWB + hi * 16;
-    const unsigned char* Bs = Bs0 + cur * T::BBUF + (wn * T::WN + l32) * ROWB + hi * 16;
+    if (more) gload(kb + (int64_t)(ks + 1) * SB);
+    const unsigned char* As = As0 + cur * T::ABUF + (wm * T::WM + l32) * ROWB + hi * Op::LB;
+    const unsigned char* Bs = Bs0 + cur * T::BBUF + (wn * T::WN + l32) * ROWB + hi * Op::LB;
 #pragma unroll
-    for (int kc = 0; kc < BK / 16; ++kc) {
-      bf16x8 af[T::MB], bv[T::NB];
+    for (int kc = 0; kc < SB / Op::KC; ++kc) {
+      typename Op::frag af[T::MB], bv[T::NB];
 #pragma unroll
-      for (int a = 0; a < T::MB; ++a) af[a] = *(const bf16x8*)(As + a * 32 * ROWB + kc * 32);
+      for (int a = 0; a < T::MB; ++a) af[a] = Op::load(As + a * 32 * ROWB + kc * Op::KC);
 #pragma unroll
-      for (int b = 0; b < T::NB; ++b) bv[b] = *(const bf16x8*)(Bs + b * 32 * ROWB + kc * 32);
+      for (int b = 0; b < T::NB; ++b) bv[b] = Op::load(Bs + b * 32 * ROWB + kc * Op::KC);
 #pragma unroll
       for (int a = 0; a < T::MB; ++a)
 #pragma unroll
-        for (int b = 0; b < T::NB; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < T::NB; ++b) Op::mma(acc[a][b], af[a], bv[b]);
     }
     if (more) lstore(cur ^ 1);
     __syncthreads();
@@ -200,13 +328,17 @@ __device__ __forceinline__ void zero_acc(f32x16 (&acc)[MB][NB]) {
 // tile 256 bins x BI neurons; grid n_itiles * n_ttiles (neuron tile fastest).
 // The bins are the MFMA row operand (A = Xtj), the neurons the column operand
 // (B = J), so a lane's accumulators hold 4 consecutive bins of one neuron per
-// group: W is stored 8 bytes at a time and the per-neuron sums over bins are
-// mostly in-lane (then one exchange between the two half-waves and one across
-// the wave rows through LDS).
-template <int BI, int WGM, int WGN>
+// group: the per-neuron sums over bins are mostly in-lane (then one exchange
+// between the two half-waves and one across the wave rows through LDS), and W
+// is staged in LDS so that each neuron's 256 bins leave as one run.
+constexpr uint32_t SR_WT = 0x85EBCA6Bu, SR_WI = 0xC2B2AE35u;  // rounding bits of the FP8 weights
+
+template <int BI, int WGM, int WGN, bool F8>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
   constexpr int BT = GLMR_TT;
+  constexpr int ES = F8 ? 1 : 2;  // bytes per element
   using T = Nt<BT, BI, WGM, WGN>;
+  using Op = typename std::conditional<F8, OpF8<0, 0>, OpBF16>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -218,19 +350,21 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
 
   f32x16 acc[T::MB][T::NB];
   zero_acc(acc);
-  nt_loop<BT, BI, WGM, WGN>((const __bf16*)g.Xtj + tt0 * g.Np, g.Np, (const __bf16*)g.Jc + i0 * g.Np,
-                            g.Np, 0, g.Np, smem, acc);
+  nt_loop<BT, BI, WGM, WGN, Op>((const unsigned char*)g.Xtj + tt0 * g.Np * ES, g.Np * ES,
+                                (const unsigned char*)g.Jc + i0 * g.Np * ES, g.Np * ES, 0, g.Np * ES,
+                                smem, acc);
 
-  // W = exp(V) (0 past the last bin), staged in LDS so that each neuron's 256
-  // bins leave as one 512-byte run; sums over the wave's bins per neuron in
+  // W = exp(V) (0 past the last bin); sums over the wave's bins per neuron in
   // FP32 over at most 16 MB values, FP64 beyond.  The loop ended on a barrier,
   // so its LDS is free.
-  constexpr int WP = BT * 2 + 16;                          // staged row pitch (bytes)
+  constexpr int WP = BT * ES + 16;                         // staged row pitch (bytes)
   unsigned char* wl = smem;                                // [BI][WP]
   double* red = (double*)(smem + (size_t)BI * WP);         // [WGM][BI]
+  const float xs_inv = F8 ? 1.f / g.xscale[0] : 1.f;
 #pragma unroll
   for (int b = 0; b < T::NB; ++b) {
     const int il = wn * T::WN + b * 32 + l32;  // neuron within the tile
+    const float vs = F8 ? xs_inv / g.jscale[i0 + il] : 1.f;  // exact: powers of two
     float cs = 0.f;
 #pragma unroll
     for (int a = 0; a < T::MB; ++a) {
@@ -240,12 +374,23 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
         float lam[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          lam[e] = __expf(acc[a][b][4 * q + e]);
+          lam[e] = __expf(acc[a][b][4 * q + e] * vs);
           if (tt0 + tq + e >= g.B) lam[e] = 0.f;
           cs += lam[e];
         }
-        bf16x2 p0 = {(__bf16)lam[0], (__bf16)lam[1]}, p1 = {(__bf16)lam[2], (__bf16)lam[3]};
-        *(uint2*)(wl + il * WP + tq * 2) = uint2{__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
+        if constexpr (F8) {
+          const uint32_t r0 = (uint32_t)(tt0 + tq) * SR_WT + (uint32_t)(i0 + il) * SR_WI;
+          int wv = 0;
+          wv = __builtin_amdgcn_cvt_sr_bf8_f32(lam[0] * (1.f / 64.f), r0, wv, 0);
+          wv = __builtin_amdgcn_cvt_sr_bf8_f32(lam[1] * (1.f / 64.f), r0 + SR_WT, wv, 1);
+          wv = __builtin_amdgcn_cvt_sr_bf8_f32(lam[2] * (1.f / 64.f), r0 + 2 * SR_WT, wv, 2);
+          wv = __builtin_amdgcn_cvt_sr_bf8_f32(lam[3] * (1.f / 64.f), r0 + 3 * SR_WT, wv, 3);
+          *(int*)(wl + il * WP + tq) = wv;
+        } else {
+          bf16x2 p0 = {(__bf16)lam[0], (__bf16)lam[1]}, p1 = {(__bf16)lam[2], (__bf16)lam[3]};
+          *(uint2*)(wl + il * WP + tq * 2) =
+              uint2{__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
+        }
       }
     }
     double v = (double)cs;
@@ -253,12 +398,12 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
     if (hi == 0) red[wm * BI + il] = v;
   }
   __syncthreads();
-  __bf16* __restrict__ W = (__bf16*)g.W;
-  constexpr int CPRW = BT * 2 / 16;  // 16-byte pieces per staged row
+  unsigned char* __restrict__ W = (unsigned char*)g.W;
+  constexpr int CPRW = BT * ES / 16;  // 16-byte pieces per staged row
 #pragma unroll 4
   for (int p = tid; p < BI * CPRW; p += T::NT) {
     const int r = p / CPRW, c = p % CPRW;
-    *(i32x4*)(W + (i0 + r) * g.L + tl0 + c * 8) = *(const i32x4*)(wl + r * WP + c * 16);
+    *(i32x4*)(W + ((i0 + r) * g.L + tl0) * ES + c * 16) = *(const i32x4*)(wl + r * WP + c * 16);
   }
   for (int il = tid; il < BI; il += T::NT) {
     double v = 0.0;
@@ -271,9 +416,11 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
 // ------------------------------------------------------------------ kernel G
 // tile BM x BN of (i, j) over one split of the chunk's bins; grid
 // n_splits * n_itiles * n_jtiles (column tile fastest, then row tile)
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, bool F8>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_res_g(ResGArgs g) {
+  constexpr int ES = F8 ? 1 : 2;
   using T = Nt<BM, BN, WGM, WGN>;
+  using Op = typename std::conditional<F8, OpF8<1, 0>, OpBF16>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -289,9 +436,12 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_g(ResGArgs g) {
 
   f32x16 acc[T::MB][T::NB];
   zero_acc(acc);
-  nt_loop<BM, BN, WGM, WGN>((const __bf16*)g.W + i0 * g.L, g.L, (const __bf16*)g.Xjt + j0 * g.Bp + g.t0,
-                            g.Bp, tb, te, smem, acc);
+  nt_loop<BM, BN, WGM, WGN, Op>((const unsigned char*)g.W + i0 * g.L * ES, g.L * ES,
+                                (const unsigned char*)g.Xjt + (j0 * g.Bp + g.t0) * ES, g.Bp * ES, tb * ES,
+                                te * ES, smem, acc);
 
+  // FP8: the weights were stored as exp(V) / 64 and the trace times its chunk scale
+  const float gs = F8 ? 64.f / g.xscale[0] : 1.f;
   float* __restrict__ Gp = (float*)g.Gp + split * g.Np * g.Np;
 #pragma unroll
   for (int a = 0; a < T::MB; ++a)
@@ -301,7 +451,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_g(ResGArgs g) {
       for (int r = 0; r < 16; ++r) {
         const int il = wm * T::WM + a * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
         const int jl = wn * T::WN + b * 32 + l32;
-        Gp[(i0 + il) * g.Np + j0 + jl] = acc[a][b][r];
+        Gp[(i0 + il) * g.Np + j0 + jl] = acc[a][b][r] * gs;
       }
 }
 
@@ -310,22 +460,22 @@ hipError_t set_lds(K kern, size_t lds) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int BI, int WGM, int WGN>
+template <int BI, int WGM, int WGN, bool F8>
 hipError_t run_u(const ResUArgs& a, hipStream_t st) {
   using T = Nt<GLMR_TT, BI, WGM, WGN>;
-  const size_t epi = (size_t)BI * (GLMR_TT * 2 + 16) + (size_t)WGM * BI * sizeof(double);
+  const size_t epi = (size_t)BI * (GLMR_TT * (F8 ? 1 : 2) + 16) + (size_t)WGM * BI * sizeof(double);
   const size_t lds = T::LDS > epi ? T::LDS : epi;
-  auto kern = k_res_u<BI, WGM, WGN>;
+  auto kern = k_res_u<BI, WGM, WGN, F8>;
   hipError_t e = set_lds(kern, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)a.n_itiles * a.n_ttiles)), dim3(T::NT), lds, st, a);
   return hipGetLastError();
 }
 
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, bool F8>
 hipError_t run_g(const ResGArgs& a, hipStream_t st) {
   using T = Nt<BM, BN, WGM, WGN>;
-  auto kern = k_res_g<BM, BN, WGM, WGN>;
+  auto kern = k_res_g<BM, BN, WGM, WGN, F8>;
   hipError_t e = set_lds(kern, T::LDS);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)a.n_splits * a.n_itiles * a.n_jtiles)),
@@ -341,34 +491,62 @@ hipError_t launch_build_x(const ResXArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// FP8 trace: a.xmax must hold zeros for the ceil(Bp / L) chunks on entry.
+hipError_t launch_build_x8(const ResXArgs& a, hipStream_t st) {
+  const int64_t blocks = a.NS * (a.Np / 64);
+  const int64_t nchunks = (a.Bp + a.L - 1) / a.L;
+  hipLaunchKernelGGL(k_xmax8, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_xscale8, dim3((unsigned)((nchunks + 255) / 256)), dim3(256), 0, st, a, nchunks);
+  hipLaunchKernelGGL(k_build_x8, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 // Tile shapes (neuron tile BM x 256 bins for U, BM x BM for G) and wave grids
-// offered to the autotuner; `shape` indexes res_shapes().
+// offered to the autotuner; `shape` indexes res_shapes().  The 8-wave
+// 256-neuron tiles need more than the 256 registers a wave may hold at two
+// waves per SIMD once the fragments are FP8 (32 bytes a lane), so FP8 skips them.
 const ResShape* res_shapes(int* n) {
   static const ResShape s[] = {
-      {256, 2, 2}, {256, 2, 4}, {256, 4, 2}, {128, 2, 2}, {128, 1, 4},
+      {256, 2, 2, 1}, {256, 2, 4, 0}, {256, 4, 2, 0}, {128, 2, 2, 1},
+      {128, 1, 4, 1}, {128, 4, 2, 1}, {128, 2, 4, 1},
   };
   *n = (int)(sizeof(s) / sizeof(s[0]));
   return s;
 }
 
-hipError_t launch_res_u(int shape, const ResUArgs& a, hipStream_t st) {
+template <bool F8>
+hipError_t res_u(int shape, const ResUArgs& a, hipStream_t st) {
   switch (shape) {
-    case 0: return run_u<256, 2, 2>(a, st);
-    case 1: return run_u<256, 2, 4>(a, st);
-    case 2: return run_u<256, 4, 2>(a, st);
-    case 3: return run_u<128, 2, 2>(a, st);
-    case 4: return run_u<128, 1, 4>(a, st);
+    case 0: return run_u<256, 2, 2, F8>(a, st);
+    case 1: return run_u<256, 2, 4, F8>(a, st);
+    case 2: return run_u<256, 4, 2, F8>(a, st);
+    case 3: return run_u<128, 2, 2, F8>(a, st);
+    case 4: return run_u<128, 1, 4, F8>(a, st);
+    case 5: return run_u<128, 4, 2, F8>(a, st);
+    case 6: return run_u<128, 2, 4, F8>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_res_g(int shape, const ResGArgs& a, hipStream_t st) {
+template <bool F8>
+hipError_t res_g(int shape, const ResGArgs& a, hipStream_t st) {
   switch (shape) {
-    case 0: return run_g<256, 256, 2, 2>(a, st);
-    case 1: return run_g<256, 256, 2, 4>(a, st);
-    case 2: return run_g<256, 256, 4, 2>(a, st);
-    case 3: return run_g<128, 128, 2, 2>(a, st);
-    case 4: return run_g<128, 128, 1, 4>(a, st);
+    case 0: return run_g<256, 256, 2, 2, F8>(a, st);
+    case 1: return run_g<256, 256, 2, 4, F8>(a, st);
+    case 2: return run_g<256, 256, 4, 2, F8>(a, st);
+    case 3: return run_g<128, 128, 2, 2, F8>(a, st);
+    case 4: return run_g<128, 128, 1, 4, F8>(a, st);
+    case 5: return run_g<128, 128, 4, 2, F8>(a, st);
+    case 6: return run_g<128, 128, 2, 4, F8>(a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Kernel U / kernel G on the resident trace, BF16 or FP8 (fp8 != 0).
+hipError_t launch_res_u(int shape, int fp8, const ResUArgs& a, hipStream_t st) {
+  return fp8 ? res_u<true>(shape, a, st) : res_u<false>(shape, a, st);
+}
+
+hipError_t launch_res_g(int shape, int fp8, const ResGArgs& a, hipStream_t st) {
+  return fp8 ? res_g<true>(shape, a, st) : res_g<false>(shape, a, st);
 }

@@ -144,6 +144,42 @@ __global__ void k_prepare_f32u(int N, int64_t Np, const double* J64, const doubl
   }
 }
 
+// FP8: row i of J times the power-of-two scale 2^floor(log2(448 / max_j |J_ij|)),
+// rounded to the nearest OCP e4m3 value; Jr holds the value actually used.
+// One 256-thread block per row.
+__global__ __launch_bounds__(256) void k_prepare_f8(int N, int64_t Np, const double* J64, const double* mu,
+                                                    unsigned char* Jc, double* Jr, double* rowscale,
+                                                    float* jscale) {
+  __shared__ float red[256];
+  const int64_t i = blockIdx.x;
+  float m = 0.f;
+  for (int64_t j = threadIdx.x; j < Np; j += 256)
+    if (i < N && j < N) m = fmaxf(m, fabsf((float)J64[i * Np + j]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const float amax = red[0];
+  float sc = 1.f;
+  if (amax > 0.f) {
+    int e = 0;
+    (void)frexpf(448.f / amax, &e);
+    sc = ldexpf(1.f, e - 1);
+  }
+  for (int64_t j = threadIdx.x; j < Np; j += 256) {
+    const float v = (i < N && j < N) ? (float)J64[i * Np + j] * sc : 0.f;
+    const int q = __builtin_amdgcn_cvt_pk_fp8_f32(v, v, 0, false) & 0xff;
+    Jc[i * Np + j] = (unsigned char)q;
+    Jr[i * Np + j] = (double)__builtin_amdgcn_cvt_f32_fp8(q, 0) / (double)sc;
+  }
+  if (threadIdx.x == 0) {
+    jscale[i] = sc;
+    rowscale[i] = (i < N) ? exp(mu[i]) : 0.0;
+  }
+}
+
 __global__ void k_copy_out(const double* src, int64_t ld, double* dst, int rows, int cols) {
   const int64_t n = (int64_t)rows * cols;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
@@ -388,7 +424,6 @@ hipError_t launch_sum_rows(const double* v, int n, double* out, hipStream_t st) 
 hipError_t launch_prepare_params(int prec, int N, int64_t Np, const double* J64, const double* mu,
                                  void* Jc, double* Jr, double* rowscale, float* jscale,
                                  hipStream_t st) {
-  (void)jscale;
   const int g = grid_for(Np * Np, 256);
   switch (prec) {
     case PREC_F64:
@@ -402,6 +437,11 @@ hipError_t launch_prepare_params(int prec, int N, int64_t Np, const double* J64,
     case PREC_BF16:
       hipLaunchKernelGGL(k_prepare<__bf16>, dim3(g), dim3(256), 0, st, N, Np, J64, mu, (__bf16*)Jc, Jr,
                          rowscale);
+      break;
+    case PREC_FP8:
+      if (!jscale) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_prepare_f8, dim3((unsigned)Np), dim3(256), 0, st, N, Np, J64, mu,
+                         (unsigned char*)Jc, Jr, rowscale, jscale);
       break;
     default: return hipErrorInvalidValue;
   }

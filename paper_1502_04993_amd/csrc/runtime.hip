@@ -91,6 +91,10 @@ struct glmr_ctx {
   unsigned char* Xtj = nullptr;
   unsigned char* Xjt = nullptr;
   int res_shape_u = 1, res_shape_g = 1;  // indices into res_shapes()
+  size_t x_bytes = 0;                    // bytes of each layout as allocated
+  unsigned* xmax = nullptr;              // FP8: per-chunk trace maxima
+  float* xscale = nullptr;               // FP8: per-chunk trace scales
+  float* jscale = nullptr;               // FP8: per-row scales of J
 
   // parameters (padded FP64 masters and the compute-precision copy)
   bool have_params = false;
@@ -237,6 +241,7 @@ size_t jc_bytes(int prec) { return prec == PREC_F32 ? 8 : in_bytes(prec); }
 // ---------------------------------------------------------------- kernel caches
 // Whether the BF16 trace is kept in HBM (see glmr_trace_mode).
 bool want_resident(glmr_ctx* c) {
+  if (c->prec == PREC_FP8) return true;  // FP8 contractions exist only on the resident trace
   if (c->prec != PREC_BF16 || c->cfg.trace == GLMR_TRACE_RECOMPUTE) return false;
   if (c->cfg.trace == GLMR_TRACE_RESIDENT) return true;
   size_t fr = 0, tot = 0;
@@ -256,9 +261,15 @@ glmr_status build_resident_trace(glmr_ctx* c) {
     dfree(c, c->Xjt);
     return GLMR_OK;
   }
-  const size_t n = (size_t)c->Bp * c->Np * 2;
+  const bool f8 = c->prec == PREC_FP8;
+  const size_t n = (size_t)c->Bp * c->Np * (f8 ? 1 : 2);
+  if (c->x_bytes != n) {
+    dfree(c, c->Xtj);
+    dfree(c, c->Xjt);
+  }
   if (!c->Xtj) TRY(dalloc(c, c->Xtj, n));
   if (!c->Xjt) TRY(dalloc(c, c->Xjt, n));
+  c->x_bytes = n;
   ResXArgs xa{};
   xa.C64 = c->C64;
   xa.masks = c->masks;
@@ -269,6 +280,18 @@ glmr_status build_resident_trace(glmr_ctx* c) {
   xa.Bp = c->Bp;
   xa.Xtj = c->Xtj;
   xa.Xjt = c->Xjt;
+  if (f8) {
+    const int64_t nchunks = (c->Bp + c->L - 1) / c->L;
+    TRY(dalloc(c, c->xmax, (size_t)nchunks));
+    TRY(dalloc(c, c->xscale, (size_t)nchunks));
+    HIPCHK(c, hipMemsetAsync(c->xmax, 0, (size_t)nchunks * sizeof(unsigned), c->st));
+    xa.L = c->L;
+    xa.xmax = c->xmax;
+    xa.xscale = c->xscale;
+    ProfScope ps(c, K_XBUILD);
+    HIPCHK(c, launch_build_x8(xa, c->st));
+    return GLMR_OK;
+  }
   ProfScope ps(c, K_XBUILD);
   HIPCHK(c, launch_build_x(xa, c->st));
   return GLMR_OK;
@@ -398,12 +421,21 @@ glmr_status ensure_workspace(glmr_ctx* c, bool want_grad, bool want_tau) {
 int64_t split_len_tiles(const glmr_ctx* c, int64_t Lc, int64_t tiles) {
   int64_t want = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
   want = std::min<int64_t>(want, c->max_splits);
-  int64_t ks = rup((Lc + want - 1) / want, 64);
-  return std::max<int64_t>(ks, 64);
+  // a split is a whole number of the contraction's 128-byte k steps
+  const int64_t q = c->prec == PREC_FP8 ? 128 : 64;
+  int64_t ks = rup((Lc + want - 1) / want, q);
+  return std::max<int64_t>(ks, q);
 }
 
 int64_t split_len(const glmr_ctx* c, int64_t Lc) {
   return split_len_tiles(c, Lc, (c->Np / c->bi2) * (c->Np / c->bj2));
+}
+
+// whether tile shape k fits this context's padding and precision
+bool shape_ok(const glmr_ctx* c, int k) {
+  int n = 0;
+  const ResShape* sh = res_shapes(&n);
+  return k >= 0 && k < n && c->Np % sh[k].bm == 0 && (c->prec != PREC_FP8 || sh[k].fp8_ok);
 }
 
 ResShape res_shape(int k) {
@@ -426,7 +458,12 @@ hipError_t launch_u_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
   ua.n_ttiles = (int)(Lc / GLMR_TT);
   ua.W = c->W;
   ua.rowpart = c->rowpart;
-  return launch_res_u(k, ua, c->st);
+  const bool f8 = c->prec == PREC_FP8;
+  if (f8) {
+    ua.xscale = c->xscale + t0 / c->L;
+    ua.jscale = c->jscale;
+  }
+  return launch_res_u(k, f8 ? 1 : 0, ua, c->st);
 }
 
 hipError_t launch_g_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc, int* n_splits) {
@@ -445,7 +482,9 @@ hipError_t launch_g_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc, int* n_spl
   ga.n_splits = (int)((Lc + ga.ks - 1) / ga.ks);
   ga.Gp = c->Gp;
   *n_splits = ga.n_splits;
-  return launch_res_g(k, ga, c->st);
+  const bool f8 = c->prec == PREC_FP8;
+  if (f8) ga.xscale = c->xscale + t0 / c->L;
+  return launch_res_g(k, f8 ? 1 : 0, ga, c->st);
 }
 
 glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
@@ -543,26 +582,26 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
 
 glmr_status prepare_params(glmr_ctx* c) {
   ProfScope ps(c, K_PREP);
+  if (c->prec == PREC_FP8 && !c->jscale) TRY(dalloc(c, c->jscale, (size_t)c->Np));
   HIPCHK(c, launch_prepare_params(c->prec, c->N, c->Np, c->J64, c->mu, c->Jc, c->Jr, c->rowscale,
-                                  nullptr, c->st));
+                                  c->prec == PREC_FP8 ? c->jscale : nullptr, c->st));
   return GLMR_OK;
 }
 
 // tiles, chunk length and split budget of the context's precision (Np fixed)
 void setup_precision(glmr_ctx* c) {
   // neuron tile of the BF16 kernels (FP64 and FP32 use 128-row tiles)
-  if (c->prec != PREC_BF16) c->tile = 256;
+  if (c->prec != PREC_BF16 && c->prec != PREC_FP8) c->tile = 256;
   else if (c->Np % 256 != 0 || c->cfg.tile_n == 128) c->tile = 128;
   else if (c->cfg.tile_n == 256) c->tile = 256;
   else c->tile = c->N > 384 ? 256 : 128;
   gemm_tiles(c->prec, c->tile, &c->bi1, &c->bt1, &c->bi2, &c->bj2);
   // resident-trace shapes: 256-neuron tiles when the padding allows
-  c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 2 : 3;
+  if (c->prec == PREC_FP8) c->res_shape_u = c->res_shape_g = 5;
+  else c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 2 : 3;
   if (const char* e = std::getenv("GLMR_RES_SHAPE")) {
-    int u = -1, g = -1, n = 0;
-    const ResShape* sh = res_shapes(&n);
-    if (std::sscanf(e, "%d,%d", &u, &g) == 2 && u >= 0 && u < n && g >= 0 && g < n &&
-        c->Np % sh[u].bm == 0 && c->Np % sh[g].bm == 0) {
+    int u = -1, g = -1;
+    if (std::sscanf(e, "%d,%d", &u, &g) == 2 && shape_ok(c, u) && shape_ok(c, g)) {
       c->res_shape_u = u;
       c->res_shape_g = g;
     }
@@ -846,9 +885,10 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
   if (!cfg) return GLMR_EINVAL;
   if (cfg->n_neurons < 1 || cfg->n_neurons > 65536 || cfg->n_bins < 1 || !(cfg->dt > 0) ||
       !std::isfinite(cfg->dt) || cfg->chunk_bins < 0 || cfg->precision < 0 || cfg->precision > 3 ||
-      !(cfg->tile_n == 0 || cfg->tile_n == 128 || cfg->tile_n == 256))
+      !(cfg->tile_n == 0 || cfg->tile_n == 128 || cfg->tile_n == 256) || cfg->trace < 0 || cfg->trace > 2)
     return GLMR_EINVAL;
-  if (cfg->precision == GLMR_FP8) return GLMR_EINVAL;  // not available in this build
+  if (cfg->precision == GLMR_FP8 && cfg->trace == GLMR_TRACE_RECOMPUTE)
+    return GLMR_EINVAL;  // FP8 contractions exist only on the resident trace
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -863,7 +903,7 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
   c->dt = cfg->dt;
   c->prec = cfg->precision;
   int tile = cfg->tile_n;
-  if (tile == 0) tile = (c->prec == GLMR_BF16 && c->N <= 384) ? 128 : 256;
+  if (tile == 0) tile = ((c->prec == GLMR_BF16 || c->prec == GLMR_FP8) && c->N <= 384) ? 128 : 256;
   c->Np = rup(c->N, tile);
   c->Bp = rup(c->B, GLMR_TT);
   c->NS = c->Bp / GLMR_SUB;
@@ -1037,7 +1077,9 @@ glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int3
 glmr_status glmr_set_precision(glmr_ctx* c, int32_t precision) {
   if (!c) return GLMR_EINVAL;
   c->err.clear();
-  if (precision < 0 || precision > 2) return fail(c, GLMR_EINVAL, "precision must be FP64, FP32 or BF16");
+  if (precision < 0 || precision > 3) return fail(c, GLMR_EINVAL, "precision must be FP64, FP32, BF16 or FP8");
+  if (precision == GLMR_FP8 && c->cfg.trace == GLMR_TRACE_RECOMPUTE)
+    return fail(c, GLMR_EINVAL, "FP8 needs the resident trace");
   if (precision == c->prec) return GLMR_OK;
   HIPCHK(c, hipSetDevice(c->cfg.device));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1090,6 +1132,8 @@ glmr_status glmr_eval(glmr_ctx* c, double* ll, double* ll_rows, double* grad_J, 
   HIPCHK(c, hipSetDevice(c->cfg.device));
   const bool want_grad = grad_J || grad_mu;
   const bool want_tau = grad_tau != nullptr;
+  if (want_tau && c->prec == PREC_FP8)
+    return fail(c, GLMR_EINVAL, "dL/dtau is evaluated in FP64, FP32 or BF16, not FP8");
   if (want_tau && !c->have_y) {
     c->keep_y = true;
     TRY(build_kernel_caches(c, true));
@@ -1217,8 +1261,7 @@ extern "C" glmr_status glmr_autotune(glmr_ctx* c, const char* cache_path, int32_
         if (std::sscanf(line, "glmrec-tune %127s %lld %lld %d %d %d", arch, &np, &l, &prec, &u, &g) == 6) {
           char k2[256];
           std::snprintf(k2, sizeof(k2), "%s %lld %lld %d", arch, np, l, prec);
-          if (key == k2 && u >= 0 && u < n && g >= 0 && g < n && c->Np % sh[u].bm == 0 &&
-              c->Np % sh[g].bm == 0) {
+          if (key == k2 && shape_ok(c, u) && shape_ok(c, g)) {
             best_u = u;  // the last matching line wins
             best_g = g;
           }
@@ -1232,7 +1275,7 @@ extern "C" glmr_status glmr_autotune(glmr_ctx* c, const char* cache_path, int32_
     const int64_t Lc = std::min<int64_t>(c->L, c->Bp);
     double tu = 1e300, tg = 1e300;
     for (int k = 0; k < n; ++k) {
-      if (c->Np % sh[k].bm != 0) continue;
+      if (!shape_ok(c, k)) continue;
       double ms = 0;
       TRY(time_launches(c, [&] { return launch_u_chunk(c, k, 0, Lc); }, 3, &ms));
       if (ms < tu) { tu = ms; best_u = k; }

@@ -39,9 +39,10 @@ def test_create_rejects_bad_config_without_device():
     lib = _lib.load()
     out = ctypes.c_void_p()
     for kw in (dict(n_neurons=0), dict(n_bins=0), dict(dt=0.0), dict(dt=float("nan")),
-               dict(precision=7), dict(tile_n=100), dict(chunk_bins=-1)):
+               dict(precision=7), dict(tile_n=100), dict(chunk_bins=-1), dict(trace=3),
+               dict(precision=3, trace=2)):  # FP8 exists only on the resident trace
         args = dict(n_neurons=10, n_bins=100, dt=0.001, chunk_bins=0, precision=1, device=0,
-                    stream=None, tile_n=0)
+                    stream=None, tile_n=0, trace=0)
         args.update(kw)
         cfg = _lib.glmr_config(**args)
         assert lib.glmr_create(ctypes.byref(cfg), ctypes.byref(out)) == _lib.GLMR_EINVAL

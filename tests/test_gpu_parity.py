@@ -14,6 +14,12 @@ likelihood of the parameters rounded to it):
   BF16: L 1e-3, gradient 1e-3 (at theta = 0 and near the truth).
 "bf16" runs the resident trace (built once per tau, kept in HBM); "bf16-rc"
 rebuilds the trace inside the contractions.
+  FP8 (no target is set for it): L 2e-3, gradient 3e-2, at J rounded to the
+        FP8 representation (per-row power-of-two scale, e4m3).  The trace is
+        e4m3 (3 mantissa bits) and the weights e5m2 (2 bits), both rounded
+        stochastically, so each element carries ~5-10 % unbiased noise that
+        averages over the bins; what is left in L is second order (the
+        convexity of exp), measured at ~3e-4 for N = 1000.
 Gradient error = ||g - g_oracle||_2 / ||g_oracle||_2 over (dL/dmu, dL/dJ).
 """
 import sys
@@ -26,8 +32,9 @@ from oracle import glm_oracle as O
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4), "bf16": (1e-3, 1e-3), "bf16-rc": (1e-3, 1e-3)}
-ALL = ["fp64", "fp32", "bf16", "bf16-rc"]
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4), "bf16": (1e-3, 1e-3), "bf16-rc": (1e-3, 1e-3),
+       "fp8": (2e-3, 3e-2)}
+ALL = ["fp64", "fp32", "bf16", "bf16-rc", "fp8"]
 
 
 def ll_tol(prec, rec):
@@ -42,8 +49,36 @@ def _G():
     return G
 
 
+def _e4m3(y):
+    """Round float32 values to the nearest OCP e4m3 value (ties to even),
+    |y| <= 448: 3 mantissa bits, exponents down to 2^-6, subnormal step 2^-9."""
+    y = np.asarray(y, np.float64)
+    a = np.abs(y)
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -6)))
+    step = 2.0 ** (e - 3)
+    return np.sign(y) * np.round(a / step) * step
+
+
+def round_fp8_rows(J):
+    """J as the FP8 path represents it: per row, a power-of-two scale
+    2^floor(log2(448 / max|J_ij|)), the scaled float32 value rounded to e4m3."""
+    J = np.asarray(J, np.float64)
+    out = np.zeros_like(J)
+    for i in range(J.shape[0]):
+        m = np.float32(np.max(np.abs(J[i]))) if J.shape[1] else np.float32(0)
+        sc = 1.0
+        if m > 0:
+            _, e = np.frexp(np.float32(448.0) / m)
+            sc = 2.0 ** (int(e) - 1)
+        y = (J[i].astype(np.float32) * np.float32(sc)).astype(np.float64)
+        out[i] = _e4m3(y) / sc
+    return out
+
+
 def _round(J, prec):
     prec = prec.split("-")[0]
+    if prec == "fp8":
+        return round_fp8_rows(J)
     if prec == "fp32":
         return J.astype(np.float32).astype(np.float64)
     if prec == "bf16":
@@ -72,8 +107,9 @@ def run_gpu(rec, J, mu, prec, tau=None, want_tau=False, **kw):
     out = ctx.eval(grad=True, want_tau=want_tau)
     out["query"] = ctx.query()
     ctx.close()
-    # BF16 keeps the trace resident unless asked not to (these inputs are small)
-    assert out["query"]["trace_resident"] == (prec == "bf16" and kw.get("trace", "auto") != "recompute")
+    # BF16 keeps the trace resident unless asked not to (these inputs are small); FP8 always does
+    assert out["query"]["trace_resident"] == (prec == "fp8" or
+                                              (prec == "bf16" and kw.get("trace", "auto") != "recompute"))
     return out
 
 
@@ -235,13 +271,28 @@ def test_tau_gradient(prec, tol):
     assert r <= tol
 
 
-@pytest.mark.parametrize("prec", ["bf16", "bf16-rc"])
+@pytest.mark.parametrize("prec", ["bf16", "bf16-rc", "fp8"])
 def test_determinism_bitwise(prec):
     rec = small_rec()
     J, mu = theta_for(rec, prec)
     a = run_gpu(rec, J, mu, prec)
     b = run_gpu(rec, J, mu, prec)
     assert a["ll"] == b["ll"] and np.array_equal(a["gJ"], b["gJ"])
+
+
+def test_fp8_rejects_tau_gradient_and_rebuilt_trace():
+    rec = small_rec()
+    G = _G()
+    with pytest.raises(G.GlmrError):
+        G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision="fp8", trace="recompute")
+    ctx = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision="fp8")
+    ctx.set_spikes(rec.bins, rec.neurons)
+    ctx.set_kernel(rec.tau)
+    ctx.set_params(_round(rec.J, "fp8"), rec.mu)
+    with pytest.raises(G.GlmrError) as e:
+        ctx.eval(grad=True, want_tau=True)
+    assert e.value.status == -1
+    ctx.close()
 
 
 def test_config1_fp64():
@@ -265,7 +316,7 @@ def big_rec():
     return _BIG["big"]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16-rc"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16-rc", "fp8"])
 @pytest.mark.parametrize("where", ["zero", "truth"])
 def test_n1000_parity(prec, where):
     rec = big_rec()
