@@ -157,8 +157,8 @@ typedef struct {
 } glmr_fit_opts;
 
 typedef struct {
-  int32_t iters;          /* ascent iterations taken */
-  int32_t evals;          /* likelihood evaluations */
+  int32_t iters;          /* ascent steps taken (one trial evaluation each) */
+  int32_t evals;          /* likelihood evaluations (steps + the initial one) */
   double ll;              /* final L */
   double max_eta;         /* max over rows of the last fractional change */
   int32_t rows_converged; /* rows that met ftol */
@@ -168,11 +168,18 @@ typedef struct {
 /* Fill opts with the defaults. */
 void glmr_fit_defaults(glmr_fit_opts* opts);
 
-/* Maximise L over theta by per-row L-BFGS with per-row Armijo backtracking.
- * L is separable over rows (Sec. 2.2), so every row takes its own step size
- * and stops on its own; all rows share each evaluation.  Requires q_i >= 1
- * for every neuron (else GLMR_ENOSPIKES).  Returns GLMR_NOT_CONVERGED (a
- * warning) if max_iter is reached.  report may be NULL. */
+/* Maximise L over theta by per-row L-BFGS with a per-row Armijo line search.
+ * L is separable over rows (Sec. 2.2), so every row takes its own step size,
+ * searches and stops on its own: each ascent step evaluates one trial point
+ * per row (all rows share the evaluation); a row whose trial fails the Armijo
+ * test halves its step for the next one (at most max_backtracks times, then it
+ * stops as stalled), a row whose trial passes updates its history and takes a
+ * new direction.  Each row's sequence of iterates is the same as with a
+ * synchronous line search.  The step is captured once in a HIP graph and
+ * replayed; the host reads one counter per step.  max_iter bounds the number
+ * of steps.  Stopping: the fractional change of L_i (Sec. 2.6.3) below ftol.
+ * Requires q_i >= 1 for every neuron (else GLMR_ENOSPIKES).  Returns
+ * GLMR_NOT_CONVERGED (a warning) if max_iter is reached.  report may be NULL. */
 glmr_status glmr_fit(glmr_ctx* ctx, const glmr_fit_opts* opts, glmr_fit_report* report);
 
 /* ---------------------------------------------------------------- batching

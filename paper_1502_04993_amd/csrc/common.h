@@ -249,12 +249,14 @@ struct AscentArgs {
   int32_t* state;         // [Np]: 0 active, 1 converged, 2 stalled
   int32_t* accepted;      // [Np]
   double* eta;            // [Np]
+  int32_t* bt;            // [Np] halvings of the current line search
 };
-hipError_t launch_lbfgs_direction(const AscentArgs& a, int first, hipStream_t st);
+hipError_t launch_lbfgs_direction(const AscentArgs& a, int async, hipStream_t st);
+hipError_t launch_armijo_async(const AscentArgs& a, double c1, int max_bt, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);
+hipError_t launch_count_active(const AscentArgs& a, int32_t* counters, hipStream_t st);
 hipError_t launch_make_trial(const AscentArgs& a, hipStream_t st);
-hipError_t launch_armijo(const AscentArgs& a, double c1, int last_try, int32_t* n_pending,
-                         hipStream_t st);
-hipError_t launch_accept_update(const AscentArgs& a, double ftol, int32_t* counters,
+hipError_t launch_accept_update(const AscentArgs& a, double ftol, int32_t* counters, int async,
                                 hipStream_t st);
 hipError_t launch_pack_theta(int N, int64_t Np, int P, const double* theta, double* J64,
                              double* mu, hipStream_t st);

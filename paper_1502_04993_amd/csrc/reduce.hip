@@ -222,7 +222,7 @@ __global__ void k_pack_grad(int N, int64_t Np, int P, const double* gJ, const do
 }
 
 // two-loop recursion for row i (f = -L, so d is a descent direction of f)
-__global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int first) {
+__global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int async) {
   __shared__ double sh[RT];
   __shared__ double alpha[64];
   const int64_t i = blockIdx.x;
@@ -231,6 +231,7 @@ __global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int first) {
   const int64_t rs = (int64_t)a.N * P;  // history slot stride
   double* d = a.d + i * P;
   const double* g = a.g + i * P;
+  if (async && a.state[i] == 0 && a.accepted[i] != 3) return;  // mid-search: keep d and step
   if (a.state[i] != 0) {
     for (int c = tid; c < P; c += RT) d[c] = 0.0;
     if (tid == 0) a.gd[i] = 0.0;
@@ -301,6 +302,7 @@ __global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int first) {
     a.gd[i] = gd;
     a.step[i] = 1.0;
     a.accepted[i] = 0;
+    a.bt[i] = 0;
   }
 }
 
@@ -316,30 +318,15 @@ __global__ void k_make_trial(AscentArgs a) {
   }
 }
 
-// Armijo test per row on the trial just evaluated (f_try from it)
-__global__ void k_armijo(AscentArgs a, double c1, int last_try, int32_t* n_pending) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.N) return;
-  if (a.state[i] != 0 || a.accepted[i]) return;
-  const double ft = a.f_try[i];
-  if (isfinite(ft) && ft <= a.f[i] + c1 * a.step[i] * a.gd[i]) {
-    a.accepted[i] = 1;
-  } else if (last_try) {
-    a.accepted[i] = 2;  // give up this iteration: keep theta
-  } else {
-    a.step[i] *= 0.5;
-    atomicAdd(n_pending, 1);
-  }
-}
-
 // accept the trial, update the history, test the stopping rule.
 // counters[0] += rows still active afterwards
-__global__ __launch_bounds__(RT) void k_accept(AscentArgs a, double ftol, int32_t* counters) {
+__global__ __launch_bounds__(RT) void k_accept(AscentArgs a, double ftol, int32_t* counters, int async) {
   __shared__ double sh[RT];
   const int64_t i = blockIdx.x;
   const int tid = threadIdx.x;
   const int P = a.P;
   if (a.state[i] != 0) return;
+  if (async && (a.accepted[i] == 0 || a.accepted[i] == 3)) return;  // still searching / no trial yet
   const int64_t rs = (int64_t)a.N * P;
   double* th = a.theta + i * P;
   const double* tt = a.theta_try + i * P;
@@ -376,8 +363,42 @@ __global__ __launch_bounds__(RT) void k_accept(AscentArgs a, double ftol, int32_
     a.eta[i] = eta;
     a.f[i] = fn;
     if (eta <= ftol) a.state[i] = 1;
-    else atomicAdd(&counters[0], 1);
+    else if (counters) atomicAdd(&counters[0], 1);
+    if (async) a.accepted[i] = 3;  // next: a new direction
   }
+}
+
+// Asynchronous per-row line search (one trial evaluation per step for every
+// row; rows are independent, so each row's sequence of iterates is the same as
+// with a synchronous search).  accepted: 0 searching, 1 trial accepted,
+// 2 search failed, 3 direction needed.  bt: halvings of the current search.
+__global__ void k_armijo_async(AscentArgs a, double c1, int max_bt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  if (a.state[i] != 0 || a.accepted[i] != 0) return;
+  const double ft = a.f_try[i];
+  if (isfinite(ft) && ft <= a.f[i] + c1 * a.step[i] * a.gd[i]) {
+    a.accepted[i] = 1;
+  } else if (a.bt[i] >= max_bt) {
+    a.accepted[i] = 2;
+  } else {
+    a.step[i] *= 0.5;
+    a.bt[i] += 1;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+// counters[0] = rows still active (state 0), by a block sum (no atomics)
+__global__ __launch_bounds__(RT) void k_count_active(const AscentArgs a, int32_t* counters) {
+  __shared__ double sh[RT];
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < a.N; i += RT) v += (a.state[i] == 0) ? 1.0 : 0.0;
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) counters[0] = (int32_t)v;
 }
 
 int grid_for(int64_t n, int threads) {
@@ -476,8 +497,23 @@ hipError_t launch_pack_grad(int N, int64_t Np, int P, const double* gJ, const do
   return hipGetLastError();
 }
 
-hipError_t launch_lbfgs_direction(const AscentArgs& a, int first, hipStream_t st) {
-  hipLaunchKernelGGL(k_lbfgs_dir, dim3((unsigned)a.N), dim3(RT), 0, st, a, first);
+hipError_t launch_lbfgs_direction(const AscentArgs& a, int async, hipStream_t st) {
+  hipLaunchKernelGGL(k_lbfgs_dir, dim3((unsigned)a.N), dim3(RT), 0, st, a, async);
+  return hipGetLastError();
+}
+
+hipError_t launch_armijo_async(const AscentArgs& a, double c1, int max_bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_armijo_async, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, st, a, c1, max_bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_active(const AscentArgs& a, int32_t* counters, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(RT), 0, st, a, counters);
   return hipGetLastError();
 }
 
@@ -486,14 +522,8 @@ hipError_t launch_make_trial(const AscentArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_armijo(const AscentArgs& a, double c1, int last_try, int32_t* n_pending,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_armijo, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, st, a, c1, last_try,
-                     n_pending);
-  return hipGetLastError();
-}
-
-hipError_t launch_accept_update(const AscentArgs& a, double ftol, int32_t* counters, hipStream_t st) {
-  hipLaunchKernelGGL(k_accept, dim3((unsigned)a.N), dim3(RT), 0, st, a, ftol, counters);
+hipError_t launch_accept_update(const AscentArgs& a, double ftol, int32_t* counters, int async,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_accept, dim3((unsigned)a.N), dim3(RT), 0, st, a, ftol, counters, async);
   return hipGetLastError();
 }

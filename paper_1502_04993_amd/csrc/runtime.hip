@@ -125,6 +125,8 @@ struct glmr_ctx {
   AscentArgs asc{};
   bool have_asc = false;
   int32_t* counters = nullptr;
+  int32_t* host_cnt = nullptr;  // pinned copy of counters
+  bool capturing = false;       // work is being captured into a graph (no profiling events)
 
   // profiling
   bool prof = false;
@@ -204,13 +206,13 @@ struct ProfScope {
   int kind;
   hipEvent_t a = nullptr;
   ProfScope(glmr_ctx* c_, int k) : c(c_), kind(k) {
-    if (c->prof) {
+    if (c->prof && !c->capturing) {
       a = ev_get(c);
       hipEventRecord(a, c->st);
     }
   }
   ~ProfScope() {
-    if (c->prof) {
+    if (c->prof && a) {
       hipEvent_t b = ev_get(c);
       hipEventRecord(b, c->st);
       c->pending.push_back({kind, a, b});
@@ -660,7 +662,9 @@ glmr_status alloc_ascent(glmr_ctx* c, int m) {
   TRY(dalloc(c, a.state, (size_t)N));
   TRY(dalloc(c, a.accepted, (size_t)N));
   TRY(dalloc(c, a.eta, (size_t)N));
+  TRY(dalloc(c, a.bt, (size_t)N));
   TRY(dalloc(c, c->counters, 4));
+  if (!c->host_cnt) HIPCHK(c, hipHostMalloc((void**)&c->host_cnt, 4 * sizeof(int32_t), hipHostMallocDefault));
   c->have_asc = true;
   return GLMR_OK;
 }
@@ -675,6 +679,64 @@ glmr_status eval_theta(glmr_ctx* c, const double* theta_src, double* g, double* 
   HIPCHK(c, launch_pack_grad(c->N, c->Np, a.P, c->gJ, c->gmu, c->ll_rows, g, f, c->st));
   return GLMR_OK;
 }
+
+// Fresh ascent state: empty histories, every row active and asking for a direction.
+glmr_status ascent_reset(glmr_ctx* c) {
+  AscentArgs& a = c->asc;
+  HIPCHK(c, launch_fill_i32(a.hist_len, c->N, 0, c->st));
+  HIPCHK(c, launch_fill_i32(a.hist_head, c->N, 0, c->st));
+  HIPCHK(c, launch_fill_i32(a.state, c->N, 0, c->st));
+  HIPCHK(c, launch_fill_i32(a.bt, c->N, 0, c->st));
+  HIPCHK(c, launch_fill_i32(a.accepted, c->N, 3, c->st));
+  HIPCHK(c, hipMemsetAsync(a.eta, 0, c->N * sizeof(double), c->st));
+  return GLMR_OK;
+}
+
+// One asynchronous ascent step for every row: trial point, one evaluation,
+// per-row Armijo test (accept, halve the step, or give up), history update
+// and stopping test for accepted rows, new directions for them, and the count
+// of active rows in counters[0].  Only kernel launches: it can be captured.
+glmr_status ascent_step(glmr_ctx* c, double ftol, int max_bt) {
+  AscentArgs& a = c->asc;
+  {
+    ProfScope ps(c, K_ASC);
+    HIPCHK(c, launch_make_trial(a, c->st));
+  }
+  TRY(eval_theta(c, a.theta_try, a.g_try, a.f_try));
+  ProfScope ps(c, K_ASC);
+  HIPCHK(c, launch_armijo_async(a, 1e-4, max_bt, c->st));
+  HIPCHK(c, launch_accept_update(a, ftol, nullptr, 1, c->st));
+  HIPCHK(c, launch_lbfgs_direction(a, 1, c->st));
+  HIPCHK(c, launch_count_active(a, c->counters, c->st));
+  return GLMR_OK;
+}
+
+bool use_graphs() {
+  const char* e = std::getenv("GLMR_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+// A captured sequence of launches, replayed with hipGraphLaunch.
+struct GraphRun {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  template <typename F>
+  glmr_status capture(glmr_ctx* c, hipStream_t st, F body) {
+    HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    const glmr_status s1 = body();
+    c->capturing = false;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (s1 != GLMR_OK) return s1;
+    if (e != hipSuccess) return fail(c, GLMR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    HIPCHK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    return GLMR_OK;
+  }
+  ~GraphRun() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+  }
+};
 
 double default_ftol(int prec) {
   switch (prec) {
@@ -717,42 +779,24 @@ glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep
   TRY(alloc_ascent(c, o.lbfgs_m));
   AscentArgs& a = c->asc;
   HIPCHK(c, launch_unpack_theta(N, Np, a.P, c->J64, c->mu, a.theta, c->st));
-  HIPCHK(c, hipMemsetAsync(a.hist_len, 0, N * sizeof(int32_t), c->st));
-  HIPCHK(c, hipMemsetAsync(a.hist_head, 0, N * sizeof(int32_t), c->st));
-  HIPCHK(c, hipMemsetAsync(a.state, 0, N * sizeof(int32_t), c->st));
-  HIPCHK(c, hipMemsetAsync(a.eta, 0, N * sizeof(double), c->st));
+  TRY(ascent_reset(c));
   const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c->prec);
   int evals = 0, iters = 0;
   TRY(eval_theta(c, a.theta, a.g, a.f));
   ++evals;
+  HIPCHK(c, launch_lbfgs_direction(a, 1, c->st));
+  // one ascent step, captured once into a graph and replayed
+  auto step = [&]() -> glmr_status { return ascent_step(c, ftol, o.max_backtracks); };
+  GraphRun gr;
+  if (use_graphs()) TRY(gr.capture(c, c->st, step));
   int active = N;
-  int32_t hc[4];
-  for (iters = 0; iters < o.max_iter && active > 0;) {
-    {
-      ProfScope ps(c, K_ASC);
-      HIPCHK(c, launch_lbfgs_direction(a, iters == 0, c->st));
-    }
-    for (int bt = 0; bt <= o.max_backtracks; ++bt) {
-      {
-        ProfScope ps(c, K_ASC);
-        HIPCHK(c, launch_make_trial(a, c->st));
-      }
-      TRY(eval_theta(c, a.theta_try, a.g_try, a.f_try));
-      ++evals;
-      ProfScope ps(c, K_ASC);
-      HIPCHK(c, hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->st));
-      HIPCHK(c, launch_armijo(a, 1e-4, bt == o.max_backtracks, c->counters, c->st));
-      HIPCHK(c, hipMemcpyAsync(hc, c->counters, sizeof hc, hipMemcpyDeviceToHost, c->st));
-      HIPCHK(c, hipStreamSynchronize(c->st));
-      if (hc[0] == 0) break;
-    }
-    ProfScope ps(c, K_ASC);
-    HIPCHK(c, hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->st));
-    HIPCHK(c, launch_accept_update(a, ftol, c->counters, c->st));
-    HIPCHK(c, hipMemcpyAsync(hc, c->counters, sizeof hc, hipMemcpyDeviceToHost, c->st));
+  for (iters = 0; iters < o.max_iter && active > 0; ++iters) {
+    if (gr.exec) HIPCHK(c, hipGraphLaunch(gr.exec, c->st));
+    else TRY(step());
+    ++evals;
+    HIPCHK(c, hipMemcpyAsync(c->host_cnt, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
-    active = hc[0];
-    ++iters;
+    active = c->host_cnt[0];
   }
   // leave the context at the accepted parameters
   HIPCHK(c, launch_pack_theta(N, Np, a.P, a.theta, c->J64, c->mu, c->st));
@@ -928,6 +972,7 @@ void glmr_destroy(glmr_ctx* c) {
   hipStreamSynchronize(c->st);
   for (void* p : c->allocs) hipFree(p);
   if (c->host_scal) hipHostFree(c->host_scal);
+  if (c->host_cnt) hipHostFree(c->host_cnt);
   for (auto& r : c->pending) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);

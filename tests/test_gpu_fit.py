@@ -119,3 +119,35 @@ def test_bf16_fit_with_fp32_polish_matches_oracle_classification():
     print(f"[fit config1 bf16+fp32 polish] {rep} max|J-Jn|={err:.3e}", flush=True)
     assert err < 1e-3
     assert np.array_equal(O.classify(J), O.classify(Jn))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_graph_replays_match_eager_steps(prec):
+    """The captured ascent step replayed k times gives bitwise the parameters
+    that k eagerly launched steps give, for several k (each fit re-captures;
+    the host reads the active-row counter between replays)."""
+    import os
+    rec = synth.config1(0)
+    N, B = rec.n_neurons, rec.n_bins
+    G = _G()
+    old = os.environ.get("GLMR_NO_GRAPH")
+    try:
+        for k in (1, 2, 3, 5, 8, 25):
+            out = []
+            for flag in ("1", "0"):
+                os.environ["GLMR_NO_GRAPH"] = flag
+                ctx = G.Context(N, B, rec.dt, precision=prec)
+                ctx.set_spikes(rec.bins, rec.neurons)
+                ctx.set_kernel(rec.tau)
+                rep = ctx.fit(max_iter=k, from_zero=True)
+                J, mu, _ = ctx.get_params()
+                ctx.close()
+                out.append((J, mu, rep["iters"], rep["ll"]))
+            assert out[0][2] == out[1][2] == k
+            assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+            assert out[0][3] == out[1][3]
+    finally:
+        if old is None:
+            os.environ.pop("GLMR_NO_GRAPH", None)
+        else:
+            os.environ["GLMR_NO_GRAPH"] = old
