@@ -186,6 +186,22 @@ struct ResShape {
   int fp8_ok;              // usable for FP8 operands
 };
 const ResShape* res_shapes(int* n);
+// Work queue of a grouped (many-recording) launch: args[r] describes recording
+// r's chunk; its tiles are k in [prefix[r], prefix[r + 1]) of [0, total).
+struct ResUGroup {
+  const ResUArgs* args;    // device [n]
+  const int64_t* prefix;   // device [n + 1]
+  int n;
+  int64_t total;
+};
+struct ResGGroup {
+  const ResGArgs* args;
+  const int64_t* prefix;
+  int n;
+  int64_t total;
+};
+hipError_t launch_res_u_group(int shape, int fp8, const ResUGroup& q, hipStream_t st);
+hipError_t launch_res_g_group(int shape, int fp8, const ResGGroup& q, hipStream_t st);
 hipError_t launch_res_u(int shape, int fp8, const ResUArgs& a, hipStream_t st);
 hipError_t launch_res_g(int shape, int fp8, const ResGArgs& a, hipStream_t st);
 
@@ -255,6 +271,7 @@ hipError_t launch_lbfgs_direction(const AscentArgs& a, int async, hipStream_t st
 hipError_t launch_armijo_async(const AscentArgs& a, double c1, int max_bt, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);
 hipError_t launch_count_active(const AscentArgs& a, int32_t* counters, hipStream_t st);
+hipError_t launch_sum_counters(int32_t* const* p, int n, int32_t* out, hipStream_t st);
 hipError_t launch_make_trial(const AscentArgs& a, hipStream_t st);
 hipError_t launch_accept_update(const AscentArgs& a, double ftol, int32_t* counters, int async,
                                 hipStream_t st);

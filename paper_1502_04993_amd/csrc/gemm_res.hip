@@ -334,18 +334,16 @@ __device__ __forceinline__ void zero_acc(f32x16 (&acc)[MB][NB]) {
 constexpr uint32_t SR_WT = 0x85EBCA6Bu, SR_WI = 0xC2B2AE35u;  // rounding bits of the FP8 weights
 
 template <int BI, int WGM, int WGN, bool F8>
-__global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
+__device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int64_t ttile,
+                                           unsigned char* smem) {
   constexpr int BT = GLMR_TT;
   constexpr int ES = F8 ? 1 : 2;  // bytes per element
   using T = Nt<BT, BI, WGM, WGN>;
   using Op = typename std::conditional<F8, OpF8<0, 0>, OpBF16>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
   const int l32 = lane & 31, hi = lane >> 5;
-  const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
-  const int64_t itile = logical % g.n_itiles, ttile = logical / g.n_itiles;
   const int64_t i0 = itile * BI, tl0 = ttile * BT, tt0 = g.t0 + tl0;
 
   f32x16 acc[T::MB][T::NB];
@@ -413,20 +411,55 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
   }
 }
 
+template <int BI, int WGM, int WGN, bool F8>
+__global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
+  res_u_tile<BI, WGM, WGN, F8>(g, logical % g.n_itiles, logical / g.n_itiles, smem);
+}
+
+// index r with prefix[r] <= k < prefix[r + 1] (prefix ascending, prefix[0] = 0)
+__device__ inline int find_rec(const int64_t* __restrict__ prefix, int n, int64_t k) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent grouped kernel U: the tiles of many recordings in one queue;
+// workgroup b takes tiles b', b' + grid, ... (b' its XCD-contiguous rank), so
+// neighbouring tiles of one recording share an L2.  Every workgroup leaves
+// once the queue is exhausted.
+template <int BI, int WGM, int WGN, bool F8>
+__global__ __launch_bounds__(WGM * WGN * 64) void k_res_u_group(ResUGroup q) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t rank = xcd_logical(blockIdx.x, gridDim.x);
+  for (int64_t base = 0; base < q.total; base += gridDim.x) {
+    const int64_t k = base + rank;
+    if (k >= q.total) break;
+    const int r = find_rec(q.prefix, q.n, k);
+    const ResUArgs g = q.args[r];
+    const int64_t local = k - q.prefix[r];
+    res_u_tile<BI, WGM, WGN, F8>(g, local % g.n_itiles, local / g.n_itiles, smem);
+    __syncthreads();  // the next tile reuses the LDS
+  }
+}
+
 // ------------------------------------------------------------------ kernel G
 // tile BM x BN of (i, j) over one split of the chunk's bins; grid
 // n_splits * n_itiles * n_jtiles (column tile fastest, then row tile)
 template <int BM, int BN, int WGM, int WGN, bool F8>
-__global__ __launch_bounds__(WGM * WGN * 64) void k_res_g(ResGArgs g) {
+__device__ __forceinline__ void res_g_tile(const ResGArgs& g, int64_t logical, unsigned char* smem) {
   constexpr int ES = F8 ? 1 : 2;
   using T = Nt<BM, BN, WGM, WGN>;
   using Op = typename std::conditional<F8, OpF8<1, 0>, OpBF16>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
   const int l32 = lane & 31, hi = lane >> 5;
-  const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
   const int64_t jtile = logical % g.n_jtiles;
   const int64_t itile = (logical / g.n_jtiles) % g.n_itiles;
   const int64_t split = logical / ((int64_t)g.n_jtiles * g.n_itiles);
@@ -455,6 +488,27 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_g(ResGArgs g) {
       }
 }
 
+template <int BM, int BN, int WGM, int WGN, bool F8>
+__global__ __launch_bounds__(WGM * WGN * 64) void k_res_g(ResGArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  res_g_tile<BM, BN, WGM, WGN, F8>(g, xcd_logical(blockIdx.x, gridDim.x), smem);
+}
+
+// Persistent grouped kernel G (same queue discipline as kernel U's).
+template <int BM, int BN, int WGM, int WGN, bool F8>
+__global__ __launch_bounds__(WGM * WGN * 64) void k_res_g_group(ResGGroup q) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t rank = xcd_logical(blockIdx.x, gridDim.x);
+  for (int64_t base = 0; base < q.total; base += gridDim.x) {
+    const int64_t k = base + rank;
+    if (k >= q.total) break;
+    const int r = find_rec(q.prefix, q.n, k);
+    const ResGArgs g = q.args[r];
+    res_g_tile<BM, BN, WGM, WGN, F8>(g, k - q.prefix[r], smem);
+    __syncthreads();
+  }
+}
+
 template <typename K>
 hipError_t set_lds(K kern, size_t lds) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -469,6 +523,43 @@ hipError_t run_u(const ResUArgs& a, hipStream_t st) {
   hipError_t e = set_lds(kern, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)a.n_itiles * a.n_ttiles)), dim3(T::NT), lds, st, a);
+  return hipGetLastError();
+}
+
+// persistent grid: as many workgroups as fit on the device at once (at least 1)
+template <typename K>
+unsigned persistent_grid(K kern, int threads, size_t lds, int64_t total) {
+  int dev = 0, cus = 256, occ = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t p{};
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, threads, lds) != hipSuccess ||
+      occ < 1)
+    occ = 1;
+  const int64_t g = (int64_t)cus * occ;
+  return (unsigned)(total < g ? (total > 0 ? total : 1) : g);
+}
+
+template <int BI, int WGM, int WGN, bool F8>
+hipError_t run_u_group(const ResUGroup& q, hipStream_t st) {
+  using T = Nt<GLMR_TT, BI, WGM, WGN>;
+  const size_t epi = (size_t)BI * (GLMR_TT * (F8 ? 1 : 2) + 16) + (size_t)WGM * BI * sizeof(double);
+  const size_t lds = T::LDS > epi ? T::LDS : epi;
+  auto kern = k_res_u_group<BI, WGM, WGN, F8>;
+  hipError_t e = set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, T::NT, lds, q.total)), dim3(T::NT), lds, st, q);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int WGM, int WGN, bool F8>
+hipError_t run_g_group(const ResGGroup& q, hipStream_t st) {
+  using T = Nt<BM, BN, WGM, WGN>;
+  auto kern = k_res_g_group<BM, BN, WGM, WGN, F8>;
+  hipError_t e = set_lds(kern, T::LDS);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, T::NT, T::LDS, q.total)), dim3(T::NT), T::LDS, st, q);
   return hipGetLastError();
 }
 
@@ -540,6 +631,43 @@ hipError_t res_g(int shape, const ResGArgs& a, hipStream_t st) {
     case 6: return run_g<128, 128, 2, 4, F8>(a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <bool F8>
+hipError_t res_u_group(int shape, const ResUGroup& q, hipStream_t st) {
+  switch (shape) {
+    case 0: return run_u_group<256, 2, 2, F8>(q, st);
+    case 1: return run_u_group<256, 2, 4, F8>(q, st);
+    case 2: return run_u_group<256, 4, 2, F8>(q, st);
+    case 3: return run_u_group<128, 2, 2, F8>(q, st);
+    case 4: return run_u_group<128, 1, 4, F8>(q, st);
+    case 5: return run_u_group<128, 4, 2, F8>(q, st);
+    case 6: return run_u_group<128, 2, 4, F8>(q, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool F8>
+hipError_t res_g_group(int shape, const ResGGroup& q, hipStream_t st) {
+  switch (shape) {
+    case 0: return run_g_group<256, 256, 2, 2, F8>(q, st);
+    case 1: return run_g_group<256, 256, 2, 4, F8>(q, st);
+    case 2: return run_g_group<256, 256, 4, 2, F8>(q, st);
+    case 3: return run_g_group<128, 128, 2, 2, F8>(q, st);
+    case 4: return run_g_group<128, 128, 1, 4, F8>(q, st);
+    case 5: return run_g_group<128, 128, 4, 2, F8>(q, st);
+    case 6: return run_g_group<128, 128, 2, 4, F8>(q, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Grouped kernels U / G over many recordings (one persistent launch each).
+hipError_t launch_res_u_group(int shape, int fp8, const ResUGroup& q, hipStream_t st) {
+  return fp8 ? res_u_group<true>(shape, q, st) : res_u_group<false>(shape, q, st);
+}
+
+hipError_t launch_res_g_group(int shape, int fp8, const ResGGroup& q, hipStream_t st) {
+  return fp8 ? res_g_group<true>(shape, q, st) : res_g_group<false>(shape, q, st);
 }
 
 // Kernel U / kernel G on the resident trace, BF16 or FP8 (fp8 != 0).

@@ -401,6 +401,15 @@ __global__ __launch_bounds__(RT) void k_count_active(const AscentArgs a, int32_t
   if (threadIdx.x == 0) counters[0] = (int32_t)v;
 }
 
+// out[0] = sum over r of p[r][0] (active rows over many contexts), one block
+__global__ __launch_bounds__(RT) void k_sum_counters(int32_t* const* p, int n, int32_t* out) {
+  __shared__ double sh[RT];
+  double v = 0.0;
+  for (int r = threadIdx.x; r < n; r += RT) v += (double)p[r][0];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) out[0] = (int32_t)v;
+}
+
 int grid_for(int64_t n, int threads) {
   int64_t g = (n + threads - 1) / threads;
   if (g > 65536) g = 65536;
@@ -509,6 +518,11 @@ hipError_t launch_armijo_async(const AscentArgs& a, double c1, int max_bt, hipSt
 
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_counters(int32_t* const* p, int n, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_counters, dim3(1), dim3(RT), 0, st, p, n, out);
   return hipGetLastError();
 }
 

@@ -446,8 +446,9 @@ ResShape res_shape(int k) {
   return s[(k >= 0 && k < n) ? k : 0];
 }
 
-// Resident-trace kernels U and G for the chunk [t0, t0 + Lc) with tile shape k.
-hipError_t launch_u_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
+// Arguments of the resident-trace kernels U and G for the chunk [t0, t0 + Lc)
+// with tile shape k.
+ResUArgs make_u_args(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
   const ResShape su = res_shape(k);
   ResUArgs ua{};
   ua.Jc = c->Jc;
@@ -460,15 +461,14 @@ hipError_t launch_u_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
   ua.n_ttiles = (int)(Lc / GLMR_TT);
   ua.W = c->W;
   ua.rowpart = c->rowpart;
-  const bool f8 = c->prec == PREC_FP8;
-  if (f8) {
+  if (c->prec == PREC_FP8) {
     ua.xscale = c->xscale + t0 / c->L;
     ua.jscale = c->jscale;
   }
-  return launch_res_u(k, f8 ? 1 : 0, ua, c->st);
+  return ua;
 }
 
-hipError_t launch_g_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc, int* n_splits) {
+ResGArgs make_g_args(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
   const ResShape sg = res_shape(k);
   ResGArgs ga{};
   ga.W = c->W;
@@ -483,11 +483,21 @@ hipError_t launch_g_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc, int* n_spl
   ga.ks = split_len_tiles(c, Lc, (int64_t)ga.n_itiles * ga.n_jtiles);
   ga.n_splits = (int)((Lc + ga.ks - 1) / ga.ks);
   ga.Gp = c->Gp;
-  *n_splits = ga.n_splits;
-  const bool f8 = c->prec == PREC_FP8;
-  if (f8) ga.xscale = c->xscale + t0 / c->L;
-  return launch_res_g(k, f8 ? 1 : 0, ga, c->st);
+  if (c->prec == PREC_FP8) ga.xscale = c->xscale + t0 / c->L;
+  return ga;
 }
+
+hipError_t launch_u_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
+  return launch_res_u(k, c->prec == PREC_FP8 ? 1 : 0, make_u_args(c, k, t0, Lc), c->st);
+}
+
+hipError_t launch_g_chunk(glmr_ctx* c, int k, int64_t t0, int64_t Lc, int* n_splits) {
+  const ResGArgs ga = make_g_args(c, k, t0, Lc);
+  *n_splits = ga.n_splits;
+  return launch_res_g(k, c->prec == PREC_FP8 ? 1 : 0, ga, c->st);
+}
+
+glmr_status eval_finish(glmr_ctx* c, bool want_grad, bool want_tau);
 
 glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
   TRY(ensure_workspace(c, want_grad, want_tau));
@@ -554,6 +564,12 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       HIPCHK(c, launch_gp_reduce(c->prec, c->Gp, g2.n_splits, Np, c->G64, ci == 0, c->st));
     }
   }
+  return eval_finish(c, want_grad, want_tau);
+}
+
+// Row sums of the weights over all bins, then L_i, dL/dmu, dL/dJ (dL/dtau) in FP64.
+glmr_status eval_finish(glmr_ctx* c, bool want_grad, bool want_tau) {
+  const int64_t Np = c->Np;
   ProfScope ps(c, K_ASM);
   const int64_t ntiles_t = c->Bp / c->bt1;
   HIPCHK(c, launch_rowpart_reduce(c->rowpart, ntiles_t, Np, c->rowsum, c->rp_tmp, c->st));
@@ -747,16 +763,18 @@ double default_ftol(int prec) {
   }
 }
 
-glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep) {
-  glmr_fit_opts o;
-  glmr_fit_defaults(&o);
-  if (o_in) o = *o_in;
-  if (o.max_iter < 0 || o.lbfgs_m < 1 || o.lbfgs_m > 64 || o.max_backtracks < 0 || o.ftol < 0)
+glmr_status check_fit_opts(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_opts* o) {
+  glmr_fit_defaults(o);
+  if (o_in) *o = *o_in;
+  if (o->max_iter < 0 || o->lbfgs_m < 1 || o->lbfgs_m > 64 || o->max_backtracks < 0 || o->ftol < 0)
     return fail(c, GLMR_EINVAL, "bad fit options");
   if (!c->have_spikes || !c->have_kernel) return fail(c, GLMR_ESTATE, "set spikes and kernel first");
   if (!c->all_spiking) return fail(c, GLMR_ENOSPIKES, "some neuron has no spike: its MLE does not exist");
-  HIPCHK(c, hipSetDevice(c->cfg.device));
-  auto t_start = std::chrono::steady_clock::now();
+  return GLMR_OK;
+}
+
+// Starting point and a fresh ascent state (every row active, asking for a direction).
+glmr_status fit_begin(glmr_ctx* c, const glmr_fit_opts& o) {
   const int N = c->N;
   const int64_t Np = c->Np;
   if (!c->have_params || o.from_zero) {
@@ -777,9 +795,44 @@ glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep
     HIPCHK(c, hipStreamSynchronize(c->st));
   }
   TRY(alloc_ascent(c, o.lbfgs_m));
-  AscentArgs& a = c->asc;
-  HIPCHK(c, launch_unpack_theta(N, Np, a.P, c->J64, c->mu, a.theta, c->st));
+  HIPCHK(c, launch_unpack_theta(N, Np, c->asc.P, c->J64, c->mu, c->asc.theta, c->st));
   TRY(ascent_reset(c));
+  return GLMR_OK;
+}
+
+// Leave the context at the accepted parameters and fill the report.
+glmr_status fit_end(glmr_ctx* c, int iters, int evals, double seconds, glmr_fit_report* rep) {
+  const int N = c->N;
+  AscentArgs& a = c->asc;
+  HIPCHK(c, launch_pack_theta(N, c->Np, a.P, a.theta, c->J64, c->mu, c->st));
+  TRY(prepare_params(c));
+  std::vector<double> f(N), eta(N);
+  std::vector<int32_t> state(N);
+  HIPCHK(c, hipMemcpyAsync(f.data(), a.f, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(eta.data(), a.eta, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(state.data(), a.state, N * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  const int32_t conv = (int32_t)std::count_if(state.begin(), state.end(), [](int32_t s) { return s != 0; });
+  if (rep) {
+    rep->iters = iters;
+    rep->evals = evals;
+    double ll = 0;
+    for (int i = 0; i < N; ++i) ll -= f[i];
+    rep->ll = ll;
+    rep->max_eta = *std::max_element(eta.begin(), eta.end());
+    rep->rows_converged = conv;
+    rep->seconds = seconds;
+  }
+  return conv < N ? GLMR_NOT_CONVERGED : GLMR_OK;
+}
+
+glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep) {
+  glmr_fit_opts o;
+  TRY(check_fit_opts(c, o_in, &o));
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  auto t_start = std::chrono::steady_clock::now();
+  TRY(fit_begin(c, o));
+  AscentArgs& a = c->asc;
   const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c->prec);
   int evals = 0, iters = 0;
   TRY(eval_theta(c, a.theta, a.g, a.f));
@@ -789,7 +842,7 @@ glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep
   auto step = [&]() -> glmr_status { return ascent_step(c, ftol, o.max_backtracks); };
   GraphRun gr;
   if (use_graphs()) TRY(gr.capture(c, c->st, step));
-  int active = N;
+  int active = c->N;
   for (iters = 0; iters < o.max_iter && active > 0; ++iters) {
     if (gr.exec) HIPCHK(c, hipGraphLaunch(gr.exec, c->st));
     else TRY(step());
@@ -798,33 +851,178 @@ glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep
     HIPCHK(c, hipStreamSynchronize(c->st));
     active = c->host_cnt[0];
   }
-  // leave the context at the accepted parameters
-  HIPCHK(c, launch_pack_theta(N, Np, a.P, a.theta, c->J64, c->mu, c->st));
-  TRY(prepare_params(c));
-  std::vector<double> f(N), eta(N);
-  std::vector<int32_t> state(N);
-  HIPCHK(c, hipMemcpyAsync(f.data(), a.f, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipMemcpyAsync(eta.data(), a.eta, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipMemcpyAsync(state.data(), a.state, N * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipStreamSynchronize(c->st));
-  if (rep) {
-    rep->iters = iters;
-    rep->evals = evals;
-    double ll = 0;
-    for (int i = 0; i < N; ++i) ll -= f[i];
-    rep->ll = ll;
-    rep->max_eta = *std::max_element(eta.begin(), eta.end());
-    rep->rows_converged = (int32_t)std::count_if(state.begin(), state.end(), [](int32_t s) { return s != 0; });
-    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-  }
-  return active > 0 ? GLMR_NOT_CONVERGED : GLMR_OK;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return fit_end(c, iters, evals, secs, rep);
 }
 
 }  // namespace
 
+// ---------------------------------------------------------------- batching
 struct glmr_batch {
   std::vector<glmr_ctx*> ctxs;
+  int dev = 0;
+  hipStream_t st = nullptr;
+  bool grouped = false;  // one persistent launch per contraction over every recording
+  int shape_u = -1, shape_g = -1;
+  struct Chunk {         // the recordings that have time chunk ci, as work queues
+    std::vector<int> recs, nsplits;
+    ResUArgs* du = nullptr;
+    ResGArgs* dg = nullptr;
+    int64_t *pu = nullptr, *pg = nullptr;
+    int64_t tu = 0, tg = 0;
+  };
+  std::vector<Chunk> chunks;
+  int32_t** dcnt = nullptr;  // [n] each context's counters
+  int32_t* dsum = nullptr;   // active rows over all recordings
+  int32_t* hsum = nullptr;   // pinned
+  std::vector<void*> allocs;
 };
+
+namespace {
+
+template <typename T>
+hipError_t balloc(glmr_batch* b, T*& p, size_t n) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T));
+  if (e == hipSuccess) {
+    b->allocs.push_back(q);
+    p = (T*)q;
+  }
+  return e;
+}
+
+void free_queues(glmr_batch* b) {
+  for (void* p : b->allocs) hipFree(p);
+  b->allocs.clear();
+  b->chunks.clear();
+  b->dcnt = nullptr;
+  b->dsum = nullptr;
+}
+
+// Every context works on the batch's stream while the batch runs it.
+struct OnBatchStream {
+  glmr_batch* b;
+  std::vector<hipStream_t> old;
+  explicit OnBatchStream(glmr_batch* b_) : b(b_) {
+    for (glmr_ctx* c : b->ctxs) {
+      hipStreamSynchronize(c->st);  // order after the context's own earlier work
+      old.push_back(c->st);
+      c->st = b->st;
+    }
+  }
+  ~OnBatchStream() {
+    hipStreamSynchronize(b->st);
+    for (size_t r = 0; r < b->ctxs.size(); ++r) b->ctxs[r]->st = old[r];
+  }
+};
+
+// first tile shape valid for every recording, preferring the given one
+int common_shape(glmr_batch* b, int pref) {
+  static const int order[] = {2, 5, 3, 6, 0, 4, 1};
+  auto ok_all = [&](int k) {
+    for (glmr_ctx* c : b->ctxs)
+      if (!shape_ok(c, k)) return false;
+    return true;
+  };
+  if (ok_all(pref)) return pref;
+  for (int k : order)
+    if (ok_all(k)) return k;
+  return -1;
+}
+
+// Work queues for the grouped launches (after every context's workspace exists).
+glmr_status build_queues(glmr_batch* b) {
+  glmr_ctx* c0 = b->ctxs[0];
+  free_queues(b);
+  const int n = (int)b->ctxs.size();
+  std::vector<int32_t*> hc(n);
+  for (int r = 0; r < n; ++r) {
+    TRY(ensure_workspace(b->ctxs[r], true, false));
+    hc[r] = b->ctxs[r]->counters;
+  }
+  HIPCHK(c0, balloc(b, b->dcnt, (size_t)n));
+  HIPCHK(c0, balloc(b, b->dsum, 1));
+  HIPCHK(c0, hipMemcpy(b->dcnt, hc.data(), n * sizeof(int32_t*), hipMemcpyHostToDevice));
+  if (!b->grouped) return GLMR_OK;
+  int64_t nch = 0;
+  for (glmr_ctx* c : b->ctxs) nch = std::max<int64_t>(nch, (c->Bp + c->L - 1) / c->L);
+  b->chunks.resize(nch);
+  for (int64_t ci = 0; ci < nch; ++ci) {
+    glmr_batch::Chunk& ch = b->chunks[ci];
+    std::vector<ResUArgs> ua;
+    std::vector<ResGArgs> ga;
+    std::vector<int64_t> pu{0}, pg{0};
+    for (int r = 0; r < n; ++r) {
+      glmr_ctx* c = b->ctxs[r];
+      const int64_t t0 = ci * c->L;
+      if (t0 >= c->Bp) continue;
+      const int64_t Lc = std::min<int64_t>(c->L, c->Bp - t0);
+      ua.push_back(make_u_args(c, b->shape_u, t0, Lc));
+      ga.push_back(make_g_args(c, b->shape_g, t0, Lc));
+      pu.push_back(pu.back() + (int64_t)ua.back().n_itiles * ua.back().n_ttiles);
+      pg.push_back(pg.back() + (int64_t)ga.back().n_splits * ga.back().n_itiles * ga.back().n_jtiles);
+      ch.recs.push_back(r);
+      ch.nsplits.push_back(ga.back().n_splits);
+    }
+    const size_t m = ch.recs.size();
+    HIPCHK(c0, balloc(b, ch.du, m));
+    HIPCHK(c0, balloc(b, ch.dg, m));
+    HIPCHK(c0, balloc(b, ch.pu, m + 1));
+    HIPCHK(c0, balloc(b, ch.pg, m + 1));
+    HIPCHK(c0, hipMemcpy(ch.du, ua.data(), m * sizeof(ResUArgs), hipMemcpyHostToDevice));
+    HIPCHK(c0, hipMemcpy(ch.dg, ga.data(), m * sizeof(ResGArgs), hipMemcpyHostToDevice));
+    HIPCHK(c0, hipMemcpy(ch.pu, pu.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(c0, hipMemcpy(ch.pg, pg.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    ch.tu = pu.back();
+    ch.tg = pg.back();
+  }
+  return GLMR_OK;
+}
+
+// L and the gradient of every recording at its current parameters.
+glmr_status batch_eval_core(glmr_batch* b) {
+  if (!b->grouped) {
+    for (glmr_ctx* c : b->ctxs) TRY(eval_core(c, true, false));
+    return GLMR_OK;
+  }
+  glmr_ctx* c0 = b->ctxs[0];
+  const int fp8 = c0->prec == PREC_FP8 ? 1 : 0;
+  for (size_t ci = 0; ci < b->chunks.size(); ++ci) {
+    const glmr_batch::Chunk& ch = b->chunks[ci];
+    const int m = (int)ch.recs.size();
+    {
+      ProfScope ps(c0, K_BU);
+      HIPCHK(c0, launch_res_u_group(b->shape_u, fp8, ResUGroup{ch.du, ch.pu, m, ch.tu}, b->st));
+    }
+    {
+      ProfScope ps(c0, K_BG);
+      HIPCHK(c0, launch_res_g_group(b->shape_g, fp8, ResGGroup{ch.dg, ch.pg, m, ch.tg}, b->st));
+    }
+    for (int q = 0; q < m; ++q) {
+      glmr_ctx* c = b->ctxs[ch.recs[q]];
+      HIPCHK(c, launch_gp_reduce(c->prec, c->Gp, ch.nsplits[q], c->Np, c->G64, ci == 0, b->st));
+    }
+  }
+  for (glmr_ctx* c : b->ctxs) TRY(eval_finish(c, true, false));
+  return GLMR_OK;
+}
+
+glmr_status batch_eval_theta(glmr_batch* b, bool trial) {
+  for (glmr_ctx* c : b->ctxs) {
+    const AscentArgs& a = c->asc;
+    HIPCHK(c, launch_pack_theta(c->N, c->Np, a.P, trial ? a.theta_try : a.theta, c->J64, c->mu, c->st));
+    TRY(prepare_params(c));
+  }
+  TRY(batch_eval_core(b));
+  for (glmr_ctx* c : b->ctxs) {
+    const AscentArgs& a = c->asc;
+    HIPCHK(c, launch_pack_grad(c->N, c->Np, a.P, c->gJ, c->gmu, c->ll_rows, trial ? a.g_try : a.g,
+                               trial ? a.f_try : a.f, c->st));
+  }
+  return GLMR_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -841,27 +1039,70 @@ glmr_status glmr_batch_create(glmr_ctx* const* ctxs, int32_t n, glmr_batch** out
   for (int r = 0; r < n; ++r) {
     if (!ctxs[r]) return GLMR_EINVAL;
     if (ctxs[r]->cfg.device != ctxs[0]->cfg.device || ctxs[r]->prec != ctxs[0]->prec) return GLMR_EINVAL;
+    for (int q = 0; q < r; ++q)
+      if (ctxs[q] == ctxs[r]) return GLMR_EINVAL;  // each recording once
   }
+  if (hipSetDevice(ctxs[0]->cfg.device) != hipSuccess) return GLMR_EDEVICE;
   glmr_batch* b = new glmr_batch();
   b->ctxs.assign(ctxs, ctxs + n);
+  b->dev = ctxs[0]->cfg.device;
+  if (hipStreamCreate(&b->st) != hipSuccess || hipHostMalloc((void**)&b->hsum, sizeof(int32_t)) != hipSuccess) {
+    if (b->st) hipStreamDestroy(b->st);
+    delete b;
+    return GLMR_EDEVICE;
+  }
   *out = b;
   return GLMR_OK;
 }
 
-void glmr_batch_destroy(glmr_batch* b) { delete b; }
+void glmr_batch_destroy(glmr_batch* b) {
+  if (!b) return;
+  hipSetDevice(b->dev);
+  hipStreamSynchronize(b->st);
+  free_queues(b);
+  if (b->hsum) hipHostFree(b->hsum);
+  hipStreamDestroy(b->st);
+  delete b;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Grouped mode (every recording's trace resident, one precision) and its tile
+// shapes, then the work queues; the contexts must have spikes, kernel and params.
+glmr_status batch_prepare(glmr_batch* b) {
+  bool grouped = true;
+  for (glmr_ctx* c : b->ctxs) {
+    TRY(check_ready(c));
+    grouped = grouped && c->resident;
+  }
+  b->grouped = grouped;
+  if (grouped) {
+    b->shape_u = common_shape(b, b->ctxs[0]->res_shape_u);
+    b->shape_g = common_shape(b, b->ctxs[0]->res_shape_g);
+    b->grouped = b->shape_u >= 0 && b->shape_g >= 0;
+  }
+  return build_queues(b);
+}
+
+}  // namespace
+
+extern "C" {
 
 glmr_status glmr_batch_eval(glmr_batch* b, double* ll) {
   if (!b) return GLMR_EINVAL;
+  HIPCHK(b->ctxs[0], hipSetDevice(b->dev));
+  OnBatchStream on(b);
+  TRY(batch_prepare(b));
+  TRY(batch_eval_core(b));
+  for (glmr_ctx* c : b->ctxs)
+    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double), hipMemcpyDeviceToHost, b->st));
+  HIPCHK(b->ctxs[0], hipStreamSynchronize(b->st));
   for (size_t r = 0; r < b->ctxs.size(); ++r) {
-    glmr_ctx* c = b->ctxs[r];
-    TRY(check_ready(c));
-    TRY(eval_core(c, true, false));
-  }
-  for (size_t r = 0; r < b->ctxs.size(); ++r) {
-    glmr_ctx* c = b->ctxs[r];
-    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipStreamSynchronize(c->st));
-    if (ll) ll[r] = c->host_scal[0];
+    if (ll) ll[r] = b->ctxs[r]->host_scal[0];
+    if (!std::isfinite(b->ctxs[r]->host_scal[0]))
+      return fail(b->ctxs[r], GLMR_ENONFINITE, "log-likelihood is not finite");
   }
   return GLMR_OK;
 }
@@ -869,6 +1110,7 @@ glmr_status glmr_batch_eval(glmr_batch* b, double* ll) {
 glmr_status glmr_batch_get_grad(glmr_batch* b, int32_t r, double* grad_J, double* grad_mu, int32_t where) {
   if (!b || r < 0 || r >= (int32_t)b->ctxs.size()) return GLMR_EINVAL;
   glmr_ctx* c = b->ctxs[r];
+  if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
   if (!c->gJ) return fail(c, GLMR_ESTATE, "no batch evaluation yet");
   if (grad_mu) HIPCHK(c, hipMemcpyAsync(grad_mu, c->gmu, c->N * sizeof(double), kind_to(where), c->st));
   if (grad_J)
@@ -878,13 +1120,60 @@ glmr_status glmr_batch_get_grad(glmr_batch* b, int32_t r, double* grad_J, double
   return GLMR_OK;
 }
 
-glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* o, glmr_fit_report* reps) {
+glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* o_in, glmr_fit_report* reps) {
   if (!b) return GLMR_EINVAL;
+  glmr_ctx* c0 = b->ctxs[0];
+  HIPCHK(c0, hipSetDevice(b->dev));
+  glmr_fit_opts o;
+  for (glmr_ctx* c : b->ctxs) {
+    c->err.clear();
+    TRY(check_fit_opts(c, o_in, &o));
+  }
+  auto t_start = std::chrono::steady_clock::now();
+  OnBatchStream on(b);
+  for (glmr_ctx* c : b->ctxs) TRY(fit_begin(c, o));
+  TRY(batch_prepare(b));
+  const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c0->prec);
+  TRY(batch_eval_theta(b, false));
+  for (glmr_ctx* c : b->ctxs) HIPCHK(c, launch_lbfgs_direction(c->asc, 1, b->st));
+  // one ascent step of every recording, captured once and replayed
+  auto step = [&]() -> glmr_status {
+    for (glmr_ctx* c : b->ctxs) HIPCHK(c, launch_make_trial(c->asc, b->st));
+    TRY(batch_eval_theta(b, true));
+    for (glmr_ctx* c : b->ctxs) {
+      const AscentArgs& a = c->asc;
+      HIPCHK(c, launch_armijo_async(a, 1e-4, o.max_backtracks, b->st));
+      HIPCHK(c, launch_accept_update(a, ftol, nullptr, 1, b->st));
+      HIPCHK(c, launch_lbfgs_direction(a, 1, b->st));
+      HIPCHK(c, launch_count_active(a, c->counters, b->st));
+    }
+    HIPCHK(c0, launch_sum_counters(b->dcnt, (int)b->ctxs.size(), b->dsum, b->st));
+    return GLMR_OK;
+  };
+  GraphRun gr;
+  if (use_graphs()) {
+    auto body = [&]() -> glmr_status {
+      for (glmr_ctx* c : b->ctxs) c->capturing = true;
+      const glmr_status s1 = step();
+      for (glmr_ctx* c : b->ctxs) c->capturing = false;
+      return s1;
+    };
+    TRY(gr.capture(c0, b->st, body));
+  }
+  int iters = 0, active = 1;
+  for (; iters < o.max_iter && active > 0; ++iters) {
+    if (gr.exec) HIPCHK(c0, hipGraphLaunch(gr.exec, b->st));
+    else TRY(step());
+    HIPCHK(c0, hipMemcpyAsync(b->hsum, b->dsum, sizeof(int32_t), hipMemcpyDeviceToHost, b->st));
+    HIPCHK(c0, hipStreamSynchronize(b->st));
+    active = b->hsum[0];
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   glmr_status worst = GLMR_OK;
   for (size_t r = 0; r < b->ctxs.size(); ++r) {
-    glmr_status s = fit_one(b->ctxs[r], o, reps ? &reps[r] : nullptr);
-    if (s < 0) return s;
-    if (s == GLMR_NOT_CONVERGED) worst = s;
+    const glmr_status s1 = fit_end(b->ctxs[r], iters, iters + 1, secs, reps ? &reps[r] : nullptr);
+    if (s1 < 0) return s1;
+    if (s1 == GLMR_NOT_CONVERGED) worst = s1;
   }
   return worst;
 }

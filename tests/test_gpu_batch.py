@@ -1,0 +1,133 @@
+"""Batched recordings of uneven N and T (needs an MI355X).
+
+With every trace resident, one persistent launch per contraction covers the
+tiles of all recordings; with the same tile shapes the batch must give
+bitwise the per-recording results, and those match the FP64 oracle.  The
+batched fit replays one captured graph per step for all recordings and must
+end at bitwise the parameters of the per-recording fits.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import glm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(70, 9_000), (130, 20_000), (260, 15_000), (333, 30_000), (520, 12_000)]
+
+
+def _G():
+    import paper_1502_04993_amd as G
+    return G
+
+
+def _bf16(J):
+    import torch
+    return torch.tensor(J).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _recs():
+    return [synth.balanced(N=n, B=b, seed=40 + k) for k, (n, b) in enumerate(SIZES)]
+
+
+def _ctx(rec, prec, shape=None):
+    G = _G()
+    old = os.environ.pop("GLMR_RES_SHAPE", None)
+    if shape is not None:
+        os.environ["GLMR_RES_SHAPE"] = shape
+    try:
+        c = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision=prec)
+    finally:
+        os.environ.pop("GLMR_RES_SHAPE", None)
+        if old is not None:
+            os.environ["GLMR_RES_SHAPE"] = old
+    c.set_spikes(rec.bins, rec.neurons)
+    c.set_kernel(rec.tau)
+    return c
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "fp64"])
+def test_batch_eval_equals_each_context_and_oracle(prec):
+    G = _G()
+    recs = _recs()
+    shape = "5,5" if prec != "fp64" else None  # one shape every padding allows
+    ctxs = [_ctx(r, prec, shape) for r in recs]
+    thetas = []
+    for r, c in zip(recs, ctxs):
+        J = _bf16(r.J) if prec == "bf16" else r.J
+        if prec == "fp8":
+            from test_gpu_parity import round_fp8_rows
+            J = round_fp8_rows(r.J)
+        c.set_params(J, r.mu)
+        thetas.append(J)
+    singles = [c.eval(grad=True) for c in ctxs]
+    b = G.Batch(ctxs)
+    lls = b.eval()
+    tol = {"bf16": (1e-3, 1e-3), "fp8": (2e-3, 3e-2), "fp64": (1e-12, 1e-10)}[prec]
+    for k, (r, c) in enumerate(zip(recs, ctxs)):
+        gJ, gmu = b.grad(k)
+        assert lls[k] == singles[k]["ll"]
+        assert np.array_equal(gJ, singles[k]["gJ"]) and np.array_equal(gmu, singles[k]["gmu"])
+        ref = O.loglik(r.bins, r.neurons, r.n_neurons, r.n_bins, r.dt, r.tau, thetas[k], r.mu)
+        rl = abs(lls[k] - ref["ll"]) / abs(ref["ll"])
+        g = np.concatenate([gmu, gJ.ravel()])
+        gr = np.concatenate([ref["gmu"], ref["gJ"].ravel()])
+        rg = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+        print(f"[batch {prec} rec {k} N={r.n_neurons} B={r.n_bins}] rel_ll={rl:.3e} rel_grad={rg:.3e}", flush=True)
+        assert rl <= tol[0] and rg <= tol[1]
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp64"])
+def test_batch_fit_equals_individual_fits(prec):
+    G = _G()
+    recs = [synth.balanced(N=n, B=b, in_frac=0.2, seed=60 + k)
+            for k, (n, b) in enumerate([(40, 8_000), (90, 12_000), (150, 10_000)])]
+    shape = "5,5" if prec == "bf16" else None
+    single = []
+    for r in recs:
+        c = _ctx(r, prec, shape)
+        c.fit(max_iter=400, from_zero=True)
+        single.append(c.get_params()[:2])
+        c.close()
+    ctxs = [_ctx(r, prec, shape) for r in recs]
+    b = G.Batch(ctxs)
+    st, reps = b.fit(max_iter=400, from_zero=True)
+    print(f"[batch fit {prec}] status={st} " + " ".join(f"iters={x['iters']} conv={x['rows_converged']}" for x in reps),
+          flush=True)
+    for k, c in enumerate(ctxs):
+        J, mu, _ = c.get_params()
+        assert np.array_equal(J, single[k][0]) and np.array_equal(mu, single[k][1])
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_fit_graph_replays_match_eager():
+    G = _G()
+    recs = [synth.balanced(N=n, B=b, in_frac=0.2, seed=70 + k)
+            for k, (n, b) in enumerate([(50, 6_000), (120, 9_000)])]
+    old = os.environ.get("GLMR_NO_GRAPH")
+    out = []
+    try:
+        for flag in ("1", "0"):
+            os.environ["GLMR_NO_GRAPH"] = flag
+            ctxs = [_ctx(r, "bf16", "5,5") for r in recs]
+            b = G.Batch(ctxs)
+            b.fit(max_iter=12, from_zero=True)
+            out.append([c.get_params()[0] for c in ctxs])
+            b.close()
+            for c in ctxs:
+                c.close()
+    finally:
+        if old is None:
+            os.environ.pop("GLMR_NO_GRAPH", None)
+        else:
+            os.environ["GLMR_NO_GRAPH"] = old
+    for a, b2 in zip(out[0], out[1]):
+        assert np.array_equal(a, b2)
