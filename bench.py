@@ -122,6 +122,10 @@ def main():
     ap.add_argument("--trace", default="auto", choices=["auto", "resident", "recompute"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--workload", default="balanced_n1000", choices=["balanced_n1000", "batch64"],
+                    help="batch64: 64 recordings of uneven N and T (balanced and synfire), "
+                         "evaluated together (grouped launches)")
+    ap.add_argument("--n-rec", type=int, default=64, help="batch64: number of recordings")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 comparison line")
     ap.add_argument("--cpu-sample-bins", type=int, default=1_572_864)
@@ -141,6 +145,9 @@ def main():
     import paper_1502_04993_amd as G
 
     torch.cuda.init()
+    if args.workload == "batch64":
+        bench_batch(args, G, torch)
+        return
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -229,6 +236,57 @@ def main():
     out.update(extra)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(rec, min(args.cpu_sample_bins, B))
+    print(json.dumps(out))
+
+
+def bench_batch(args, G, torch):
+    """64 recordings (N ~ U{100..2000}, synfire half U{625..2000}; T ~ U[60, 600] s;
+    even balanced, odd synfire), all evaluated by one batched call: the value is
+    sum_r B_r N_r^2 over the seconds of one batched evaluation."""
+    import synth
+    sizes = synth.config5_sizes()[: args.n_rec]
+    ctxs, units, nbins = [], 0.0, 0
+    t_setup = time.perf_counter()
+    for r, (kind, N, B, seed) in enumerate(sizes):
+        rec = synth.config5_recording(kind, N, B, seed)
+        c = G.Context(N, B, rec.dt, precision=args.precision)
+        c.set_spikes_allow_silent(rec.bins, rec.neurons)
+        c.set_kernel(rec.tau)
+        c.set_params(rec.J, rec.mu)
+        ctxs.append(c)
+        units += float(B) * N * N
+        nbins += B
+        print(f"[batch64] recording {r} {kind} N={N} B={B} ready", file=sys.stderr, flush=True)
+        del rec
+    b = G.Batch(ctxs)
+    tiles = b.autotune() if not args.no_tune else (-1, -1)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t_setup
+    for _ in range(args.warmup):
+        b.eval()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lls = b.eval()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    peak = PEAK[args.precision]
+    achieved = 4.0 * units / sec
+    out = {
+        "metric": "LL+grad throughput (bins*N^2/s), recordings batched",
+        "value": units / sec, "unit": "bins*N^2/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"batch{len(sizes)}_balanced_synfire_uneven_n_t", "n_recordings": len(sizes),
+                   "sum_bins": nbins, "sum_bins_N2": units, "tile_shapes": list(tiles)},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "whole batched evaluation (4 sum B N^2 flop per evaluation)"},
+        "setup_ms": setup * 1e3, "ll_sum": float(sum(lls)),
+    }
+    for c in ctxs:
+        c.close()
+    b.close()
     print(json.dumps(out))
 
 

@@ -209,6 +209,15 @@ glmr_status glmr_batch_get_grad(glmr_batch* b, int32_t r, double* grad_J, double
  * (nullable). */
 glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* opts, glmr_fit_report* reports);
 
+/* Autotuner of the grouped launches: times every tile shape that all the
+ * batch's recordings allow on the batch's first time chunk (three launches of
+ * each grouped kernel) and keeps the fastest for later batch calls.  Cache as
+ * in glmr_autotune, keyed by the architecture, precision and the recordings'
+ * padded sizes.  Reports -1 when the batch is not grouped (some trace not
+ * resident).  Clobbers the contexts' evaluation workspaces. */
+glmr_status glmr_batch_autotune(glmr_batch* b, const char* cache_path, int32_t* shape_u,
+                                int32_t* shape_g);
+
 /* ------------------------------------------------------------- diagnostics */
 const char* glmr_status_string(glmr_status s);
 const char* glmr_last_error(const glmr_ctx* ctx);

@@ -205,6 +205,13 @@ def glmr_batch_get_grad(b, r, grad_J=None, grad_mu=None):
     return _check(L.load().glmr_batch_get_grad(b, r, pj, pm, where))
 
 
+def glmr_batch_autotune(b, cache_path=None):
+    u, g = ctypes.c_int32(), ctypes.c_int32()
+    _check(L.load().glmr_batch_autotune(b, cache_path.encode() if cache_path else None, ctypes.byref(u),
+                                        ctypes.byref(g)))
+    return u.value, g.value
+
+
 def glmr_batch_fit(b, n, opts=None):
     o = opts if opts is not None else glmr_fit_defaults()
     reps = (L.glmr_fit_report * n)()
@@ -342,6 +349,10 @@ class Batch:
 
     def eval(self):
         return glmr_batch_eval(self._b, len(self.ctxs))
+
+    def autotune(self, cache_path=None):
+        """Pick the fastest tile shapes of the grouped launches (see glmr_batch_autotune)."""
+        return glmr_batch_autotune(self._b, cache_path)
 
     def grad(self, r):
         c = self.ctxs[r]

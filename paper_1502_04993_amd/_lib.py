@@ -66,6 +66,8 @@ SIGNATURES = {
     "glmr_batch_destroy": (None, [_vp]),
     "glmr_batch_eval": (ctypes.c_int, [_vp, _dp]),
     "glmr_batch_get_grad": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32]),
+    "glmr_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)]),
     "glmr_batch_fit": (ctypes.c_int, [_vp, ctypes.POINTER(glmr_fit_opts), ctypes.POINTER(glmr_fit_report)]),
     "glmr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "glmr_last_error": (ctypes.c_char_p, [_vp]),

@@ -857,6 +857,44 @@ glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep
 
 }  // namespace
 
+// autotuner helpers
+namespace {
+
+// mean milliseconds of `reps` launches of fn on the context's stream (after one warm-up)
+template <typename F>
+glmr_status time_launches(glmr_ctx* c, F fn, int reps, double* ms) {
+  hipEvent_t a, b;
+  HIPCHK(c, hipEventCreate(&a));
+  HIPCHK(c, hipEventCreate(&b));
+  glmr_status st = GLMR_OK;
+  float el = 0.f;
+  if (fn() != hipSuccess) st = fail(c, GLMR_EDEVICE, "autotune launch failed");
+  if (st == GLMR_OK && hipEventRecord(a, c->st) != hipSuccess) st = fail(c, GLMR_EDEVICE, "event record");
+  for (int r = 0; st == GLMR_OK && r < reps; ++r)
+    if (fn() != hipSuccess) st = fail(c, GLMR_EDEVICE, "autotune launch failed");
+  if (st == GLMR_OK && (hipEventRecord(b, c->st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                        hipEventElapsedTime(&el, a, b) != hipSuccess))
+    st = fail(c, GLMR_EDEVICE, "event timing");
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  *ms = el / reps;
+  return st;
+}
+
+std::string tune_key(glmr_ctx* c) {
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->cfg.device) == hipSuccess) arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s %lld %lld %d", arch.c_str(), (long long)c->Np, (long long)c->L,
+                c->prec);
+  return buf;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------- batching
 struct glmr_batch {
   std::vector<glmr_ctx*> ctxs;
@@ -864,6 +902,7 @@ struct glmr_batch {
   hipStream_t st = nullptr;
   bool grouped = false;  // one persistent launch per contraction over every recording
   int shape_u = -1, shape_g = -1;
+  int tuned_u = -1, tuned_g = -1;  // set by glmr_batch_autotune
   struct Chunk {         // the recordings that have time chunk ci, as work queues
     std::vector<int> recs, nsplits;
     ResUArgs* du = nullptr;
@@ -1079,8 +1118,8 @@ glmr_status batch_prepare(glmr_batch* b) {
   }
   b->grouped = grouped;
   if (grouped) {
-    b->shape_u = common_shape(b, b->ctxs[0]->res_shape_u);
-    b->shape_g = common_shape(b, b->ctxs[0]->res_shape_g);
+    b->shape_u = common_shape(b, b->tuned_u >= 0 ? b->tuned_u : b->ctxs[0]->res_shape_u);
+    b->shape_g = common_shape(b, b->tuned_g >= 0 ? b->tuned_g : b->ctxs[0]->res_shape_g);
     b->grouped = b->shape_u >= 0 && b->shape_g >= 0;
   }
   return build_queues(b);
@@ -1117,6 +1156,81 @@ glmr_status glmr_batch_get_grad(glmr_batch* b, int32_t r, double* grad_J, double
     HIPCHK(c, hipMemcpy2DAsync(grad_J, c->N * sizeof(double), c->gJ, c->Np * sizeof(double),
                                c->N * sizeof(double), c->N, kind_to(where), c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  return GLMR_OK;
+}
+
+glmr_status glmr_batch_autotune(glmr_batch* b, const char* cache_path, int32_t* shape_u, int32_t* shape_g) {
+  if (!b) return GLMR_EINVAL;
+  glmr_ctx* c0 = b->ctxs[0];
+  HIPCHK(c0, hipSetDevice(b->dev));
+  OnBatchStream on(b);
+  b->tuned_u = b->tuned_g = -1;
+  TRY(batch_prepare(b));
+  if (!b->grouped) {
+    if (shape_u) *shape_u = -1;
+    if (shape_g) *shape_g = -1;
+    return GLMR_OK;
+  }
+  // key: architecture, precision, recording count and sizes
+  uint64_t h = 1469598103934665603ull;
+  for (glmr_ctx* c : b->ctxs) {
+    for (int64_t v : {c->Np, c->Bp, c->L}) {
+      h ^= (uint64_t)v;
+      h *= 1099511628211ull;
+    }
+  }
+  char kb[64];
+  std::snprintf(kb, sizeof(kb), "batch%zu-%016llx", b->ctxs.size(), (unsigned long long)h);
+  std::string key = tune_key(c0);
+  key = key.substr(0, key.find(' ')) + " " + kb + " 0 " + std::to_string(c0->prec);
+  int best_u = -1, best_g = -1;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        char arch[128], k2[128];
+        long long l = 0;
+        int prec = -1, u = -1, g = -1;
+        if (std::sscanf(line, "glmrec-tune %127s %127s %lld %d %d %d", arch, k2, &l, &prec, &u, &g) == 6) {
+          const std::string kk = std::string(arch) + " " + k2 + " " + std::to_string(l) + " " + std::to_string(prec);
+          if (kk == key && common_shape(b, u) == u && common_shape(b, g) == g) {
+            best_u = u;
+            best_g = g;
+          }
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  if (best_u < 0) {
+    int n = 0;
+    (void)res_shapes(&n);
+    const int fp8 = c0->prec == PREC_FP8 ? 1 : 0;
+    double tu = 1e300, tg = 1e300;
+    for (int k = 0; k < n; ++k) {
+      if (common_shape(b, k) != k) continue;
+      b->shape_u = b->shape_g = k;
+      TRY(build_queues(b));
+      const glmr_batch::Chunk& ch = b->chunks[0];
+      const int m = (int)ch.recs.size();
+      double ms = 0;
+      TRY(time_launches(c0, [&] { return launch_res_u_group(k, fp8, ResUGroup{ch.du, ch.pu, m, ch.tu}, b->st); }, 3, &ms));
+      if (ms < tu) { tu = ms; best_u = k; }
+      TRY(time_launches(c0, [&] { return launch_res_g_group(k, fp8, ResGGroup{ch.dg, ch.pg, m, ch.tg}, b->st); }, 3, &ms));
+      if (ms < tg) { tg = ms; best_g = k; }
+    }
+    if (cache_path && best_u >= 0) {
+      if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "glmrec-tune %s %d %d %.4f %.4f\n", key.c_str(), best_u, best_g, tu, tg);
+        std::fclose(f);
+      }
+    }
+  }
+  b->tuned_u = best_u;
+  b->tuned_g = best_g;
+  TRY(batch_prepare(b));
+  if (shape_u) *shape_u = b->shape_u;
+  if (shape_g) *shape_g = b->shape_g;
   return GLMR_OK;
 }
 
@@ -1533,42 +1647,7 @@ glmr_status glmr_query(const glmr_ctx* c, int64_t* n_pad, int64_t* b_pad, int64_
 }  // extern "C"
 
 // ------------------------------------------------------------------ autotuner
-namespace {
 
-// mean milliseconds of `reps` launches of fn on the context's stream (after one warm-up)
-template <typename F>
-glmr_status time_launches(glmr_ctx* c, F fn, int reps, double* ms) {
-  hipEvent_t a, b;
-  HIPCHK(c, hipEventCreate(&a));
-  HIPCHK(c, hipEventCreate(&b));
-  glmr_status st = GLMR_OK;
-  float el = 0.f;
-  if (fn() != hipSuccess) st = fail(c, GLMR_EDEVICE, "autotune launch failed");
-  if (st == GLMR_OK && hipEventRecord(a, c->st) != hipSuccess) st = fail(c, GLMR_EDEVICE, "event record");
-  for (int r = 0; st == GLMR_OK && r < reps; ++r)
-    if (fn() != hipSuccess) st = fail(c, GLMR_EDEVICE, "autotune launch failed");
-  if (st == GLMR_OK && (hipEventRecord(b, c->st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
-                        hipEventElapsedTime(&el, a, b) != hipSuccess))
-    st = fail(c, GLMR_EDEVICE, "event timing");
-  hipEventDestroy(a);
-  hipEventDestroy(b);
-  *ms = el / reps;
-  return st;
-}
-
-std::string tune_key(glmr_ctx* c) {
-  hipDeviceProp_t prop{};
-  std::string arch = "unknown";
-  if (hipGetDeviceProperties(&prop, c->cfg.device) == hipSuccess) arch = prop.gcnArchName;
-  for (char& ch : arch)
-    if (ch == ' ') ch = '_';
-  char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s %lld %lld %d", arch.c_str(), (long long)c->Np, (long long)c->L,
-                c->prec);
-  return buf;
-}
-
-}  // namespace
 
 extern "C" glmr_status glmr_autotune(glmr_ctx* c, const char* cache_path, int32_t* shape_u,
                                      int32_t* shape_g) {

@@ -131,3 +131,24 @@ def test_batch_fit_graph_replays_match_eager():
             os.environ["GLMR_NO_GRAPH"] = old
     for a, b2 in zip(out[0], out[1]):
         assert np.array_equal(a, b2)
+
+
+def test_batch_autotune_keeps_results_within_tolerance(tmp_path):
+    G = _G()
+    recs = _recs()
+    ctxs = [_ctx(r, "bf16") for r in recs]
+    for r, c in zip(recs, ctxs):
+        c.set_params(_bf16(r.J), r.mu)
+    b = G.Batch(ctxs)
+    cache = str(tmp_path / "tune.txt")
+    u, g = b.autotune(cache)
+    assert u in (3, 4, 5, 6) and g in (3, 4, 5, 6)  # N = 70 pads to 128: only 128-neuron tiles
+    assert b.autotune(cache) == (u, g)
+    assert len(open(cache).read().splitlines()) == 1
+    lls = b.eval()
+    for k, r in enumerate(recs):
+        ref = O.loglik(r.bins, r.neurons, r.n_neurons, r.n_bins, r.dt, r.tau, _bf16(r.J), r.mu)
+        assert abs(lls[k] - ref["ll"]) / abs(ref["ll"]) <= 1e-3
+    b.close()
+    for c in ctxs:
+        c.close()
