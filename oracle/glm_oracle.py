@@ -390,6 +390,66 @@ def lbfgs_fit(bins, neurons, N: int, B: int, dt: float, tau: float,
     return res.x[N:].reshape(N, N), res.x[:N], res
 
 
+# ------------------------------- penalty and bound constraints (Sec. 2.5, 2.6.3)
+
+def l1_eps_penalty(J: np.ndarray, alpha: float, eps: float):
+    """The smooth epsilon-l1 penalty of Eq. (16)-(17) per row,
+    alpha * sum_{j != i} sqrt(J_ij^2 + eps), and its derivative with respect to
+    J_ij, alpha * J_ij / sqrt(J_ij^2 + eps) (zero on the diagonal: the
+    self-connection is not penalised)."""
+    J = np.asarray(J, dtype=np.float64)
+    off = ~np.eye(J.shape[0], J.shape[1], dtype=bool)
+    r = np.sqrt(J * J + eps)
+    pen = alpha * np.where(off, r, 0.0).sum(axis=1)
+    dpen = alpha * np.where(off, J / r, 0.0)
+    return pen, dpen
+
+
+def penalized_fit(bins, neurons, N: int, B: int, dt: float, tau: float, alpha: float = 0.0,
+                  eps: float = 1e-8, j_max: Optional[float] = None,
+                  rate_min: Optional[float] = None, rate_max: Optional[float] = None,
+                  ftol: float = 1e-15, gtol: float = 1e-12, maxiter: int = 20000):
+    """Maximise L_i - alpha sum_{j != i} sqrt(J_ij^2 + eps) for every row i
+    (Eq. (16)-(17)) subject to |J_ij| <= j_max and rate_min <= e^{mu_i} <=
+    rate_max (the bounds of Sec. 2.6.3), by scipy's L-BFGS-B, the bounded
+    quasi-Newton method the paper used.  The objective is separable over rows,
+    so each row is its own problem.  Returns (J, mu, results)."""
+    S = spike_matrix(bins, neurons, N, B).toarray()
+    X = trace_lfilter(S, decay(dt, tau))
+    A = np.concatenate([np.ones((B, 1)), X], axis=1)
+    lo_mu = math.log(rate_min) if rate_min else None
+    hi_mu = math.log(rate_max) if rate_max else None
+    bounds = [(lo_mu, hi_mu)] + [(-j_max, j_max) if j_max else (None, None)] * N
+    J = np.zeros((N, N))
+    mu = np.zeros(N)
+    results = []
+    for i in range(N):
+        s = S[:, i]
+
+        def f(th):
+            U = A @ th
+            lam = np.exp(U)
+            L = float(s @ U) - dt * float(lam.sum())
+            g = A.T @ (s - dt * lam)
+            Jr = th[1:]
+            r = np.sqrt(Jr * Jr + eps)
+            pen = alpha * (r.sum() - r[i])
+            d = alpha * Jr / r
+            d[i] = 0.0
+            return -(L - pen), -(g - np.concatenate([[0.0], d]))
+
+        th0 = np.zeros(N + 1)
+        if lo_mu is not None or hi_mu is not None:
+            th0[0] = min(max(0.0, lo_mu if lo_mu is not None else -np.inf),
+                         hi_mu if hi_mu is not None else np.inf)
+        res = scipy.optimize.minimize(f, th0, jac=True, method="L-BFGS-B", bounds=bounds,
+                                      options=dict(ftol=ftol, gtol=gtol, maxiter=maxiter, maxcor=10))
+        mu[i] = res.x[0]
+        J[i] = res.x[1:]
+        results.append(res)
+    return J, mu, results
+
+
 # ------------------------------------------- continuous time (tiny inputs)
 
 def _ei_diff(D: float, xi: float) -> float:
