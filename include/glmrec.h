@@ -154,12 +154,22 @@ typedef struct {
   int32_t max_backtracks; /* Armijo halvings per iteration (default 30) */
   int32_t warm_start_mu;  /* 1: start mu_i at log(q_i / T) instead of the current mu */
   int32_t from_zero;      /* 1: start from J = 0, mu = 0 (overrides the current params) */
+  /* Regularisation (Sec. 2.5) and bounds (Sec. 2.6.3); zeros leave them off.
+   * The maximised objective becomes L_i - l1_alpha sum_{j != i}
+   * sqrt(J_ij^2 + l1_eps) (Eq. (16)-(17)); parameters stay in the box
+   * |J_ij| <= j_max, rate_min <= e^{mu_i} <= rate_max (trial points are
+   * projected on it; components held at a bound leave the search direction). */
+  double l1_alpha;        /* penalty strength, >= 0 */
+  double l1_eps;          /* its smoothing epsilon (0: 1e-8) */
+  double j_max;           /* bound on |J_ij| (0: none) */
+  double rate_min;        /* lower bound on e^{mu_i} in 1/s (0: none) */
+  double rate_max;        /* upper bound on e^{mu_i} in 1/s (0: none) */
 } glmr_fit_opts;
 
 typedef struct {
   int32_t iters;          /* ascent steps taken (one trial evaluation each) */
   int32_t evals;          /* likelihood evaluations (steps + the initial one) */
-  double ll;              /* final L */
+  double ll;              /* final L (minus the penalty when l1_alpha > 0) */
   double max_eta;         /* max over rows of the last fractional change */
   int32_t rows_converged; /* rows that met ftol */
   double seconds;         /* wall time of the fit */

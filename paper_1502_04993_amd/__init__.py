@@ -291,12 +291,15 @@ class Context:
         return dict(ll=ll, ll_rows=ll_rows, gJ=gJ, gmu=gmu, gtau=gt)
 
     def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
-            from_zero=False, polish=None, polish_iter=200):
+            from_zero=False, polish=None, polish_iter=200, l1_alpha=0.0, l1_eps=0.0, j_max=0.0,
+            rate_min=0.0, rate_max=0.0):
         """Per-row L-BFGS ascent.  polish="fp32" finishes a BF16 ascent with FP32
-        evaluations from the BF16 optimum (then switches back)."""
+        evaluations from the BF16 optimum (then switches back).  l1_alpha /
+        l1_eps: the smooth epsilon-l1 penalty; j_max, rate_min, rate_max: bounds."""
         o = glmr_fit_defaults()
         o.max_iter, o.ftol, o.lbfgs_m, o.max_backtracks = max_iter, ftol, lbfgs_m, max_backtracks
         o.warm_start_mu, o.from_zero = int(warm_start_mu), int(from_zero)
+        o.l1_alpha, o.l1_eps, o.j_max, o.rate_min, o.rate_max = l1_alpha, l1_eps, j_max, rate_min, rate_max
         st, rep = glmr_fit(self._c, o)
         out = dict(status=st, converged=(st == GLMR_OK), iters=rep.iters, evals=rep.evals,
                    ll=rep.ll, max_eta=rep.max_eta, rows_converged=rep.rows_converged,
@@ -362,10 +365,11 @@ class Batch:
         return gJ, gmu
 
     def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
-            from_zero=False):
+            from_zero=False, l1_alpha=0.0, l1_eps=0.0, j_max=0.0, rate_min=0.0, rate_max=0.0):
         o = glmr_fit_defaults()
         o.max_iter, o.ftol, o.lbfgs_m, o.max_backtracks = max_iter, ftol, lbfgs_m, max_backtracks
         o.warm_start_mu, o.from_zero = int(warm_start_mu), int(from_zero)
+        o.l1_alpha, o.l1_eps, o.j_max, o.rate_min, o.rate_max = l1_alpha, l1_eps, j_max, rate_min, rate_max
         st, reps = glmr_batch_fit(self._b, len(self.ctxs), o)
         return st, [dict(iters=r.iters, evals=r.evals, ll=r.ll, max_eta=r.max_eta,
                          rows_converged=r.rows_converged, seconds=r.seconds) for r in reps]

@@ -39,7 +39,9 @@ class glmr_config(ctypes.Structure):
 class glmr_fit_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("ftol", ctypes.c_double), ("lbfgs_m", ctypes.c_int32),
                 ("max_backtracks", ctypes.c_int32), ("warm_start_mu", ctypes.c_int32),
-                ("from_zero", ctypes.c_int32)]
+                ("from_zero", ctypes.c_int32), ("l1_alpha", ctypes.c_double),
+                ("l1_eps", ctypes.c_double), ("j_max", ctypes.c_double), ("rate_min", ctypes.c_double),
+                ("rate_max", ctypes.c_double)]
 
 
 class glmr_fit_report(ctypes.Structure):

@@ -266,8 +266,13 @@ struct AscentArgs {
   int32_t* accepted;      // [Np]
   double* eta;            // [Np]
   int32_t* bt;            // [Np] halvings of the current line search
+  double* gstep;          // [Np] g_i . (theta_try_i - theta_i) of the current trial
+  // smooth epsilon-l1 penalty (alpha = 0: none) and bounds (jmax = 0: none on J)
+  double alpha, eps, jmax, mu_lo, mu_hi;
 };
 hipError_t launch_lbfgs_direction(const AscentArgs& a, int async, hipStream_t st);
+hipError_t launch_penalty(const AscentArgs& a, const double* theta, double* g, double* f, hipStream_t st);
+hipError_t launch_project_theta(const AscentArgs& a, double* theta, hipStream_t st);
 hipError_t launch_armijo_async(const AscentArgs& a, double c1, int max_bt, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);
 hipError_t launch_count_active(const AscentArgs& a, int32_t* counters, hipStream_t st);

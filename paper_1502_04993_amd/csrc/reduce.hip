@@ -221,6 +221,59 @@ __global__ void k_pack_grad(int N, int64_t Np, int P, const double* gJ, const do
   }
 }
 
+// Bounds of component c of a row (c = 0: mu, else J): [lo, hi]
+__device__ inline void comp_bounds(const AscentArgs& a, int c, double* lo, double* hi) {
+  if (c == 0) {
+    *lo = a.mu_lo;
+    *hi = a.mu_hi;
+  } else if (a.jmax > 0) {
+    *lo = -a.jmax;
+    *hi = a.jmax;
+  } else {
+    *lo = -INFINITY;
+    *hi = INFINITY;
+  }
+}
+
+// Gradient of f = -L with the steps that would leave the box removed: a
+// component at its lower bound with g > 0, or at its upper bound with g < 0,
+// cannot move along -g.
+__device__ inline double proj_grad(const AscentArgs& a, int c, double th, double gv) {
+  double lo, hi;
+  comp_bounds(a, c, &lo, &hi);
+  if ((th <= lo && gv > 0.0) || (th >= hi && gv < 0.0)) return 0.0;
+  return gv;
+}
+
+// f += alpha sum_{j != i} sqrt(J_ij^2 + eps), g_J += alpha J / sqrt(J^2 + eps)
+// (Eq. (16)-(17); the self-connection is not penalised).  One block per row.
+__global__ __launch_bounds__(RT) void k_penalty(AscentArgs a, const double* theta, double* g, double* f) {
+  __shared__ double sh[RT];
+  const int64_t i = blockIdx.x;
+  const int P = a.P;
+  const double* th = theta + i * P;
+  double* gi = g + i * P;
+  double v = 0.0;
+  for (int c = 1 + threadIdx.x; c < P; c += RT) {
+    if (c - 1 == i) continue;
+    const double J = th[c], r = sqrt(J * J + a.eps);
+    v += r;
+    gi[c] += a.alpha * J / r;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) f[i] += a.alpha * v;
+}
+
+__global__ void k_project_theta(AscentArgs a, double* theta) {
+  const int64_t n = (int64_t)a.N * a.P;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double lo, hi;
+    comp_bounds(a, (int)(k % a.P), &lo, &hi);
+    theta[k] = fmin(fmax(theta[k], lo), hi);
+  }
+}
+
 // two-loop recursion for row i (f = -L, so d is a descent direction of f)
 __global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int async) {
   __shared__ double sh[RT];
@@ -238,7 +291,8 @@ __global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int async) {
     return;
   }
   const int len = a.hist_len[i], head = a.hist_head[i];
-  for (int c = tid; c < P; c += RT) d[c] = g[c];
+  const double* th = a.theta + i * P;
+  for (int c = tid; c < P; c += RT) d[c] = proj_grad(a, c, th[c], g[c]);
   __syncthreads();
   // newest to oldest
   for (int k = 0; k < len; ++k) {
@@ -264,7 +318,10 @@ __global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int async) {
     gamma = sy / yy;
   } else {
     double gg = 0.0;
-    for (int c = tid; c < P; c += RT) gg += g[c] * g[c];
+    for (int c = tid; c < P; c += RT) {
+      const double pg = proj_grad(a, c, th[c], g[c]);
+      gg += pg * pg;
+    }
     gg = block_sum(gg, sh);
     gamma = 1.0 / fmax(sqrt(gg), 1e-300);  // first step: unit length along -g
   }
@@ -284,17 +341,21 @@ __global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int async) {
   }
   double gd = 0.0;
   for (int c = tid; c < P; c += RT) {
-    d[c] = -d[c];
+    // components held at a bound do not move
+    d[c] = (proj_grad(a, c, th[c], g[c]) == 0.0 && g[c] != 0.0) ? 0.0 : -d[c];
     gd += g[c] * d[c];
   }
   gd = block_sum(gd, sh);
   if (!(gd < 0.0)) {
-    // not a descent direction: drop the history, steepest descent of unit length
+    // not a descent direction: drop the history, projected steepest descent of unit length
     double gg = 0.0;
-    for (int c = tid; c < P; c += RT) gg += g[c] * g[c];
+    for (int c = tid; c < P; c += RT) {
+      const double pg = proj_grad(a, c, th[c], g[c]);
+      gg += pg * pg;
+    }
     gg = block_sum(gg, sh);
     const double sc = 1.0 / fmax(sqrt(gg), 1e-300);
-    for (int c = tid; c < P; c += RT) d[c] = -sc * g[c];
+    for (int c = tid; c < P; c += RT) d[c] = -sc * proj_grad(a, c, th[c], g[c]);
     gd = -sqrt(gg);
     if (tid == 0) a.hist_len[i] = 0;
   }
@@ -306,16 +367,32 @@ __global__ __launch_bounds__(RT) void k_lbfgs_dir(AscentArgs a, int async) {
   }
 }
 
-__global__ void k_make_trial(AscentArgs a) {
-  const int64_t n = (int64_t)a.N * a.P;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = k / a.P;
-    if (a.state[i] == 0 && !a.accepted[i])
-      a.theta_try[k] = a.theta[k] + a.step[i] * a.d[k];
-    else if (a.state[i] != 0)
-      a.theta_try[k] = a.theta[k];
+// trial point of row i: theta + step d projected on the box (theta itself for
+// rows that stopped), and gstep_i = g_i . (theta_try_i - theta_i), the
+// first-order change the Armijo test compares with.  One block per row.
+__global__ __launch_bounds__(RT) void k_make_trial(AscentArgs a) {
+  __shared__ double sh[RT];
+  const int64_t i = blockIdx.x;
+  const int P = a.P;
+  const double* th = a.theta + i * P;
+  const double* d = a.d + i * P;
+  const double* g = a.g + i * P;
+  double* tt = a.theta_try + i * P;
+  const bool move = a.state[i] == 0 && !a.accepted[i];
+  const double st = a.step[i];
+  double v = 0.0;
+  for (int c = threadIdx.x; c < P; c += RT) {
+    double x = th[c];
+    if (move) {
+      double lo, hi;
+      comp_bounds(a, c, &lo, &hi);
+      x = fmin(fmax(th[c] + st * d[c], lo), hi);
+      v += g[c] * (x - th[c]);
+    }
+    if (move || a.state[i] != 0) tt[c] = x;
   }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) a.gstep[i] = v;
 }
 
 // accept the trial, update the history, test the stopping rule.
@@ -377,7 +454,7 @@ __global__ void k_armijo_async(AscentArgs a, double c1, int max_bt) {
   if (i >= a.N) return;
   if (a.state[i] != 0 || a.accepted[i] != 0) return;
   const double ft = a.f_try[i];
-  if (isfinite(ft) && ft <= a.f[i] + c1 * a.step[i] * a.gd[i]) {
+  if (isfinite(ft) && ft <= a.f[i] + c1 * a.gstep[i]) {
     a.accepted[i] = 1;
   } else if (a.bt[i] >= max_bt) {
     a.accepted[i] = 2;
@@ -532,7 +609,18 @@ hipError_t launch_count_active(const AscentArgs& a, int32_t* counters, hipStream
 }
 
 hipError_t launch_make_trial(const AscentArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_make_trial, dim3(grid_for((int64_t)a.N * a.P, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_make_trial, dim3((unsigned)a.N), dim3(RT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_penalty(const AscentArgs& a, const double* theta, double* g, double* f, hipStream_t st) {
+  if (!(a.alpha > 0.0)) return hipSuccess;
+  hipLaunchKernelGGL(k_penalty, dim3((unsigned)a.N), dim3(RT), 0, st, a, theta, g, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_theta(const AscentArgs& a, double* theta, hipStream_t st) {
+  hipLaunchKernelGGL(k_project_theta, dim3(grid_for((int64_t)a.N * a.P, 256)), dim3(256), 0, st, a, theta);
   return hipGetLastError();
 }
 

@@ -679,6 +679,7 @@ glmr_status alloc_ascent(glmr_ctx* c, int m) {
   TRY(dalloc(c, a.accepted, (size_t)N));
   TRY(dalloc(c, a.eta, (size_t)N));
   TRY(dalloc(c, a.bt, (size_t)N));
+  TRY(dalloc(c, a.gstep, (size_t)N));
   TRY(dalloc(c, c->counters, 4));
   if (!c->host_cnt) HIPCHK(c, hipHostMalloc((void**)&c->host_cnt, 4 * sizeof(int32_t), hipHostMallocDefault));
   c->have_asc = true;
@@ -693,6 +694,7 @@ glmr_status eval_theta(glmr_ctx* c, const double* theta_src, double* g, double* 
   TRY(eval_core(c, true, false));
   ProfScope ps(c, K_ASC);
   HIPCHK(c, launch_pack_grad(c->N, c->Np, a.P, c->gJ, c->gmu, c->ll_rows, g, f, c->st));
+  HIPCHK(c, launch_penalty(a, theta_src, g, f, c->st));
   return GLMR_OK;
 }
 
@@ -766,7 +768,9 @@ double default_ftol(int prec) {
 glmr_status check_fit_opts(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_opts* o) {
   glmr_fit_defaults(o);
   if (o_in) *o = *o_in;
-  if (o->max_iter < 0 || o->lbfgs_m < 1 || o->lbfgs_m > 64 || o->max_backtracks < 0 || o->ftol < 0)
+  if (o->max_iter < 0 || o->lbfgs_m < 1 || o->lbfgs_m > 64 || o->max_backtracks < 0 || o->ftol < 0 ||
+      !(o->l1_alpha >= 0) || !(o->l1_eps >= 0) || !(o->j_max >= 0) || !(o->rate_min >= 0) ||
+      !(o->rate_max >= 0) || (o->rate_min > 0 && o->rate_max > 0 && o->rate_min >= o->rate_max))
     return fail(c, GLMR_EINVAL, "bad fit options");
   if (!c->have_spikes || !c->have_kernel) return fail(c, GLMR_ESTATE, "set spikes and kernel first");
   if (!c->all_spiking) return fail(c, GLMR_ENOSPIKES, "some neuron has no spike: its MLE does not exist");
@@ -795,7 +799,14 @@ glmr_status fit_begin(glmr_ctx* c, const glmr_fit_opts& o) {
     HIPCHK(c, hipStreamSynchronize(c->st));
   }
   TRY(alloc_ascent(c, o.lbfgs_m));
-  HIPCHK(c, launch_unpack_theta(N, Np, c->asc.P, c->J64, c->mu, c->asc.theta, c->st));
+  AscentArgs& a = c->asc;
+  a.alpha = o.l1_alpha;
+  a.eps = o.l1_eps > 0 ? o.l1_eps : 1e-8;
+  a.jmax = o.j_max > 0 ? o.j_max : 0.0;
+  a.mu_lo = o.rate_min > 0 ? std::log(o.rate_min) : -INFINITY;
+  a.mu_hi = o.rate_max > 0 ? std::log(o.rate_max) : INFINITY;
+  HIPCHK(c, launch_unpack_theta(N, Np, a.P, c->J64, c->mu, a.theta, c->st));
+  HIPCHK(c, launch_project_theta(a, a.theta, c->st));  // start inside the box
   TRY(ascent_reset(c));
   return GLMR_OK;
 }
@@ -1057,6 +1068,8 @@ glmr_status batch_eval_theta(glmr_batch* b, bool trial) {
     const AscentArgs& a = c->asc;
     HIPCHK(c, launch_pack_grad(c->N, c->Np, a.P, c->gJ, c->gmu, c->ll_rows, trial ? a.g_try : a.g,
                                trial ? a.f_try : a.f, c->st));
+    HIPCHK(c, launch_penalty(a, trial ? a.theta_try : a.theta, trial ? a.g_try : a.g, trial ? a.f_try : a.f,
+                             c->st));
   }
   return GLMR_OK;
 }
@@ -1324,6 +1337,11 @@ void glmr_fit_defaults(glmr_fit_opts* o) {
   o->max_backtracks = 30;
   o->warm_start_mu = 0;
   o->from_zero = 0;
+  o->l1_alpha = 0.0;
+  o->l1_eps = 0.0;
+  o->j_max = 0.0;
+  o->rate_min = 0.0;
+  o->rate_max = 0.0;
 }
 
 glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
