@@ -357,3 +357,20 @@ def test_row_subset_is_the_same_definition():
     assert np.array_equal(sub["ll_rows"], full["ll_rows"][[4, 1]])
     assert np.allclose(sub["gJ"], full["gJ"][[4, 1]], rtol=1e-13, atol=1e-13)
     assert np.array_equal(sub["gmu"], full["gmu"][[4, 1]])
+
+
+def test_validation_likelihood_is_full_minus_training_prefix():
+    """The trace is causal, so the log-likelihood of the bins after a split,
+    with the whole recording as history, is the full L minus the L of the
+    training prefix alone (the identity the cross-validation scans use)."""
+    import synth
+    rec = synth.balanced(N=15, B=8000, in_frac=0.3, seed=4)
+    N, B = rec.n_neurons, rec.n_bins
+    rng = np.random.default_rng(5)
+    J = rec.J + rng.normal(0, 0.05, (N, N))
+    bt = 4700
+    full = O.loglik(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, J, rec.mu)
+    tail = O.loglik(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, J, rec.mu, bin_range=(bt, B))
+    m = rec.bins < bt
+    head = O.loglik(rec.bins[m], rec.neurons[m], N, bt, rec.dt, rec.tau, J, rec.mu)
+    assert np.allclose(full["ll_rows"] - head["ll_rows"], tail["ll_rows"], rtol=1e-12, atol=1e-9)
