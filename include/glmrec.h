@@ -22,6 +22,22 @@
  *   dL/dmu_i = q_i - dt sum_t lambda_i[t]
  *   dL/dtau  = sum_{t,i} (s_i[t] - dt lambda_i[t]) sum_j J_ij dx_j[t]/dtau
  *
+ * On the event grid (continuous time, Sec. 2.3, no binning): the spikes are q
+ * events (t_k, n_k) in [T0, T1); between consecutive events every potential
+ * relaxes, U_i(t) = mu_i + D_ik e^{-(t - t_k)/tau} with D_ik = sum_j J_ij v_j(t_k+)
+ * (Eq. (8)), so with delta_k = (t_{k+1} - t_k)/tau, xi_k = e^{-delta_k}:
+ *   L_i     = sum_{k: n_k = i} U_i(t_k-) - tau e^{mu_i} sum_k [Ei(D_ik) - Ei(D_ik xi_k)]  (Eq. (7), (10))
+ *   dL/dJ_ij = sum_{k: n_k = i} v_j(t_k-) - tau e^{mu_i} sum_k v_j(t_k+) (e^{D_ik} - e^{D_ik xi_k}) / D_ik
+ *                                                                         (Eq. (12), (14))
+ *   dL/dmu_i = q_i - tau e^{mu_i} sum_k [Ei(D_ik) - Ei(D_ik xi_k)]
+ * with v_j(t) = sum_{events m of j, t_m < t} e^{-(t - t_m)/tau}; the intervals
+ * run from T0 to the first event, between events, and from the last event to
+ * T1.  A spike does not act on its own neuron's intensity at its own time
+ * (left limit t_k-); events at equal times act in (time, neuron) order.
+ * The intervals are the "bins" of a non-uniform grid of slots (n_bins of the
+ * context = number of slots, from glmr_event_slots); everything else (params,
+ * eval, fit, batching) is shared with the regular grid.
+ *
  * Conventions shared by every entry point
  *   - Matrices are dense row-major with row = postsynaptic neuron:
  *     J[i*N + j] is the weight from presynaptic j to postsynaptic i.
@@ -84,7 +100,12 @@ typedef struct {
   int32_t tile_n;      /* neuron tile (128 or 256); 0 = automatic */
   int32_t trace;       /* where the BF16 trace lives (glmr_trace_mode); other
                           precisions always rebuild it inside the contractions */
+  int32_t time_mode;   /* glmr_time_mode: GLMR_TIME_EVENTS for continuous time
+                          (then n_bins = glmr_event_slots(...), precision FP64 or
+                          FP32, dt is not used) */
 } glmr_config;
+
+typedef enum { GLMR_TIME_GRID = 0, GLMR_TIME_EVENTS = 1 } glmr_time_mode;
 
 /* The trace x depends on the spikes and tau only.  GLMR_TRACE_RESIDENT builds
  * it once per tau and keeps it in HBM (4 * Bp * Np bytes: two BF16 layouts);
@@ -112,8 +133,40 @@ void glmr_destroy(glmr_ctx* ctx);
 glmr_status glmr_set_spikes(glmr_ctx* ctx, const int64_t* bin, const int32_t* neuron,
                             int64_t n_spikes, int32_t where);
 
+/* Number of slots of the event grid of q = n_events spike times (host array,
+ * sorted non-decreasing, each in [T0, T1)): one slot from T0, one per event,
+ * plus, for every gap between consecutive slot starts (T0, events, T1) longer
+ * than max_gap, ceil(gap / max_gap) - 1 spike-free slots splitting it evenly
+ * (the likelihood is additive over sub-intervals, so they change nothing but
+ * bound the span of 64 consecutive slots).  max_gap <= 0 selects
+ * 4 (T1 - T0) / (q + 1).  Host-only arithmetic; no device.  GLMR_EINVAL on
+ * unsorted or out-of-range times or a max_gap below (T1 - T0) / 1e9. */
+glmr_status glmr_event_slots(const double* times, int64_t n_events, double T0, double T1,
+                             double max_gap, int64_t* slots);
+
+/* The spikes of an event-grid context (time_mode GLMR_TIME_EVENTS): n_events
+ * pairs (times[k] seconds, neuron[k]) in `where` memory, T0 <= t < T1, in
+ * strictly increasing (time, neuron) order, and the same T0, T1, max_gap as
+ * given to glmr_event_slots, whose slot count must equal the context's
+ * n_bins.  Lays out the slots and ingests the events on the device.  Errors:
+ * GLMR_EINVAL on a range or order violation or a slot-count mismatch (nothing
+ * is kept), GLMR_ESTATE on a regular-grid context, GLMR_ENOSPIKES as for
+ * glmr_set_spikes.  glmr_set_kernel then also fails with GLMR_EINVAL if 64
+ * consecutive slots span more than 600 tau (pass a smaller max_gap). */
+glmr_status glmr_set_spike_times(glmr_ctx* ctx, const double* times, const int32_t* neuron,
+                                 int64_t n_events, double T0, double T1, double max_gap,
+                                 int32_t where);
+
+/* The two interval integrals of the event grid, on the host, by the same code
+ * the kernels run (Eq. (10), (14)): for an interval of length delta (in units
+ * of tau) starting at potential offset D,
+ *   F = int_0^delta exp(D e^{-s}) ds = Ei(D) - Ei(D e^{-delta}),
+ *   H = int_0^delta e^{-s} exp(D e^{-s}) ds = (e^D - e^{D e^{-delta}}) / D.
+ * Either output pointer may be NULL. */
+void glmr_ei_interval(double D, double delta, double* F, double* H);
+
 /* Kernel time constant tau (seconds) of h(t) = H(t) exp(-t/tau), Sec. 2.2.
- * Requires dt <= tau.  Computes the parameter-independent parts (the trace
+ * Requires dt <= tau on the regular grid.  Computes the parameter-independent parts (the trace
  * carries at every 64-bin boundary and the spike term
  * dSigma_ij = sum_t s_i[t] x_j[t] of Eq. (12), which Sec. 2.3.3 notes need
  * only be computed once). */
@@ -140,7 +193,7 @@ glmr_status glmr_get_params(glmr_ctx* ctx, double* J, double* mu, double* tau, i
  *   ll_rows  N doubles, nullable: L_i
  *   grad_J   N*N doubles, nullable: dL/dJ_ij
  *   grad_mu  N doubles, nullable: dL/dmu_i
- *   grad_tau host, 1 double, nullable: dL/dtau (one extra contraction)
+ *   grad_tau host, 1 double, nullable: dL/dtau (one extra contraction; regular grid only)
  * Array outputs live in `where` memory.  With grad_J and grad_mu both NULL
  * only the likelihood is computed.  GLMR_ENONFINITE if L is not finite. */
 glmr_status glmr_eval(glmr_ctx* ctx, double* ll, double* ll_rows, double* grad_J,

@@ -556,6 +556,59 @@ def continuous_grad_integral(spike_times: Sequence[np.ndarray], T0: float, T1: f
     return np.array([math.fsum(p) for p in parts])
 
 
+def _ei_diff_rows(D: np.ndarray, xi: float) -> np.ndarray:
+    """_ei_diff for a vector of D at one xi: the series where |D| < 1e-2, the
+    library exponential integral elsewhere."""
+    out = np.empty_like(D)
+    small = np.abs(D) < 1e-2
+    for k in np.flatnonzero(small):
+        out[k] = _ei_diff(float(D[k]), xi)
+    big = ~small
+    out[big] = scipy.special.expi(D[big]) - scipy.special.expi(D[big] * xi)
+    return out
+
+
+def continuous_eval(spike_times: Sequence[np.ndarray], T0: float, T1: float, tau: float,
+                    J: np.ndarray, mu: np.ndarray) -> Dict[str, np.ndarray]:
+    """Continuous-time L_i, dL/dJ_ij and dL/dmu_i of every neuron in one pass
+    over the network's events (Eq. (7)-(8), (10), (12), (14)).
+
+    v holds v_j right after the current event; over the interval that follows
+    (length Delta, xi = e^{-Delta/tau}) neuron i has U_i = mu_i + D_i e^{-s/tau}
+    with D = J v, whose integrals are tau e^{mu_i} [Ei(D_i) - Ei(D_i xi)]
+    (Eq. (10)) and, against v_j e^{-s/tau}, tau e^{mu_i} v_j (e^{D_i} - e^{D_i xi}) / D_i
+    (Eq. (14)).  At an event of neuron i its spike term takes the left limit
+    U_i(t-) = mu_i + J_i . v and the trace v(t-) (Eq. (12)); the event's own
+    jump comes after.  Equal times are taken in (time, neuron) order."""
+    N = len(spike_times)
+    ev = _events(spike_times)
+    times = [T0] + [t for t, _ in ev] + [T1]
+    c = np.exp(mu)
+    v = np.zeros(N)
+    spike = np.zeros(N)
+    dsig = np.zeros((N, N))
+    integ = np.zeros(N)
+    G = np.zeros((N, N))
+    q = np.zeros(N)
+    for k in range(len(times) - 1):
+        if k >= 1:
+            j = ev[k - 1][1]
+            spike[j] += mu[j] + J[j] @ v
+            dsig[j] += v
+            q[j] += 1
+            v[j] += 1.0
+        delta = (times[k + 1] - times[k]) / tau
+        if delta > 0:
+            xi = math.exp(-delta)
+            D = J @ v
+            integ += c * tau * _ei_diff_rows(D, xi)
+            H = np.where(np.abs(D) < 1e-8, (1.0 - xi) + D * (1.0 - xi * xi) / 2.0,
+                         (np.exp(D) - np.exp(D * xi)) / np.where(D == 0.0, 1.0, D))
+            G += np.outer(c * tau * H, v)
+            v = v * xi
+    return dict(ll_rows=spike - integ, ll=float(math.fsum(spike - integ)), gJ=dsig - G, gmu=q - integ)
+
+
 def grid_ll_from_times(spike_times: Sequence[np.ndarray], T: float, dt: float, tau: float,
                        J: np.ndarray, mu: np.ndarray) -> np.ndarray:
     """Bin continuous spike times on a grid of width dt and return the grid L_i."""

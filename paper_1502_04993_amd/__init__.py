@@ -18,6 +18,7 @@ from ._lib import (GLMR_BF16, GLMR_DEVICE, GLMR_FP8, GLMR_FP32, GLMR_FP64, GLMR_
                    GLMR_NOT_CONVERGED, GlmrError, PRECISIONS)
 
 __all__ = ["Context", "Batch", "GlmrError", "glmr_create", "glmr_destroy", "glmr_set_spikes",
+           "glmr_event_slots", "glmr_set_spike_times", "glmr_ei_interval",
            "glmr_set_kernel", "glmr_set_precision", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
            "glmr_fit_defaults", "glmr_status_string", "glmr_last_error", "glmr_query",
            "glmr_batch_create", "glmr_batch_destroy", "glmr_batch_eval", "glmr_batch_get_grad",
@@ -59,10 +60,11 @@ def _check(status: int, ctx=None):
 # ---------------------------------------------------------------- C names
 
 def glmr_create(n_neurons, n_bins, dt, precision="fp32", device=0, stream=None, chunk_bins=0,
-                tile_n=0, trace="auto"):
+                tile_n=0, trace="auto", time_mode="grid"):
     lib = L.load()
     cfg = L.glmr_config(n_neurons, n_bins, dt, chunk_bins, PRECISIONS[precision], device,
-                        ctypes.c_void_p(stream) if stream else None, tile_n, L.TRACE_MODES[trace])
+                        ctypes.c_void_p(stream) if stream else None, tile_n, L.TRACE_MODES[trace],
+                        L.TIME_MODES[time_mode])
     out = ctypes.c_void_p()
     _check(lib.glmr_create(ctypes.byref(cfg), ctypes.byref(out)))
     return out
@@ -82,6 +84,34 @@ def glmr_set_spikes(ctx, bins, neurons):
         raise ValueError("bins and neurons differ in length")
     _sync_torch(bins)
     return _check(L.load().glmr_set_spikes(ctx, pb, pn, n, wb), ctx)
+
+
+def glmr_event_slots(times, T0, T1, max_gap=0.0):
+    """Slot count of the event grid of the (host) spike times."""
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    out = ctypes.c_int64()
+    _check(L.load().glmr_event_slots(ctypes.c_void_p(t.ctypes.data), int(t.shape[0]), float(T0), float(T1),
+                                     float(max_gap), ctypes.byref(out)))
+    return out.value
+
+
+def glmr_set_spike_times(ctx, times, neurons, T0, T1, max_gap=0.0):
+    pt, wt = _ptr(times, np.float64)
+    pn, wn = _ptr(neurons, np.int32)
+    if wt != wn:
+        raise ValueError("times and neurons must both be host or both be device arrays")
+    n = int(times.shape[0])
+    if neurons.shape[0] != n:
+        raise ValueError("times and neurons differ in length")
+    _sync_torch(times)
+    return _check(L.load().glmr_set_spike_times(ctx, pt, pn, n, float(T0), float(T1), float(max_gap), wt), ctx)
+
+
+def glmr_ei_interval(D, delta):
+    """(F, H) of one event-grid interval, by the library's own code on the host."""
+    F, H = ctypes.c_double(), ctypes.c_double()
+    L.load().glmr_ei_interval(float(D), float(delta), ctypes.byref(F), ctypes.byref(H))
+    return F.value, H.value
 
 
 def glmr_set_kernel(ctx, tau):
@@ -230,14 +260,34 @@ def _sync_torch(x):
 # -------------------------------------------------------------- convenience
 
 class Context:
-    """One recording: N neurons, B bins of width dt, one precision."""
+    """One recording: N neurons, B bins of width dt, one precision.  With
+    time_mode="events" the bins are the slots of the event grid (continuous
+    time; see from_events)."""
 
     def __init__(self, n_neurons: int, n_bins: int, dt: float, precision: str = "fp32",
                  device: int = 0, stream=None, chunk_bins: int = 0, tile_n: int = 0,
-                 trace: str = "auto"):
+                 trace: str = "auto", time_mode: str = "grid"):
         self.N, self.B, self.dt, self.precision = int(n_neurons), int(n_bins), float(dt), precision
+        self.time_mode = time_mode
         self._c = glmr_create(self.N, self.B, self.dt, precision, device, stream, chunk_bins, tile_n,
-                              trace)
+                              trace, time_mode)
+
+    @classmethod
+    def from_events(cls, n_neurons: int, times, neurons, T0: float, T1: float, precision: str = "fp64",
+                    max_gap: float = 0.0, device: int = 0, stream=None, chunk_bins: int = 0):
+        """Continuous-time context of spike times (seconds, host arrays sorted by
+        (time, neuron)) on [T0, T1); the spikes are set, the kernel is not."""
+        times = np.ascontiguousarray(times, dtype=np.float64)
+        neurons = np.ascontiguousarray(neurons, dtype=np.int32)
+        slots = glmr_event_slots(times, T0, T1, max_gap)
+        c = cls(n_neurons, slots, (T1 - T0) / slots, precision, device, stream, chunk_bins,
+                time_mode="events")
+        c.T0, c.T1, c.max_gap = float(T0), float(T1), float(max_gap)
+        c.set_spike_times(times, neurons, T0, T1, max_gap)
+        return c
+
+    def set_spike_times(self, times, neurons, T0, T1, max_gap=0.0):
+        return glmr_set_spike_times(self._c, times, neurons, T0, T1, max_gap)
 
     def close(self):
         if self._c is not None and self._c.value:

@@ -27,13 +27,15 @@ GLMR_TRACE_AUTO, GLMR_TRACE_RESIDENT, GLMR_TRACE_RECOMPUTE = 0, 1, 2
 TRACE_MODES = {"auto": GLMR_TRACE_AUTO, "resident": GLMR_TRACE_RESIDENT, "recompute": GLMR_TRACE_RECOMPUTE}
 
 PRECISIONS = {"fp64": GLMR_FP64, "fp32": GLMR_FP32, "bf16": GLMR_BF16, "fp8": GLMR_FP8}
+GLMR_TIME_GRID, GLMR_TIME_EVENTS = 0, 1
+TIME_MODES = {"grid": GLMR_TIME_GRID, "events": GLMR_TIME_EVENTS}
 
 
 class glmr_config(ctypes.Structure):
     _fields_ = [("n_neurons", ctypes.c_int32), ("n_bins", ctypes.c_int64), ("dt", ctypes.c_double),
                 ("chunk_bins", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("tile_n", ctypes.c_int32),
-                ("trace", ctypes.c_int32)]
+                ("trace", ctypes.c_int32), ("time_mode", ctypes.c_int32)]
 
 
 class glmr_fit_opts(ctypes.Structure):
@@ -57,6 +59,11 @@ SIGNATURES = {
     "glmr_create": (ctypes.c_int, [ctypes.POINTER(glmr_config), ctypes.POINTER(_vp)]),
     "glmr_destroy": (None, [_vp]),
     "glmr_set_spikes": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32]),
+    "glmr_event_slots": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]),
+    "glmr_set_spike_times": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_int32]),
+    "glmr_ei_interval": (None, [ctypes.c_double, ctypes.c_double, _dp, _dp]),
     "glmr_set_kernel": (ctypes.c_int, [_vp, ctypes.c_double]),
     "glmr_set_precision": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "glmr_set_params": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),

@@ -17,6 +17,9 @@
 //   Gp[k][i][j]     per split partial of sum_t W[i][t] x_j[t]
 // Inside a subtile the trace is evaluated in closed form:
 //   x_j[64 s + m] = a^m * (C[s][j] + sum_{b < m, spike of j in bin 64 s + b} a^-(b+1))
+// On the event grid of the continuous-time likelihood the bins are the slots
+// between network events and a^m, a^-(b+1), a^64 become the per-slot tables
+// of EvSlots (events.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,6 +46,16 @@ struct Tables {
   float ainv32[64];
 };
 
+// Per-slot tables of the event grid for the current tau (null pointers on the
+// regular grid).  k is a slot, k0 the first slot of its subtile.
+struct EvSlots {
+  const double* pw;        // [NS*64] e^{-(t_k - t_k0)/tau}
+  const double* ainv;      // [NS*64] e^{(t_{k+1} - t_k0)/tau}
+  const double* left;      // [NS*64] e^{-(t_{k+1} - t_k0)/tau}
+  const double* delta;     // [NS*64] (t_{k+1} - t_k)/tau
+  const double* asub;      // [NS]    e^{-(t_{k0+64} - t_k0)/tau}
+};
+
 // ------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns hipSuccess or the launch error.
 struct IngestBufs {
@@ -67,6 +80,37 @@ hipError_t launch_ingest_sort(const IngestBufs& b, hipStream_t st);
 hipError_t launch_ingest_masks(const IngestBufs& b, uint64_t* masks, int planes, int64_t Np,
                                hipStream_t st);
 
+// Event grid layout (events.hip) ---------------------------------------------
+struct EvLayoutArgs {
+  int64_t n;                  // events
+  const double* times;        // [n] sorted by (time, neuron)
+  const int32_t* neu;         // [n]
+  int32_t N;
+  double T0, T1, max_gap;
+  int64_t NS;                 // subtiles of the slot grid
+  unsigned long long* bad;    // [2]: count, first bad index
+  int64_t* cnt;               // [n] slots taken by event k (with the spike-free ones before it)
+  int64_t* slot;              // [n] slot of event k
+  int64_t* scan_tmp;          // [ev_scan_tmp_len(n)]
+  int64_t* bins;              // [n] pseudo-bin of event k (slot - 1)
+  double* tslot;              // [NS*64 + 1] slot start times
+};
+int64_t ev_scan_tmp_len(int64_t n);
+hipError_t launch_ev_check(const EvLayoutArgs& a, hipStream_t st);
+hipError_t launch_ev_layout(const EvLayoutArgs& a, hipStream_t st);
+hipError_t launch_ev_place(const EvLayoutArgs& a, int64_t s_last, double t_last, int64_t n_tail,
+                           hipStream_t st);
+double ev_resolve_max_gap(int64_t n, double T0, double T1, double max_gap);
+int64_t ev_host_slots_of_gap(double gap, double max_gap);
+struct EvTableArgs {
+  const double* tslot;
+  double tau;
+  int64_t NS;
+  double *pw, *ainv, *left, *delta, *asub;
+  unsigned long long* maxspan;  // max over subtiles of the span / tau (double bits), zero on entry
+};
+hipError_t launch_ev_tables(const EvTableArgs& a, hipStream_t st);
+
 struct CarryArgs {
   const uint64_t* masks;
   int planes;
@@ -81,6 +125,7 @@ struct CarryArgs {
   double* seg;             // [nseg][Np][2] scratch
   double* segin;           // [nseg][Np][2] scratch
   int64_t G;               // subtiles per segment (64)
+  EvSlots ev;              // event grid (ev.pw != null): per-slot decays, no y
 };
 hipError_t launch_carries(const CarryArgs& c, hipStream_t st);
 
@@ -98,6 +143,7 @@ struct SpikeTermArgs {
   double* part;            // [splits][Np][Np] (and a second block for Y)
   double* dsig;            // [Np][Np]
   double* dsigY;           // [Np][Np] or null
+  EvSlots ev;              // event grid: left limits at the events
 };
 hipError_t launch_spike_term(const SpikeTermArgs& a, hipStream_t st);
 
@@ -122,6 +168,7 @@ struct Gemm1Args {
   const float* jscale;
   int mode;                // 0: U -> W, 1: V = Y J^T -> sum W V
   int w_plain;             // mode 1: W holds exp(V) (resident trace) instead of exp(V) a^m
+  EvSlots ev;              // event grid (mode 0 only): W = H(D, delta) pw, row sums of F(D, delta)
 };
 hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st);
 
@@ -139,6 +186,7 @@ struct Gemm2Args {
   void* Gp;                // [n_splits][Np][Np] float (double for F64)
   const float* xscale;
   const float* wscale;
+  EvSlots ev;              // event grid
 };
 hipError_t launch_gemm2(int prec, int tile, const Gemm2Args& a, hipStream_t st);
 

@@ -1,0 +1,136 @@
+// Special functions of the continuous-time likelihood on the event grid
+// (Sec. 2.3: between two consecutive network events the potential relaxes as
+// U = mu + D e^{-s}, s = (t - t_k)/tau, so each interval's integrals have
+// closed forms):
+//
+//   F(D, delta) = int_0^delta exp(D e^{-s}) ds = Ei(D) - Ei(D xi)      (Eq. (10))
+//   H(D, delta) = int_0^delta e^{-s} exp(D e^{-s}) ds = (e^D - e^{D xi}) / D  (Eq. (14))
+//
+// with xi = e^{-delta}; the interval's intensity integral is tau e^{mu} F and
+// its weight on the trace integral tau e^{mu} H.  Both are written for FP64
+// and compiled for host and device, so the kernels' arithmetic can be checked
+// on the CPU against a library exponential integral.
+//
+// F by branch (every branch loses at most a small constant factor of FP64
+// precision):
+//  * |D| <= 2: the series of Ei difference term by term,
+//      F = delta + (1 - xi) sum_{n>=1} D^n S_n / (n n!),  S_n = 1 + xi + ... + xi^{n-1},
+//    which keeps 1 - xi^n = (1 - xi) S_n exact for short intervals (no
+//    cancellation between Ei(D) and Ei(D xi)); 26 terms.
+//  * |D| > 2 and |D| (1 - xi) <= 1: the two Ei values nearly cancel; integrate
+//    e^u / u over u in [D xi, D] (length <= 1, at least 1 away from the pole
+//    at 0) by 16-point Gauss-Legendre.
+//  * otherwise Ei(D) - Ei(D xi) directly.
+// Ei(x): the power series gamma + ln|x| + sum x^n/(n n!) for -1 <= x <= 40
+// (Abramowitz & Stegun 5.1.10), the continued fraction of E1 for x < -1
+// (A&S 5.1.22, evaluated by the modified Lentz method), the asymptotic series
+// e^x/x sum k!/x^k for x > 40 (A&S 5.1.51), truncated at its smallest term.
+#pragma once
+
+#include <math.h>
+
+#if defined(__HIPCC__)
+#define GLMR_HD __host__ __device__
+#else
+#define GLMR_HD
+#endif
+
+namespace glmr_ev {
+
+constexpr double kEulerGamma = 0.57721566490153286061;
+
+GLMR_HD inline double ei(double x) {
+  if (x == 0.0) return -INFINITY;
+  if (x < -1.0) {
+    const double z = -x;
+    // E1(z) = e^{-z} / (z + 1 - 1/(z + 3 - 4/(z + 5 - 9/(z + 7 - ...))))
+    const double tiny = 1e-300;
+    double b = z + 1.0, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i < 500; ++i) {
+      const double an = -(double)i * (double)i;
+      b += 2.0;
+      d = an * d + b;
+      if (fabs(d) < tiny) d = tiny;
+      c = b + an / c;
+      if (fabs(c) < tiny) c = tiny;
+      d = 1.0 / d;
+      const double del = c * d;
+      h *= del;
+      if (fabs(del - 1.0) < 1e-17) break;
+    }
+    return -h * exp(-z);
+  }
+  if (x <= 40.0) {
+    double term = 1.0, sum = 0.0;
+    for (int n = 1; n < 400; ++n) {
+      term *= x / (double)n;  // x^n / n!
+      const double t = term / (double)n;
+      sum += t;
+      if (fabs(t) <= 1e-17 * fabs(sum)) break;
+    }
+    return kEulerGamma + log(fabs(x)) + sum;
+  }
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    const double next = term * (double)k / x;
+    if (next > term || next < 1e-18) break;
+    term = next;
+    sum += term;
+  }
+  return exp(x) / x * sum;
+}
+
+// 16-point Gauss-Legendre nodes (positive half) and weights on [-1, 1]
+GLMR_HD inline double gl16_node(int k) {
+  const double v[8] = {9.50125098376374544e-02, 2.81603550779258915e-01, 4.58016777657227370e-01,
+                       6.17876244402643771e-01, 7.55404408355002999e-01, 8.65631202387831755e-01,
+                       9.44575023073232600e-01, 9.89400934991649939e-01};
+  return v[k];
+}
+GLMR_HD inline double gl16_weight(int k) {
+  const double v[8] = {1.89450610455068585e-01, 1.82603415044923612e-01, 1.69156519395002619e-01,
+                       1.49595988816576764e-01, 1.24628971255534030e-01, 9.51585116824925914e-02,
+                       6.22535239386477063e-02, 2.71524594117540374e-02};
+  return v[k];
+}
+
+// F and H of one interval of length delta (in units of tau) that starts with
+// potential offset D; delta = 0 gives 0 for both.
+GLMR_HD inline void interval(double D, double delta, double* F, double* H) {
+  if (!(delta > 0.0)) {
+    *F = 0.0;
+    *H = 0.0;
+    return;
+  }
+  const double e1 = -expm1(-delta);  // 1 - xi, exact for short intervals
+  const double xi = exp(-delta);
+  const double y = D * e1;
+  *H = exp(D * xi) * e1 * (y == 0.0 ? 1.0 : expm1(y) / y);
+  const double ad = fabs(D);
+  if (ad <= 2.0) {
+    double p = 1.0, S = 1.0, acc = 0.0;
+#pragma unroll
+    for (int n = 1; n <= 26; ++n) {
+      p *= D * (1.0 / (double)n);            // D^n / n!
+      acc += p * (1.0 / (double)n) * S;      // D^n S_n / (n n!)
+      S = 1.0 + xi * S;                      // S_{n+1}
+    }
+    *F = delta + e1 * acc;
+    return;
+  }
+  if (fabs(y) <= 1.0) {
+    const double half = 0.5 * y, mid = D - half;  // u in [D xi, D] = mid -/+ half
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double x = gl16_node(k) * half;
+      const double u1 = mid + x, u2 = mid - x;
+      acc += gl16_weight(k) * (exp(u1) / u1 + exp(u2) / u2);
+    }
+    *F = half * acc;
+    return;
+  }
+  *F = ei(D) - ei(D * xi);
+}
+
+}  // namespace glmr_ev

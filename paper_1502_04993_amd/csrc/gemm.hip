@@ -38,10 +38,21 @@
 // the bin and the column only, so both contractions see the identical rounded
 // trace.  Rounded values are unbiased and their errors average out over t.
 //
+// Event grid (continuous time, FP64 and FP32 modes): the bins are the slots
+// between network events, a^m and a^-(b+1) come from the per-slot tables
+// (pw, ainv relative to the subtile's first slot), and kernel U's epilogue
+// takes the closed forms of the interval integrals instead of exp: with
+// D = pw acc the potential offset at the slot start,
+//   row sums of F(D, delta) = Ei(D) - Ei(D xi)    (Eq. (10)),
+//   W' = H(D, delta) pw,  H = (e^D - e^{D xi}) / D (Eq. (14)),
+// so kernel G contracts W' with z into sum_k H x_j, the trace integral of
+// Eq. (12) up to the factor tau e^{mu_i}.
+//
 // Pipelining: the J (or W) tile of the next step is fetched into registers
 // and the trace tile of the next step is rebuilt into the second LDS buffer
 // while the MFMAs of the current step run; one barrier per step.
 #include "common.h"
+#include "evfun.h"
 
 namespace {
 
@@ -162,22 +173,23 @@ __device__ inline int64_t xcd_logical(int64_t bid, int64_t nblk) {
 //   z = x / a^m = c + sum_{b < m, bit b of the masks} a^-(b+1)
 // c (the carry) and mk (plane-0 mask) are wave-uniform; further planes
 // (several spikes in one bin) are read here.
-template <typename T>
-__device__ inline T z_from(T c, uint64_t mk, int m, const Tables* tab,
+// On the event grid (EV) a^-(b+1) is the per-slot table eva[b] of subtile s.
+template <typename T, bool EV>
+__device__ inline T z_from(T c, uint64_t mk, int m, const Tables* tab, const double* __restrict__ eva,
                            const uint64_t* __restrict__ masks, int planes, int64_t NS,
                            int64_t Np, int64_t s, int64_t j) {
   T run = c;
   while (mk) {
     const int b = __builtin_ctzll(mk);
     mk &= mk - 1;
-    if (b < m) run += tab_ainv<T>(tab, b);
+    if (b < m) run += EV ? (T)eva[b] : tab_ainv<T>(tab, b);
   }
   for (int p = 1; p < planes; ++p) {
     uint64_t mp = masks[((int64_t)p * NS + s) * Np + j];
     while (mp) {
       const int b = __builtin_ctzll(mp);
       mp &= mp - 1;
-      if (b < m) run += tab_ainv<T>(tab, b);
+      if (b < m) run += EV ? (T)eva[b] : tab_ainv<T>(tab, b);
     }
   }
   return run;
@@ -204,7 +216,7 @@ __device__ inline T zy_at(const CT* __restrict__ C, const CT* __restrict__ CY,
 constexpr int PAD = 16;  // bytes of padding per LDS row
 
 // ---------------------------------------------------------------- kernel U/V
-template <int PREC, int BI, int BT, int WGM, int WGN, int DB>
+template <int PREC, int BI, int BT, int WGM, int WGN, int DB, bool EV>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
   using P = Pol<PREC>;
   using in_t = typename P::in_t;
@@ -297,7 +309,8 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
             const int64_t j = jg + e;
             T z = cz[e];
             if (mz[e] != 0 || g.planes > 1)
-              z = z_from<T>(cz[e], mz[e], lane, g.tab, g.masks, g.planes, g.NS, g.Np, s, j);
+              z = z_from<T, EV>(cz[e], mz[e], lane, g.tab, EV ? g.ev.ainv + s * 64 : nullptr, g.masks,
+                                g.planes, g.NS, g.Np, s, j);
             v[e] = P::cvt(z, rt + (uint32_t)j * SR_J);
           }
         } else {
@@ -370,8 +383,21 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
 #pragma unroll
     for (int b = 0; b < WNB; ++b) {
       const int tl = wn * WN + b * P::MB + P::col(lane);
-      const T pw = tab_pw<T>(g.tab, tl & 63);
       const bool valid = (tt0 + tl) < g.B;
+      if constexpr (EV) {
+        const double pwd = g.ev.pw[tt0 + tl];
+        const double delta = g.ev.delta[tt0 + tl];
+#pragma unroll
+        for (int r = 0; r < P::NACC; ++r) {
+          const int il = wm * WM + a * P::MB + P::row(r, lane);
+          double F = 0.0, H = 0.0;
+          if (valid) glmr_ev::interval(pwd * (double)acc[a][b][r], delta, &F, &H);
+          W[(i0 + il) * g.L + (tl0 + tl)] = (w_t)(H * pwd);
+          rs[r] += F;
+        }
+        continue;
+      }
+      const T pw = tab_pw<T>(g.tab, tl & 63);
 #pragma unroll
       for (int r = 0; r < P::NACC; ++r) {
         const int il = wm * WM + a * P::MB + P::row(r, lane);
@@ -406,7 +432,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
 }
 
 // ---------------------------------------------------------------- kernel G
-template <int PREC, int BI, int BJ, int WGM, int WGN, int DB>
+template <int PREC, int BI, int BJ, int WGM, int WGN, int DB, bool EV>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
   using P = Pol<PREC>;
   using in_t = typename P::in_t;
@@ -493,7 +519,8 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
         const int64_t j = jg + e;
         T z = cz[e];
         if (mz[e] != 0 || g.planes > 1)
-          z = z_from<T>(cz[e], mz[e], lane, g.tab, g.masks, g.planes, g.NS, g.Np, s, j);
+          z = z_from<T, EV>(cz[e], mz[e], lane, g.tab, EV ? g.ev.ainv + s * 64 : nullptr, g.masks,
+                            g.planes, g.NS, g.Np, s, j);
         *(in_t*)(Bs + (wave * CPW + cgi + e) * ROWB + lane * sizeof(in_t)) =
             P::cvt(z, rt + (uint32_t)j * SR_J);
       }
@@ -559,13 +586,13 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
       }
 }
 
-template <int PREC, int BI, int BT, int WGM, int WGN, int DB>
+template <int PREC, int BI, int BT, int WGM, int WGN, int DB, bool EV = false>
 hipError_t run_gemm1(const Gemm1Args& a, hipStream_t st) {
   using P = Pol<PREC>;
   constexpr int BK = 128 / sizeof(typename P::in_t);
   constexpr int ROWB = BK * sizeof(typename P::in_t) + PAD;
   size_t lds = (size_t)DB * (BI + BT) * ROWB + (size_t)WGN * BI * sizeof(double);
-  auto kern = k_gemm1<PREC, BI, BT, WGM, WGN, DB>;
+  auto kern = k_gemm1<PREC, BI, BT, WGM, WGN, DB, EV>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int64_t nblk = (int64_t)a.n_itiles * a.n_ttiles;
@@ -573,12 +600,12 @@ hipError_t run_gemm1(const Gemm1Args& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int PREC, int BI, int BJ, int WGM, int WGN, int DB>
+template <int PREC, int BI, int BJ, int WGM, int WGN, int DB, bool EV = false>
 hipError_t run_gemm2(const Gemm2Args& a, hipStream_t st) {
   using P = Pol<PREC>;
   constexpr int ROWB = 64 * sizeof(typename P::in_t) + PAD;
   size_t lds = (size_t)DB * (BI + BJ) * ROWB;
-  auto kern = k_gemm2<PREC, BI, BJ, WGM, WGN, DB>;
+  auto kern = k_gemm2<PREC, BI, BJ, WGM, WGN, DB, EV>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int64_t nblk = (int64_t)a.n_splits * a.n_itiles * a.n_jtiles;
@@ -591,6 +618,12 @@ hipError_t run_gemm2(const Gemm2Args& a, hipStream_t st) {
 // Tile shapes: BI x BT for kernel U/V, BI x BJ for kernel G.  `tile` is the
 // neuron tile of the context (the padding unit of N).
 hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st) {
+  if (a.ev.pw) {  // event grid: FP64 and FP32 modes, likelihood kernel only
+    if (a.mode != 0) return hipErrorInvalidValue;
+    if (prec == PREC_F64) return run_gemm1<PREC_F64, 128, 128, 2, 2, 2, true>(a, st);
+    if (prec == PREC_F32) return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2, true>(a, st);
+    return hipErrorInvalidValue;
+  }
   switch (prec) {
     case PREC_F64: return run_gemm1<PREC_F64, 128, 128, 2, 2, 2>(a, st);
     case PREC_F32: return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2>(a, st);
@@ -602,6 +635,11 @@ hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st) 
 }
 
 hipError_t launch_gemm2(int prec, int tile, const Gemm2Args& a, hipStream_t st) {
+  if (a.ev.pw) {
+    if (prec == PREC_F64) return run_gemm2<PREC_F64, 128, 128, 2, 2, 1, true>(a, st);
+    if (prec == PREC_F32) return run_gemm2<PREC_F32, 128, 128, 2, 4, 2, true>(a, st);
+    return hipErrorInvalidValue;
+  }
   switch (prec) {
     case PREC_F64: return run_gemm2<PREC_F64, 128, 128, 2, 2, 1>(a, st);
     case PREC_F32: return run_gemm2<PREC_F32, 128, 128, 2, 4, 2>(a, st);

@@ -76,6 +76,13 @@ struct glmr_ctx {
   std::vector<int64_t> q_host;
   bool all_spiking = false;
 
+  // event grid (continuous time): slot start times and per-slot tables
+  bool evm = false;
+  double T0 = 0, T1 = 0, max_gap = 0;
+  double* tslot = nullptr;  // [NS*64 + 1]
+  double* evtab = nullptr;  // [4 * NS*64 + NS]: pw, ainv, left, delta, asub
+  double max_span = 0;      // largest 64-slot span / tau of the current tables
+
   // kernel
   bool have_kernel = false, have_y = false, keep_y = false;
   double tau = 0, a = 0;
@@ -242,7 +249,53 @@ size_t jc_bytes(int prec) { return prec == PREC_F32 ? 8 : in_bytes(prec); }
 
 // ---------------------------------------------------------------- kernel caches
 // Whether the BF16 trace is kept in HBM (see glmr_trace_mode).
+EvSlots ev_slots(const glmr_ctx* c) {
+  EvSlots e{};
+  if (!c->evm || !c->evtab) return e;
+  const int64_t n = c->NS * 64;
+  e.pw = c->evtab;
+  e.ainv = c->evtab + n;
+  e.left = c->evtab + 2 * n;
+  e.delta = c->evtab + 3 * n;
+  e.asub = c->evtab + 4 * n;
+  return e;
+}
+
+// Per-slot tables of the event grid for the current tau.  A run of 64 slots
+// longer than kMaxSpan tau would overflow e^{(t - t_k0)/tau}.
+constexpr double kMaxSpan = 600.0;
+glmr_status build_ev_tables(glmr_ctx* c) {
+  const int64_t n = c->NS * 64;
+  if (!c->evtab) TRY(dalloc(c, c->evtab, (size_t)(4 * n + c->NS)));
+  unsigned long long* ms = nullptr;
+  TRY(dalloc(c, ms, 1));
+  HIPCHK(c, hipMemsetAsync(ms, 0, sizeof(unsigned long long), c->st));
+  EvTableArgs ta{};
+  ta.tslot = c->tslot;
+  ta.tau = c->tau;
+  ta.NS = c->NS;
+  ta.pw = c->evtab;
+  ta.ainv = c->evtab + n;
+  ta.left = c->evtab + 2 * n;
+  ta.delta = c->evtab + 3 * n;
+  ta.asub = c->evtab + 4 * n;
+  ta.maxspan = ms;
+  HIPCHK(c, launch_ev_tables(ta, c->st));
+  unsigned long long h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, ms, sizeof h, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  dfree(c, ms);
+  double span = 0;
+  std::memcpy(&span, &h, sizeof span);
+  c->max_span = span;
+  if (!(span <= kMaxSpan))
+    return fail(c, GLMR_EINVAL, "64 consecutive slots span %.1f tau (at most %.0f): pass a smaller max_gap",
+                span, kMaxSpan);
+  return GLMR_OK;
+}
+
 bool want_resident(glmr_ctx* c) {
+  if (c->evm) return false;
   if (c->prec == PREC_FP8) return true;  // FP8 contractions exist only on the resident trace
   if (c->prec != PREC_BF16 || c->cfg.trace == GLMR_TRACE_RECOMPUTE) return false;
   if (c->cfg.trace == GLMR_TRACE_RESIDENT) return true;
@@ -301,6 +354,11 @@ glmr_status build_resident_trace(glmr_ctx* c) {
 
 glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
   const double dt = c->dt, tau = c->tau;
+  c->have_kernel = false;
+  if (c->evm) {
+    want_y = false;
+    TRY(build_ev_tables(c));
+  }
   Tables h{};
   for (int m = 0; m < 64; ++m) {
     h.pw[m] = std::exp(-(double)m * dt / tau);
@@ -339,6 +397,7 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
   ca.seg = seg;
   ca.segin = segin;
   ca.G = G;
+  ca.ev = ev_slots(c);
   {
     ProfScope ps(c, K_CARRY);
     HIPCHK(c, launch_carries(ca, c->st));
@@ -371,6 +430,7 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
   sa.part = part;
   sa.dsig = c->dsig;
   sa.dsigY = want_y ? c->dsigY : nullptr;
+  sa.ev = ev_slots(c);
   {
     ProfScope ps(c, K_SPIKE);
     HIPCHK(c, launch_spike_term(sa, c->st));
@@ -522,6 +582,7 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
     g1.W = c->W;
     g1.rowpart = c->rowpart;
     g1.mode = 0;
+    g1.ev = ev_slots(c);
     if (c->resident) {
       ProfScope ps(c, K_U);
       HIPCHK(c, launch_u_chunk(c, c->res_shape_u, t0, Lc));
@@ -553,6 +614,7 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       g2.n_itiles = (int)(Np / c->bi2);
       g2.n_jtiles = (int)(Np / c->bj2);
       g2.Gp = c->Gp;
+      g2.ev = ev_slots(c);
       if (c->resident) {
         ProfScope ps(c, K_G);
         HIPCHK(c, launch_g_chunk(c, c->res_shape_g, t0, Lc, &g2.n_splits));
@@ -578,7 +640,7 @@ glmr_status eval_finish(glmr_ctx* c, bool want_grad, bool want_tau) {
   AssembleArgs aa{};
   aa.N = c->N;
   aa.Np = Np;
-  aa.dt = c->dt;
+  aa.dt = c->evm ? c->tau : c->dt;  // the event grid's integrals are in units of tau
   aa.q = c->q;
   aa.mu = c->mu;
   aa.Jr = c->Jr;
@@ -1354,6 +1416,9 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
     return GLMR_EINVAL;
   if (cfg->precision == GLMR_FP8 && cfg->trace == GLMR_TRACE_RECOMPUTE)
     return GLMR_EINVAL;  // FP8 contractions exist only on the resident trace
+  if (cfg->time_mode != GLMR_TIME_GRID && cfg->time_mode != GLMR_TIME_EVENTS) return GLMR_EINVAL;
+  if (cfg->time_mode == GLMR_TIME_EVENTS && cfg->precision != GLMR_FP64 && cfg->precision != GLMR_FP32)
+    return GLMR_EINVAL;  // the event grid's contractions run in FP64 or FP32
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -1366,6 +1431,7 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
   c->N = cfg->n_neurons;
   c->B = cfg->n_bins;
   c->dt = cfg->dt;
+  c->evm = cfg->time_mode == GLMR_TIME_EVENTS;
   c->prec = cfg->precision;
   int tile = cfg->tile_n;
   if (tile == 0) tile = ((c->prec == GLMR_BF16 || c->prec == GLMR_FP8) && c->N <= 384) ? 128 : 256;
@@ -1403,14 +1469,11 @@ void glmr_destroy(glmr_ctx* c) {
   delete c;
 }
 
-glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neuron, int64_t n,
-                            int32_t where) {
-  if (!c) return GLMR_EINVAL;
-  c->err.clear();
-  if (n < 0 || n >= (1ll << 31)) return fail(c, GLMR_EINVAL, "n_spikes must be in [0, 2^31)");
-  if (n > 0 && (!bin || !neuron)) return fail(c, GLMR_EINVAL, "null spike arrays");
-  if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
-  HIPCHK(c, hipSetDevice(c->cfg.device));
+namespace {
+
+// Spike ingest from device arrays of (bin, neuron) pairs (spike layout of the
+// regular grid, or the pseudo-bins of the event grid).
+glmr_status ingest_pairs(glmr_ctx* c, const int64_t* bin, const int32_t* neuron, int64_t n) {
   ProfScope ps(c, K_INGEST);
   const int64_t nseg = c->NS * c->NIB;
   IngestBufs b{};
@@ -1419,19 +1482,8 @@ glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neur
   b.B = c->B;
   b.NS = c->NS;
   b.NIB = c->NIB;
-  int64_t* dbin = nullptr;
-  int32_t* dneu = nullptr;
-  if (where == GLMR_HOST && n > 0) {
-    TRY(dalloc(c, dbin, (size_t)n));
-    TRY(dalloc(c, dneu, (size_t)n));
-    HIPCHK(c, hipMemcpyAsync(dbin, bin, n * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
-    HIPCHK(c, hipMemcpyAsync(dneu, neuron, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-    b.bin = dbin;
-    b.neu = dneu;
-  } else {
-    b.bin = bin;
-    b.neu = neuron;
-  }
+  b.bin = bin;
+  b.neu = neuron;
   unsigned long long* bad = nullptr;
   int32_t *cnt = nullptr, *cursor = nullptr, *maxmult = nullptr;
   int64_t* scan_tmp = nullptr;
@@ -1440,9 +1492,10 @@ glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neur
   TRY(dalloc(c, cursor, (size_t)nseg + 1));
   TRY(dalloc(c, maxmult, 1));
   TRY(dalloc(c, scan_tmp, (size_t)ingest_scan_tmp_len(nseg)));
-  TRY(dalloc(c, c->seg_off, (size_t)nseg + 1));
+  if (!c->seg_off) TRY(dalloc(c, c->seg_off, (size_t)nseg + 1));
+  dfree(c, c->seg_ent);
   TRY(dalloc(c, c->seg_ent, (size_t)std::max<int64_t>(n, 1)));
-  TRY(dalloc(c, c->q, (size_t)c->Np));
+  if (!c->q) TRY(dalloc(c, c->q, (size_t)c->Np));
   HIPCHK(c, hipMemsetAsync(bad, 0, sizeof(unsigned long long), c->st));
   HIPCHK(c, hipMemsetAsync(bad + 1, 0xff, sizeof(unsigned long long), c->st));
   HIPCHK(c, hipMemsetAsync(cnt, 0, (nseg + 1) * sizeof(int32_t), c->st));
@@ -1463,11 +1516,7 @@ glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neur
   if (n > 0) HIPCHK(c, launch_ingest_count(b, c->st));
   HIPCHK(c, hipMemcpyAsync(hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  if (hbad[0] > 0) {
-    dfree(c, dbin);
-    dfree(c, dneu);
-    return fail(c, GLMR_EINVAL, "%llu spikes out of range; first at index %llu", hbad[0], hbad[1]);
-  }
+  if (hbad[0] > 0) return fail(c, GLMR_EINVAL, "%llu spikes out of range; first at index %llu", hbad[0], hbad[1]);
   HIPCHK(c, launch_ingest_scan(b, c->st));
   if (n > 0) HIPCHK(c, launch_ingest_scatter(b, c->st));
   HIPCHK(c, launch_ingest_sort(b, c->st));
@@ -1476,14 +1525,13 @@ glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neur
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->planes = std::max(1, (int)hmax);
   const size_t nm = (size_t)c->planes * c->NS * c->Np;
+  dfree(c, c->masks);
   TRY(dalloc(c, c->masks, nm));
   HIPCHK(c, hipMemsetAsync(c->masks, 0, nm * sizeof(uint64_t), c->st));
   HIPCHK(c, launch_ingest_masks(b, c->masks, c->planes, c->Np, c->st));
   c->q_host.assign(c->Np, 0);
   HIPCHK(c, hipMemcpyAsync(c->q_host.data(), c->q, c->Np * sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  dfree(c, dbin);
-  dfree(c, dneu);
   dfree(c, bad);
   dfree(c, cnt);
   dfree(c, cursor);
@@ -1499,11 +1547,145 @@ glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neur
   return GLMR_OK;
 }
 
+}  // namespace
+
+glmr_status glmr_set_spikes(glmr_ctx* c, const int64_t* bin, const int32_t* neuron, int64_t n,
+                            int32_t where) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (c->evm) return fail(c, GLMR_ESTATE, "an event-grid context takes glmr_set_spike_times");
+  if (n < 0 || n >= (1ll << 31)) return fail(c, GLMR_EINVAL, "n_spikes must be in [0, 2^31)");
+  if (n > 0 && (!bin || !neuron)) return fail(c, GLMR_EINVAL, "null spike arrays");
+  if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  int64_t* dbin = nullptr;
+  int32_t* dneu = nullptr;
+  if (where == GLMR_HOST && n > 0) {
+    TRY(dalloc(c, dbin, (size_t)n));
+    TRY(dalloc(c, dneu, (size_t)n));
+    HIPCHK(c, hipMemcpyAsync(dbin, bin, n * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(dneu, neuron, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    bin = dbin;
+    neuron = dneu;
+  }
+  const glmr_status st = ingest_pairs(c, bin, neuron, n);
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  dfree(c, dbin);
+  dfree(c, dneu);
+  return st;
+}
+
+glmr_status glmr_set_spike_times(glmr_ctx* c, const double* times, const int32_t* neuron, int64_t n,
+                                 double T0, double T1, double max_gap, int32_t where) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (!c->evm) return fail(c, GLMR_ESTATE, "a regular-grid context takes glmr_set_spikes");
+  if (n < 0 || n >= (1ll << 31)) return fail(c, GLMR_EINVAL, "n_events must be in [0, 2^31)");
+  if (n > 0 && (!times || !neuron)) return fail(c, GLMR_EINVAL, "null event arrays");
+  if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
+  if (!std::isfinite(T0) || !std::isfinite(T1) || !(T1 > T0)) return fail(c, GLMR_EINVAL, "need T0 < T1");
+  if (std::isnan(max_gap) || std::isinf(max_gap)) return fail(c, GLMR_EINVAL, "bad max_gap");
+  const double mg = ev_resolve_max_gap(n, T0, T1, max_gap);
+  if (!(mg > 0) || !((T1 - T0) / mg <= 1e9)) return fail(c, GLMR_EINVAL, "max_gap too small");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  c->have_spikes = false;
+  c->have_kernel = false;
+  double* dt_ = nullptr;
+  int32_t* dn_ = nullptr;
+  if (where == GLMR_HOST && n > 0) {
+    TRY(dalloc(c, dt_, (size_t)n));
+    TRY(dalloc(c, dn_, (size_t)n));
+    HIPCHK(c, hipMemcpyAsync(dt_, times, n * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(dn_, neuron, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    times = dt_;
+    neuron = dn_;
+  }
+  EvLayoutArgs a{};
+  a.n = n;
+  a.times = times;
+  a.neu = neuron;
+  a.N = c->N;
+  a.T0 = T0;
+  a.T1 = T1;
+  a.max_gap = mg;
+  a.NS = c->NS;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(c->st);
+    dfree(c, dt_);
+    dfree(c, dn_);
+    dfree(c, a.bad);
+    dfree(c, a.cnt);
+    dfree(c, a.slot);
+    dfree(c, a.scan_tmp);
+    dfree(c, a.bins);
+  };
+  glmr_status st = GLMR_OK;
+  do {
+    if ((st = dalloc(c, a.bad, 2)) != GLMR_OK) break;
+    if ((st = dalloc(c, a.cnt, nn)) != GLMR_OK) break;
+    if ((st = dalloc(c, a.slot, nn)) != GLMR_OK) break;
+    if ((st = dalloc(c, a.scan_tmp, (size_t)ev_scan_tmp_len(n))) != GLMR_OK) break;
+    if ((st = dalloc(c, a.bins, nn)) != GLMR_OK) break;
+    unsigned long long hbad[2] = {0, 0};
+    if (hipMemsetAsync(a.bad, 0, sizeof(unsigned long long), c->st) != hipSuccess ||
+        hipMemsetAsync(a.bad + 1, 0xff, sizeof(unsigned long long), c->st) != hipSuccess ||
+        (n > 0 && launch_ev_check(a, c->st) != hipSuccess) ||
+        hipMemcpyAsync(hbad, a.bad, sizeof hbad, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess) {
+      st = fail(c, GLMR_EDEVICE, "event check: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    if (hbad[0] > 0) {
+      st = fail(c, GLMR_EINVAL,
+                "%llu events out of [T0, T1), of neuron range, or not in strictly increasing (time, neuron) "
+                "order; first at index %llu", hbad[0], hbad[1]);
+      break;
+    }
+    int64_t s_last = 0;
+    double t_last = T0;
+    if (launch_ev_layout(a, c->st) != hipSuccess ||
+        (n > 0 && hipMemcpyAsync(&s_last, a.slot + (n - 1), sizeof s_last, hipMemcpyDeviceToHost, c->st) != hipSuccess) ||
+        (n > 0 && hipMemcpyAsync(&t_last, times + (n - 1), sizeof t_last, hipMemcpyDeviceToHost, c->st) != hipSuccess) ||
+        hipStreamSynchronize(c->st) != hipSuccess) {
+      st = fail(c, GLMR_EDEVICE, "event layout: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    const int64_t n_tail = ev_host_slots_of_gap(T1 - t_last, mg);
+    const int64_t M = s_last + n_tail;
+    if (M != c->B) {
+      st = fail(c, GLMR_EINVAL, "the events make %lld slots; the context has n_bins = %lld (glmr_event_slots)",
+                (long long)M, (long long)c->B);
+      break;
+    }
+    if (!c->tslot && (st = dalloc(c, c->tslot, (size_t)(c->NS * 64 + 1))) != GLMR_OK) break;
+    a.tslot = c->tslot;
+    if (launch_ev_place(a, s_last, t_last, n_tail, c->st) != hipSuccess) {
+      st = fail(c, GLMR_EDEVICE, "event placement: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    c->T0 = T0;
+    c->T1 = T1;
+    c->max_gap = mg;
+    st = ingest_pairs(c, a.bins, neuron, n);
+  } while (false);
+  cleanup();
+  return st;
+}
+
+namespace {
+glmr_status reject_event_grid_precision(glmr_ctx* c, int prec) {
+  if (c->evm && prec != GLMR_FP64 && prec != GLMR_FP32)
+    return fail(c, GLMR_EINVAL, "the event grid is evaluated in FP64 or FP32");
+  return GLMR_OK;
+}
+}  // namespace
+
 glmr_status glmr_set_kernel(glmr_ctx* c, double tau) {
   if (!c) return GLMR_EINVAL;
   c->err.clear();
   if (!(tau > 0) || !std::isfinite(tau)) return fail(c, GLMR_EINVAL, "tau must be positive");
-  if (tau < c->dt) return fail(c, GLMR_EINVAL, "tau must be >= dt");
+  if (!c->evm && tau < c->dt) return fail(c, GLMR_EINVAL, "tau must be >= dt");
   HIPCHK(c, hipSetDevice(c->cfg.device));
   c->tau = tau;
   c->a = std::exp(-c->dt / tau);
@@ -1546,6 +1728,7 @@ glmr_status glmr_set_precision(glmr_ctx* c, int32_t precision) {
   if (precision < 0 || precision > 3) return fail(c, GLMR_EINVAL, "precision must be FP64, FP32, BF16 or FP8");
   if (precision == GLMR_FP8 && c->cfg.trace == GLMR_TRACE_RECOMPUTE)
     return fail(c, GLMR_EINVAL, "FP8 needs the resident trace");
+  TRY(reject_event_grid_precision(c, precision));
   if (precision == c->prec) return GLMR_OK;
   HIPCHK(c, hipSetDevice(c->cfg.device));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1600,6 +1783,7 @@ glmr_status glmr_eval(glmr_ctx* c, double* ll, double* ll_rows, double* grad_J, 
   const bool want_tau = grad_tau != nullptr;
   if (want_tau && c->prec == PREC_FP8)
     return fail(c, GLMR_EINVAL, "dL/dtau is evaluated in FP64, FP32 or BF16, not FP8");
+  if (want_tau && c->evm) return fail(c, GLMR_EINVAL, "dL/dtau is not available on the event grid");
   if (want_tau && !c->have_y) {
     c->keep_y = true;
     TRY(build_kernel_caches(c, true));

@@ -12,22 +12,51 @@
 //    over segment aggregates, and a fix-up that adds the carried-in state
 //    (after k subtiles: C += A^k C_in, CY += A^k CY_in + 64 k c A^k C_in).
 //
+//  * On the event grid (continuous time) the same scan runs with the per-slot
+//    decays of events.hip: C[s+1] = asub[s] (C[s] + sum_b ainv[64 s + b]).
+//
 //  * dSigma[i][j] = sum_t s_i[t] x_j[t] (Eq. (12)) and dSigmaY[i][j] =
 //    sum_t s_i[t] y_j[t] in FP64, from the spike segments: one wavefront per
 //    (64 presynaptic j) x (64 postsynaptic i) x time split, lane = j, walking
 //    the spikes of the i-block in bin order and advancing each lane's
 //    running sum over its own mask bits; accumulators in LDS; partials per
-//    split reduced in a fixed order.
+//    split reduced in a fixed order.  On the event grid the trace at a spike of
+//    i is the left limit v_j(t^-) of Eq. (12): the spike recorded at slot b is
+//    weighed by left[64 s + b] = e^{-(t_{b+1} - t_k0)/tau}.
 #include "common.h"
 
 namespace {
 
+// EV: event grid, per-subtile decays; seg[...][1] then holds the product of
+// the segment's subtile decays (there is no y)
+template <bool EV>
 __global__ void k_carry_local(CarryArgs c) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t g = blockIdx.y;
   if (j >= c.Np) return;
   const int64_t s0 = g * c.G;
   const int64_t s1 = (s0 + c.G < c.NS) ? s0 + c.G : c.NS;
+  if (EV) {
+    double x = 0.0, prod = 1.0;
+    for (int64_t s = s0; s < s1; ++s) {
+      c.C64[s * c.Np + j] = x;
+      double D = 0.0;
+      for (int p = 0; p < c.planes; ++p) {
+        uint64_t mk = c.masks[((int64_t)p * c.NS + s) * c.Np + j];
+        while (mk) {
+          const int b = __builtin_ctzll(mk);
+          mk &= mk - 1;
+          D += c.ev.ainv[s * 64 + b];
+        }
+      }
+      const double A = c.ev.asub[s];
+      x = A * (x + D);
+      prod *= A;
+    }
+    c.seg[(g * c.Np + j) * 2 + 0] = x;
+    c.seg[(g * c.Np + j) * 2 + 1] = prod;
+    return;
+  }
   const double A = c.tab->apow[1];
   double x = 0.0, y = 0.0;
   for (int64_t s = s0; s < s1; ++s) {
@@ -51,6 +80,7 @@ __global__ void k_carry_local(CarryArgs c) {
   c.seg[(g * c.Np + j) * 2 + 1] = y;
 }
 
+template <bool EV>
 __global__ void k_carry_scan(CarryArgs c, int64_t nseg) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= c.Np) return;
@@ -58,6 +88,10 @@ __global__ void k_carry_scan(CarryArgs c, int64_t nseg) {
   for (int64_t g = 0; g < nseg; ++g) {
     c.segin[(g * c.Np + j) * 2 + 0] = cin;
     c.segin[(g * c.Np + j) * 2 + 1] = cyin;
+    if (EV) {
+      cin = c.seg[(g * c.Np + j) * 2 + 1] * cin + c.seg[(g * c.Np + j) * 2 + 0];
+      continue;
+    }
     const int64_t s0 = g * c.G;
     const int64_t len = (s0 + c.G < c.NS) ? c.G : c.NS - s0;
     const double AG = c.tab->apow[len];
@@ -68,6 +102,7 @@ __global__ void k_carry_scan(CarryArgs c, int64_t nseg) {
   }
 }
 
+template <bool EV>
 __global__ void k_carry_apply(CarryArgs c) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t g = blockIdx.y;
@@ -76,6 +111,16 @@ __global__ void k_carry_apply(CarryArgs c) {
   const int64_t s1 = (s0 + c.G < c.NS) ? s0 + c.G : c.NS;
   const double cin = c.segin[(g * c.Np + j) * 2 + 0];
   const double cyin = c.segin[(g * c.Np + j) * 2 + 1];
+  if (EV) {
+    double Ak = 1.0;  // decay from the segment start to subtile s
+    for (int64_t s = s0; s < s1; ++s) {
+      const double x = c.C64[s * c.Np + j] + Ak * cin;
+      c.C64[s * c.Np + j] = x;
+      if (c.C32) c.C32[s * c.Np + j] = (float)x;
+      Ak *= c.ev.asub[s];
+    }
+    return;
+  }
   for (int64_t s = s0; s < s1; ++s) {
     const int64_t k = s - s0;
     const double Ak = c.tab->apow[k];
@@ -93,7 +138,8 @@ __global__ void k_carry_apply(CarryArgs c) {
 // ------------------------------------------------------------ spike term
 __device__ inline int lane_bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
-template <bool WANT_Y>
+// EV: event grid; the trace at a spike is its left limit at the event time
+template <bool WANT_Y, bool EV>
 __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
   __shared__ double acc[64][64];
   __shared__ double accy[WANT_Y ? 64 : 1][64];
@@ -131,7 +177,7 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
           while (m) {
             const int bb = __builtin_ctzll(m);
             m &= m - 1;
-            const double w = a.tab->ainv[bb];
+            const double w = EV ? a.ev.ainv[s * 64 + bb] : a.tab->ainv[bb];
             run += w;
             if (WANT_Y) { P0 += w; P1 += (double)(bb + 1) * w; }
           }
@@ -140,14 +186,14 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
             while (mp) {
               const int bb = __builtin_ctzll(mp);
               mp &= mp - 1;
-              const double w = a.tab->ainv[bb];
+              const double w = EV ? a.ev.ainv[s * 64 + bb] : a.tab->ainv[bb];
               run += w;
               if (WANT_Y) { P0 += w; P1 += (double)(bb + 1) * w; }
             }
           }
           bcur = b;
         }
-        const double pw = a.tab->pw[b];
+        const double pw = EV ? a.ev.left[s * 64 + b] : a.tab->pw[b];
         acc[il][lane] += pw * run;
         if (WANT_Y) accy[il][lane] += pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
       }
@@ -175,18 +221,26 @@ __global__ void k_split_reduce(const double* part, int splits, int64_t n, double
 hipError_t launch_carries(const CarryArgs& c, hipStream_t st) {
   const int64_t nseg = (c.NS + c.G - 1) / c.G;
   dim3 grid((unsigned)((c.Np + 255) / 256), (unsigned)nseg);
-  hipLaunchKernelGGL(k_carry_local, grid, dim3(256), 0, st, c);
-  hipLaunchKernelGGL(k_carry_scan, dim3((unsigned)((c.Np + 63) / 64)), dim3(64), 0, st, c, nseg);
-  hipLaunchKernelGGL(k_carry_apply, grid, dim3(256), 0, st, c);
+  if (c.ev.pw) {
+    hipLaunchKernelGGL(k_carry_local<true>, grid, dim3(256), 0, st, c);
+    hipLaunchKernelGGL(k_carry_scan<true>, dim3((unsigned)((c.Np + 63) / 64)), dim3(64), 0, st, c, nseg);
+    hipLaunchKernelGGL(k_carry_apply<true>, grid, dim3(256), 0, st, c);
+  } else {
+    hipLaunchKernelGGL(k_carry_local<false>, grid, dim3(256), 0, st, c);
+    hipLaunchKernelGGL(k_carry_scan<false>, dim3((unsigned)((c.Np + 63) / 64)), dim3(64), 0, st, c, nseg);
+    hipLaunchKernelGGL(k_carry_apply<false>, grid, dim3(256), 0, st, c);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_spike_term(const SpikeTermArgs& a, hipStream_t st) {
   dim3 grid((unsigned)a.NIB, (unsigned)a.NIB, (unsigned)a.splits);
-  if (a.CY64)
-    hipLaunchKernelGGL(k_spike_term<true>, grid, dim3(64), 0, st, a);
+  if (a.ev.pw)
+    hipLaunchKernelGGL((k_spike_term<false, true>), grid, dim3(64), 0, st, a);
+  else if (a.CY64)
+    hipLaunchKernelGGL((k_spike_term<true, false>), grid, dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL(k_spike_term<false>, grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_spike_term<false, false>), grid, dim3(64), 0, st, a);
   const int64_t n = a.Np * a.Np;
   int blocks = (int)((n + 255) / 256);
   if (blocks > 65536) blocks = 65536;

@@ -113,6 +113,16 @@ class Recording:
         return np.bincount(self.neurons, minlength=self.n_neurons).astype(np.int64)
 
 
+def event_times(rec: Recording, seed: int = 0):
+    """Continuous spike times of a raster: each spike of bin b is placed at
+    (b + u) dt with u uniform in [0, 1), then the events are sorted by (time,
+    neuron).  Returns (times [q] float64 seconds in [0, T), neurons [q] int32)."""
+    rng = np.random.default_rng(seed)
+    t = (rec.bins.astype(np.float64) + rng.random(rec.bins.shape[0])) * rec.dt
+    order = np.lexsort((rec.neurons, t))
+    return np.ascontiguousarray(t[order]), np.ascontiguousarray(rec.neurons[order])
+
+
 def simulate(N: int, B: int, dt: float, tau: float, mu: np.ndarray, J: np.ndarray,
              seed: int, threads: int = 0):
     lib = _load()

@@ -170,6 +170,56 @@ def test_ei_small_argument_branch():
         assert abs(O._ei_diff(D, xi) - direct) < 1e-11
 
 
+def test_continuous_eval_matches_event_loops_and_fd():
+    ts = _times(N=3, seed=5)
+    J = np.array([[-1.0, 0.6, -0.4], [0.3, -2.0, 0.9], [0.0, -0.7, -1.2]])
+    mu = np.log(np.array([6.0, 9.0, 4.0]))
+    tau = 0.02
+    r = O.continuous_eval(ts, 0.0, 1.0, tau, J, mu)
+    # the row-by-row loops of Eq. (8)/(10), themselves pinned by quadrature
+    assert np.allclose(r["ll_rows"], O.continuous_ll(ts, 0.0, 1.0, tau, J, mu), rtol=1e-12, atol=1e-12)
+    for i in range(3):
+        gi = O.continuous_grad_integral(ts, 0.0, 1.0, tau, J, mu, i)
+        vsum = np.array([sum(math.exp(-(t - tp) / tau) for t in ts[i] for tp in ts[j] if tp < t)
+                         for j in range(3)])
+        assert np.allclose(r["gJ"][i], vsum - gi, rtol=1e-11, atol=1e-11)
+    # gradient against central differences of the row likelihoods
+    h = 1e-6
+    for i in range(3):
+        mp, mm = mu.copy(), mu.copy()
+        mp[i] += h
+        mm[i] -= h
+        fd = (O.continuous_ll(ts, 0, 1, tau, J, mp)[i] - O.continuous_ll(ts, 0, 1, tau, J, mm)[i]) / (2 * h)
+        assert abs(fd - r["gmu"][i]) < 1e-6 * (1 + abs(fd))
+        for j in range(3):
+            Jp, Jm = J.copy(), J.copy()
+            Jp[i, j] += h
+            Jm[i, j] -= h
+            fd = (O.continuous_ll(ts, 0, 1, tau, Jp, mu)[i] - O.continuous_ll(ts, 0, 1, tau, Jm, mu)[i]) / (2 * h)
+            assert abs(fd - r["gJ"][i, j]) < 1e-6 * (1 + abs(fd))
+
+
+def test_continuous_eval_without_events_is_poisson():
+    # no spikes: U_i = mu_i throughout, L_i = -e^{mu_i} (T1 - T0)
+    mu = np.log(np.array([2.0, 5.0]))
+    J = np.array([[0.3, -1.0], [2.0, 0.1]])
+    r = O.continuous_eval([np.array([]), np.array([])], 1.5, 4.0, 0.01, J, mu)
+    assert np.allclose(r["ll_rows"], -np.exp(mu) * 2.5, rtol=1e-14)
+    assert np.allclose(r["gmu"], -np.exp(mu) * 2.5, rtol=1e-14)
+    assert np.all(r["gJ"] == 0.0)
+
+
+def test_continuous_eval_equal_times_are_the_limit_of_ordered_times():
+    # two events at the same time act in (time, neuron) order: the same as the
+    # limit of neuron 1 firing just after neuron 0
+    J = np.array([[-0.5, 0.8], [1.2, -0.3]])
+    mu = np.log(np.array([4.0, 3.0]))
+    tie = O.continuous_eval([np.array([0.2, 0.5]), np.array([0.5, 0.7])], 0.0, 1.0, 0.03, J, mu)
+    near = O.continuous_eval([np.array([0.2, 0.5]), np.array([0.5 + 1e-10, 0.7])], 0.0, 1.0, 0.03, J, mu)
+    assert np.allclose(tie["ll_rows"], near["ll_rows"], rtol=0, atol=1e-7)
+    assert np.allclose(tie["gJ"], near["gJ"], rtol=0, atol=1e-7)
+
+
 def test_grid_converges_to_continuous_first_order():
     ts = _times(N=3, T=2.0, rate=8.0, seed=4)
     J = np.array([[-1.0, 0.6, -0.4], [0.3, -2.0, 0.9], [0.0, -0.7, -1.2]])
