@@ -122,9 +122,12 @@ def main():
     ap.add_argument("--trace", default="auto", choices=["auto", "resident", "recompute"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
-    ap.add_argument("--workload", default="balanced_n1000", choices=["balanced_n1000", "batch64"],
+    ap.add_argument("--workload", default="balanced_n1000", choices=["balanced_n1000", "batch64", "events"],
                     help="batch64: 64 recordings of uneven N and T (balanced and synfire), "
-                         "evaluated together (grouped launches)")
+                         "evaluated together (grouped launches); events: the balanced N = 1000 "
+                         "recording in continuous time (event grid, Ei integrals)")
+    ap.add_argument("--cpu-sample-events", type=int, default=4000,
+                    help="events: network events of the oracle's bounded sample")
     ap.add_argument("--n-rec", type=int, default=64, help="batch64: number of recordings")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 comparison line")
@@ -147,6 +150,9 @@ def main():
     torch.cuda.init()
     if args.workload == "batch64":
         bench_batch(args, G, torch)
+        return
+    if args.workload == "events":
+        bench_events(args, G, torch)
         return
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -236,6 +242,81 @@ def main():
     out.update(extra)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(rec, min(args.cpu_sample_bins, B))
+    print(json.dumps(out))
+
+
+def cpu_baseline_events(times, neurons, N, tau, J, mu, n_events):
+    """The FP64 oracle's continuous-time L + gradient over the first n_events
+    network events (the window [0, t of event n_events)), scaled to slots*N^2/s."""
+    from oracle import glm_oracle as O
+    n_threads = os.cpu_count() or 1
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        n_threads = max(i.get("num_threads", 1) for i in info if i.get("user_api") == "blas")
+    except Exception:
+        pass
+    T1 = float(times[n_events])
+    t, n = times[:n_events], neurons[:n_events]
+    lists = [t[n == j] for j in range(N)]
+    t0 = time.perf_counter()
+    O.continuous_eval(lists, 0.0, T1, tau, J, mu)
+    dt = time.perf_counter() - t0
+    return {"value": (n_events + 1) * N * N / dt, "unit": "slots*N^2/s", "cores": int(n_threads),
+            "kind": "oracle",
+            "sample": f"FP64 continuous-time L + gradient over the first {n_events} events of the same "
+                      f"recording (window [0, {T1:.3f}) s, N = {N}); {dt:.1f} s"}
+
+
+def bench_events(args, G, torch):
+    """Continuous-time L + gradient on the event grid: the balanced N = 1000
+    recording with every spike placed uniformly inside its 1 ms bin, so the
+    slots are the intervals between ~2.7e7 network events.  A step is one
+    evaluation; value = slots * N^2 / (seconds per step)."""
+    import synth
+    prec = args.precision if args.precision in ("fp64", "fp32") else "fp64"
+    rec = synth.cached("config2", seed=0, B=args.bins)
+    N = rec.n_neurons
+    times, neu = synth.event_times(rec, seed=0)
+    T0, T1 = 0.0, rec.T
+    print(f"[events] {times.shape[0]} events ready", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ctx = G.Context.from_events(N, times, neu, T0, T1, precision=prec)
+    ctx.set_kernel(rec.tau)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    slots = ctx.B
+    ctx.set_params(rec.J, rec.mu)
+    print(f"[events] context ready: {slots} slots, setup {setup:.2f} s", file=sys.stderr, flush=True)
+    sec, r = time_steps(ctx, args.steps, args.warmup)
+    kt = kernel_times(ctx, reps=1)
+    q = ctx.query()
+    ctx.close()
+    dom = max(("kernel_U", "kernel_G"), key=lambda k: kt.get(k, (0, 0))[0])
+    ms_total, launches = kt[dom]
+    per_launch_s = ms_total / 1e3 / launches
+    achieved = 2.0 * N * N * slots / launches / per_launch_s
+    # kernel U runs on the FP64 MFMA in both modes; kernel G on the FP32 one in FP32 mode
+    peak = PEAK["fp32"] if (prec == "fp32" and dom == "kernel_G") else PEAK["fp64"]
+    units = float(slots) * N * N
+    out = {
+        "metric": "continuous-time LL+grad throughput (slots*N^2/s) at N=1000",
+        "value": units / sec, "unit": "slots*N^2/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "balanced_n1000_indeg100_t3600s_event_grid", "n_neurons": N,
+                   "n_events": int(times.shape[0]), "n_slots": slots, "precision": prec,
+                   "chunk_slots": q["chunk_bins"], "n_pad": q["n_pad"]},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "kernel": dom,
+                     "launch_ms": per_launch_s * 1e3, "launches_per_step": launches,
+                     "per_kernel_ms": {k: v[0] for k, v in kt.items()}},
+        "setup_ms": setup * 1e3, "ll": r["ll"],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_events(times, neu, N, rec.tau, rec.J, rec.mu,
+                                                  min(args.cpu_sample_events, times.shape[0] - 1))
     print(json.dumps(out))
 
 

@@ -375,6 +375,41 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
   // from the resident-trace kernel U they hold W itself and take the factor a^m.  FP64 row sums, one
   // block-row at a time.
   w_t* __restrict__ W = (w_t*)g.W;
+  if constexpr (EV) {
+    // Event grid: the interval integrals cost far more than exp, so each wave
+    // stages one 16-row block of its tile in LDS (the operand buffers are free
+    // after the last barrier of the k loop) and walks it a neuron row at a
+    // time, lanes over 64 consecutive slots: one table load per lane, the
+    // accumulators die block by block, W stores are contiguous, and the
+    // branches of the integrals follow one neuron's potential through time.
+    static_assert(P::MB == 16 && WN == 64, "event-grid epilogue expects the FP64 16x16 tile layout");
+    double* stage = (double*)smem + wave * (P::MB * WN);
+    const int tl = wn * WN + lane;
+    const bool valid = (tt0 + tl) < g.B;
+    const double pwd = g.ev.pw[tt0 + tl];
+    // zero length for padded slots: both integrals vanish
+    const glmr_ev::Slot sc = glmr_ev::slot_consts(valid ? g.ev.delta[tt0 + tl] : 0.0);
+#pragma unroll
+    for (int a = 0; a < WMB; ++a) {
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < WNB; ++b)
+#pragma unroll
+        for (int r = 0; r < P::NACC; ++r)
+          stage[P::row(r, lane) * WN + b * P::MB + P::col(lane)] = (double)acc[a][b][r];
+      __syncthreads();
+#pragma unroll 2
+      for (int e = 0; e < P::MB; ++e) {
+        const int il = wm * WM + a * P::MB + e;
+        double F, H;
+        glmr_ev::interval(pwd * stage[e * WN + lane], sc, &F, &H);
+        W[(i0 + il) * g.L + (tl0 + tl)] = (w_t)(H * pwd);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) F += __shfl_xor(F, off, 64);
+        if (lane == 0) red[wn * BI + il] = F;
+      }
+    }
+  } else
 #pragma unroll
   for (int a = 0; a < WMB; ++a) {
     double rs[P::NACC];
@@ -384,19 +419,6 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
     for (int b = 0; b < WNB; ++b) {
       const int tl = wn * WN + b * P::MB + P::col(lane);
       const bool valid = (tt0 + tl) < g.B;
-      if constexpr (EV) {
-        const double pwd = g.ev.pw[tt0 + tl];
-        const double delta = g.ev.delta[tt0 + tl];
-#pragma unroll
-        for (int r = 0; r < P::NACC; ++r) {
-          const int il = wm * WM + a * P::MB + P::row(r, lane);
-          double F = 0.0, H = 0.0;
-          if (valid) glmr_ev::interval(pwd * (double)acc[a][b][r], delta, &F, &H);
-          W[(i0 + il) * g.L + (tl0 + tl)] = (w_t)(H * pwd);
-          rs[r] += F;
-        }
-        continue;
-      }
       const T pw = tab_pw<T>(g.tab, tl & 63);
 #pragma unroll
       for (int r = 0; r < P::NACC; ++r) {

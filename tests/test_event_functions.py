@@ -2,7 +2,8 @@
 computes them, on the CPU: the same host/device code the kernels run,
 reached through glmr_ei_interval, against the exponential integral and the
 exponential evaluated to 40 digits by mpmath.  Covers every branch of the
-evaluation (the |D| <= 2 series, the near-cancelling Gauss-Legendre branch,
+evaluation (the midpoint Taylor expansion of short intervals, the |D| <= 2
+series, the near-cancelling Gauss-Legendre branch,
 the direct difference of Ei for either sign and for large arguments) and the
 limits delta -> 0, delta -> large, D -> 0."""
 import numpy as np
@@ -26,7 +27,11 @@ def _cases():
                         [0.0, 1e-12, -1e-12, 2.0, -2.0, 2.0 + 1e-9, -2.0 - 1e-9, 40.0, 41.0, -1.0, 200.0]])
     delta = 10 ** rng.uniform(-9, 2.6, D.shape[0])
     delta[:40] = 10 ** rng.uniform(-12, -6, 40)
-    return list(zip(D.tolist(), delta.tolist()))
+    # the short intervals between the events of a large network (the
+    # midpoint-Taylor branch and its boundary delta max(1, |u|) = 0.1)
+    Ds = rng.uniform(-12, 12, 400)
+    ds = 10 ** rng.uniform(-6, -0.9, 400)
+    return list(zip(D.tolist(), delta.tolist())) + list(zip(Ds.tolist(), ds.tolist()))
 
 
 def test_interval_integrals_match_mpmath_in_every_branch():
