@@ -216,7 +216,8 @@ __device__ inline T zy_at(const CT* __restrict__ C, const CT* __restrict__ CY,
 constexpr int PAD = 16;  // bytes of padding per LDS row
 
 // ---------------------------------------------------------------- kernel U/V
-template <int PREC, int BI, int BT, int WGM, int WGN, int DB, bool EV>
+// KB: bytes of k (presynaptic j) per step and LDS row
+template <int PREC, int BI, int BT, int WGM, int WGN, int DB, bool EV, int KB = 128>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
   using P = Pol<PREC>;
   using in_t = typename P::in_t;
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
   using T = c_t;  // arithmetic type of the trace
   constexpr int NW = WGM * WGN;
   constexpr int NT = NW * 64;
-  constexpr int BK = 128 / sizeof(in_t);          // k (presynaptic j) per step
+  constexpr int BK = KB / sizeof(in_t);           // k (presynaptic j) per step
   constexpr int ROWB = BK * sizeof(in_t) + PAD;   // LDS row pitch, bytes
   constexpr int WM = BI / WGM, WN = BT / WGN;
   constexpr int WMB = WM / P::MB, WNB = WN / P::MB;
@@ -608,13 +609,13 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
       }
 }
 
-template <int PREC, int BI, int BT, int WGM, int WGN, int DB, bool EV = false>
+template <int PREC, int BI, int BT, int WGM, int WGN, int DB, bool EV = false, int KB = 128>
 hipError_t run_gemm1(const Gemm1Args& a, hipStream_t st) {
   using P = Pol<PREC>;
-  constexpr int BK = 128 / sizeof(typename P::in_t);
+  constexpr int BK = KB / sizeof(typename P::in_t);
   constexpr int ROWB = BK * sizeof(typename P::in_t) + PAD;
   size_t lds = (size_t)DB * (BI + BT) * ROWB + (size_t)WGN * BI * sizeof(double);
-  auto kern = k_gemm1<PREC, BI, BT, WGM, WGN, DB, EV>;
+  auto kern = k_gemm1<PREC, BI, BT, WGM, WGN, DB, EV, KB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int64_t nblk = (int64_t)a.n_itiles * a.n_ttiles;
@@ -642,13 +643,13 @@ hipError_t run_gemm2(const Gemm2Args& a, hipStream_t st) {
 hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st) {
   if (a.ev.pw) {  // event grid: FP64 and FP32 modes, likelihood kernel only
     if (a.mode != 0) return hipErrorInvalidValue;
-    if (prec == PREC_F64) return run_gemm1<PREC_F64, 128, 128, 2, 2, 2, true>(a, st);
-    if (prec == PREC_F32) return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2, true>(a, st);
+    if (prec == PREC_F64) return run_gemm1<PREC_F64, 128, 128, 2, 2, 2, true, 256>(a, st);
+    if (prec == PREC_F32) return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2, true, 256>(a, st);
     return hipErrorInvalidValue;
   }
   switch (prec) {
-    case PREC_F64: return run_gemm1<PREC_F64, 128, 128, 2, 2, 2>(a, st);
-    case PREC_F32: return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2>(a, st);
+    case PREC_F64: return run_gemm1<PREC_F64, 128, 128, 2, 2, 2, false, 256>(a, st);
+    case PREC_F32: return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2, false, 256>(a, st);
     case PREC_BF16:
       if (tile == 128) return run_gemm1<PREC_BF16, 128, 256, 2, 4, 2>(a, st);
       return run_gemm1<PREC_BF16, 256, 256, 2, 4, 2>(a, st);
