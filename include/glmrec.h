@@ -172,6 +172,20 @@ void glmr_ei_interval(double D, double delta, double* F, double* H);
  * only be computed once). */
 glmr_status glmr_set_kernel(glmr_ctx* ctx, double tau);
 
+/* Transmission delays of Sec. 2.4, Eq. (15), on the regular grid, in bins:
+ * every connection j -> i with j != i delays by d, the self-connection
+ * i -> i by d_self, 0 <= d, d_self < n_bins.  Row i then sees
+ *   U_i[t] = mu_i + sum_{j != i} J_ij x_j[t - d] + J_ii x_i[t - d_self]
+ * (x_j[t] = 0 for t <= 0), while its spike terms stay at the recorded bins:
+ *   L_i = sum_t s_i[t] U_i[t] - dt sum_t lambda_i[t],
+ *   dL/dJ_ij = sum_t (s_i[t] - dt lambda_i[t]) x_j[t - D_ij].
+ * The contractions run on the raster shifted by d; d_self != d adds a
+ * per-(bin, neuron) correction of the self term.  Allowed at any time
+ * (rebuilds the kernel caches); (0, 0) is the undelayed model.  GLMR_EINVAL
+ * on the event grid, for d_self != d in FP8, or out-of-range delays;
+ * dL/dtau then requires d_self = d. */
+glmr_status glmr_set_delays(glmr_ctx* ctx, int64_t d, int64_t d_self);
+
 /* Change the arithmetic of later evaluations (glmr_precision).  Keeps the
  * spikes, the kernel and the FP64 parameters; rebuilds the precision-specific
  * buffers.  Used to finish a BF16 ascent with FP32 evaluations: BF16 rounds J

@@ -277,6 +277,36 @@ def loglik(bins, neurons, N: int, B: int, dt: float, tau: float, J: np.ndarray,
     return out
 
 
+def loglik_delayed(bins, neurons, N: int, B: int, dt: float, tau: float, J: np.ndarray,
+                   mu: np.ndarray, d: int, d_self: int) -> Dict:
+    """Grid L_i and gradient with transmission delays (Sec. 2.4, Eq. (15)) in
+    FP64, dense (small inputs): row i sees every presynaptic trace x_j with
+    j != i delayed by d bins and its own x_i by d_self bins, while its spike
+    terms stay at the recorded bins:
+        U_i[t] = mu_i + sum_{j != i} J_ij x_j[t - d] + J_ii x_i[t - d_self],
+        L_i = sum_t s_i[t] U_i[t] - dt sum_t exp(U_i[t]),
+        dL/dJ_ij = sum_t (s_i[t] - dt lambda_i[t]) x_j[t - D_ij],
+    with x_j[t] = 0 for t <= 0 (the trace of reading R1)."""
+    S = spike_matrix(bins, neurons, N, B).toarray()
+    X = trace_lfilter(S, decay(dt, tau))
+
+    def delayed(k):
+        out = np.zeros_like(X)
+        if k < B:
+            out[k:] = X[:B - k]
+        return out
+
+    Xd, Xs = delayed(d), delayed(d_self)
+    off = J * (1.0 - np.eye(N))
+    U = mu[None, :] + Xd @ off.T + Xs * np.diag(J)[None, :]
+    lam = np.exp(U)
+    R = S - dt * lam
+    ll_rows = (S * U).sum(axis=0) - dt * lam.sum(axis=0)
+    gJ = R.T @ Xd
+    gJ[np.arange(N), np.arange(N)] = (R * Xs).sum(axis=0)
+    return dict(ll_rows=ll_rows, ll=float(math.fsum(ll_rows)), gJ=gJ, gmu=R.sum(axis=0))
+
+
 def spike_term_matrix(bins, neurons, N: int, B: int, dt: float, tau: float,
                       chunk: int = DEFAULT_CHUNK) -> np.ndarray:
     """partial^Sigma_ij = sum_t s_i[t] x_j[t] (Eq. (12)); parameter-free (L212)."""

@@ -18,7 +18,7 @@ from ._lib import (GLMR_BF16, GLMR_DEVICE, GLMR_FP8, GLMR_FP32, GLMR_FP64, GLMR_
                    GLMR_NOT_CONVERGED, GlmrError, PRECISIONS)
 
 __all__ = ["Context", "Batch", "GlmrError", "glmr_create", "glmr_destroy", "glmr_set_spikes",
-           "glmr_event_slots", "glmr_set_spike_times", "glmr_ei_interval",
+           "glmr_event_slots", "glmr_set_spike_times", "glmr_ei_interval", "glmr_set_delays",
            "glmr_set_kernel", "glmr_set_precision", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
            "glmr_fit_defaults", "glmr_status_string", "glmr_last_error", "glmr_query",
            "glmr_batch_create", "glmr_batch_destroy", "glmr_batch_eval", "glmr_batch_get_grad",
@@ -112,6 +112,10 @@ def glmr_ei_interval(D, delta):
     F, H = ctypes.c_double(), ctypes.c_double()
     L.load().glmr_ei_interval(float(D), float(delta), ctypes.byref(F), ctypes.byref(H))
     return F.value, H.value
+
+
+def glmr_set_delays(ctx, d_bins, d_self_bins):
+    return _check(L.load().glmr_set_delays(ctx, int(d_bins), int(d_self_bins)), ctx)
 
 
 def glmr_set_kernel(ctx, tau):
@@ -318,6 +322,11 @@ class Context:
 
     def set_kernel(self, tau: float):
         return glmr_set_kernel(self._c, tau)
+
+    def set_delays(self, d_bins: int, d_self_bins: int):
+        """Transmission delays in bins: d on every connection j -> i (j != i),
+        d_self on the self-connection (Sec. 2.4, Eq. (15))."""
+        return glmr_set_delays(self._c, d_bins, d_self_bins)
 
     def set_params(self, J, mu):
         return glmr_set_params(self._c, J, mu)

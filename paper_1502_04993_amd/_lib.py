@@ -65,6 +65,7 @@ SIGNATURES = {
                                             ctypes.c_double, ctypes.c_int32]),
     "glmr_ei_interval": (None, [ctypes.c_double, ctypes.c_double, _dp, _dp]),
     "glmr_set_kernel": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "glmr_set_delays": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64]),
     "glmr_set_precision": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "glmr_set_params": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
     "glmr_get_params": (ctypes.c_int, [_vp, _vp, _vp, _dp, ctypes.c_int32]),

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libglmrec.so")
-SOURCES = ["ingest.hip", "events.hip", "trace.hip", "gemm.hip", "gemm_res.hip", "reduce.hip", "runtime.hip"]
+SOURCES = ["ingest.hip", "events.hip", "delays.hip", "trace.hip", "gemm.hip", "gemm_res.hip", "reduce.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -147,6 +147,41 @@ struct SpikeTermArgs {
 };
 hipError_t launch_spike_term(const SpikeTermArgs& a, hipStream_t st);
 
+// Transmission delays (delays.hip) ---------------------------------------------
+struct DelayTrace {          // the recorded (unshifted) raster's trace, FP64
+  const uint64_t* masks;     // [planes][NS][Np]
+  int planes;
+  const double* C;           // [NS][Np] carries
+  const Tables* tab;
+  int64_t NS, Np;
+};
+hipError_t launch_shift_masks(const uint64_t* src, uint64_t* dst, int planes, int64_t NS, int64_t Np,
+                              int64_t d, hipStream_t st);
+struct SelfDelayArgs {
+  DelayTrace x;
+  void* W;                   // [Np][L] weights of the chunk (kernel U's output)
+  int wtype;                 // 0 double, 1 float, 2 bf16
+  int scaled;                // 1: W holds lambda a^m (rebuilt-trace kernels), 0: lambda
+  const double* Jr;          // [Np][Np] J as the contraction used it
+  int64_t B, t0, L, Lc;      // bins, chunk start, W pitch, bins of the chunk
+  int tb;                    // bins per row-sum tile of kernel U (128 or 256)
+  int64_t d, ds;             // delays in bins
+  double* rowpart;           // [Bp/tb][Np] rewritten
+  double* gpart;             // [Bp/tb][Np] sum lambda Delta
+};
+hipError_t launch_self_delay(const SelfDelayArgs& a, hipStream_t st);
+struct SelfSpikeArgs {
+  DelayTrace x;
+  const int32_t* seg_off;
+  const uint16_t* seg_ent;
+  int64_t NIB;
+  int splits;
+  int64_t d, ds;
+  double* part;              // [splits][Np]
+  double* dsig;              // [Np][Np]: the diagonal is incremented
+};
+hipError_t launch_self_spike(const SelfSpikeArgs& a, hipStream_t st);
+
 // Likelihood kernels -------------------------------------------------------
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_FP8 = 3 };
 
@@ -270,6 +305,7 @@ struct AssembleArgs {
   const double* rowsum;   // sum_t W  [Np]
   const double* rowsumV;  // nullable
   const double* G64;      // nullable (no gradient)
+  const double* gself;    // nullable: per-row correction of G_ii (self-delay)
   const double* rowscale; // [Np] multiplier of rowsum/G (e^mu, FP8 scales folded in)
   double* ll_rows;        // [Np]
   double* gJ;             // [Np][Np] or null

@@ -94,7 +94,8 @@ __global__ __launch_bounds__(RT) void k_assemble(AssembleArgs a) {
   }
   if (a.gJ) {
     for (int64_t j = tid; j < a.Np; j += RT)
-      a.gJ[i * a.Np + j] = (j < a.N) ? ds[j] - sc * a.G64[i * a.Np + j] : 0.0;
+      a.gJ[i * a.Np + j] =
+          (j < a.N) ? ds[j] - sc * (a.G64[i * a.Np + j] + ((a.gself && j == i) ? a.gself[i] : 0.0)) : 0.0;
   }
 }
 

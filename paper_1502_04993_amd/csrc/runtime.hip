@@ -83,6 +83,13 @@ struct glmr_ctx {
   double* evtab = nullptr;  // [4 * NS*64 + NS]: pw, ainv, left, delta, asub
   double max_span = 0;      // largest 64-slot span / tau of the current tables
 
+  // transmission delays in bins (regular grid): d on j -> i (j != i), d_s on i -> i
+  int64_t dly = 0, dly_s = 0;
+  uint64_t* masks0 = nullptr;  // recorded raster's masks when delayed (masks is the shifted one)
+  double* C0 = nullptr;        // its carries when d_s != d
+  double* gpart = nullptr;     // [Bp/bt1][Np] self-delay correction of G_ii per tile
+  double* gself = nullptr;     // [Np]
+
   // kernel
   bool have_kernel = false, have_y = false, keep_y = false;
   double tau = 0, a = 0;
@@ -249,6 +256,45 @@ size_t jc_bytes(int prec) { return prec == PREC_F32 ? 8 : in_bytes(prec); }
 
 // ---------------------------------------------------------------- kernel caches
 // Whether the BF16 trace is kept in HBM (see glmr_trace_mode).
+bool delayed(const glmr_ctx* c) { return c->dly != 0 || c->dly_s != 0; }
+bool self_delayed(const glmr_ctx* c) { return c->dly != c->dly_s; }
+
+// The masks the contractions use: the recorded raster's shifted by d bins
+// (masks0 keeps the recorded ones).  Called after the ingest and when the
+// delays change.
+glmr_status apply_delays(glmr_ctx* c) {
+  if (!c->have_spikes && !c->masks) return GLMR_OK;
+  if (!delayed(c)) {
+    if (c->masks0) {
+      dfree(c, c->masks);
+      c->masks = c->masks0;
+      c->masks0 = nullptr;
+    }
+    dfree(c, c->C0);
+    return GLMR_OK;
+  }
+  const size_t nm = (size_t)c->planes * c->NS * c->Np;
+  if (!c->masks0) {
+    c->masks0 = c->masks;
+    c->masks = nullptr;
+    TRY(dalloc(c, c->masks, nm));
+  }
+  HIPCHK(c, launch_shift_masks(c->masks0, c->masks, c->planes, c->NS, c->Np, c->dly, c->st));
+  if (!self_delayed(c)) dfree(c, c->C0);
+  return GLMR_OK;
+}
+
+DelayTrace delay_trace(const glmr_ctx* c) {
+  DelayTrace x{};
+  x.masks = c->masks0;
+  x.planes = c->planes;
+  x.C = c->C0;
+  x.tab = c->tab;
+  x.NS = c->NS;
+  x.Np = c->Np;
+  return x;
+}
+
 EvSlots ev_slots(const glmr_ctx* c) {
   EvSlots e{};
   if (!c->evm || !c->evtab) return e;
@@ -402,6 +448,19 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
     ProfScope ps(c, K_CARRY);
     HIPCHK(c, launch_carries(ca, c->st));
   }
+  if (self_delayed(c)) {
+    // the recorded raster's own trace, for the self-connection's delay
+    if (!c->C0) TRY(dalloc(c, c->C0, nc));
+    CarryArgs c0 = ca;
+    c0.masks = c->masks0;
+    c0.want_y = 0;
+    c0.C64 = c->C0;
+    c0.CY64 = nullptr;
+    c0.C32 = nullptr;
+    c0.CY32 = nullptr;
+    ProfScope ps(c, K_CARRY);
+    HIPCHK(c, launch_carries(c0, c->st));
+  }
   TRY(build_resident_trace(c));
 
   // spike term dSigma (and dSigmaY)
@@ -435,6 +494,20 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
     ProfScope ps(c, K_SPIKE);
     HIPCHK(c, launch_spike_term(sa, c->st));
   }
+  if (self_delayed(c)) {
+    SelfSpikeArgs ss{};
+    ss.x = delay_trace(c);
+    ss.seg_off = c->seg_off;
+    ss.seg_ent = c->seg_ent;
+    ss.NIB = c->NIB;
+    ss.splits = (int)std::max<int64_t>(1, std::min<int64_t>(64, c->NS));
+    ss.d = c->dly;
+    ss.ds = c->dly_s;
+    ss.part = part;  // splits * Np doubles fit in the spike term's partial buffer
+    ss.dsig = c->dsig;
+    ProfScope ps(c, K_SPIKE);
+    HIPCHK(c, launch_self_spike(ss, c->st));
+  }
   HIPCHK(c, hipStreamSynchronize(c->st));
   dfree(c, part);
   dfree(c, seg);
@@ -456,6 +529,8 @@ glmr_status ensure_workspace(glmr_ctx* c, bool want_grad, bool want_tau) {
   if (!c->rowpart) TRY(dalloc(c, c->rowpart, (size_t)ntiles_t * Np));
   if (want_tau && !c->rowpartV) TRY(dalloc(c, c->rowpartV, (size_t)ntiles_t * Np));
   if (!c->rowsum) TRY(dalloc(c, c->rowsum, (size_t)Np));
+  if (self_delayed(c) && !c->gpart) TRY(dalloc(c, c->gpart, (size_t)ntiles_t * Np));
+  if (self_delayed(c) && !c->gself) TRY(dalloc(c, c->gself, (size_t)Np));
   if (want_tau && !c->rowsumV) TRY(dalloc(c, c->rowsumV, (size_t)Np));
   if (!c->rp_tmp) TRY(dalloc(c, c->rp_tmp, (size_t)rowpart_tmp_len(Np)));
   if (!c->ll_rows) TRY(dalloc(c, c->ll_rows, (size_t)Np));
@@ -590,6 +665,25 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       ProfScope ps(c, K_U);
       HIPCHK(c, launch_gemm1(c->prec, c->tile, g1, c->st));
     }
+    if (self_delayed(c)) {
+      SelfDelayArgs sd{};
+      sd.x = delay_trace(c);
+      sd.W = c->W;
+      sd.wtype = c->prec == PREC_F64 ? 0 : (c->prec == PREC_F32 ? 1 : 2);
+      sd.scaled = c->resident ? 0 : 1;
+      sd.Jr = c->Jr;
+      sd.B = c->B;
+      sd.t0 = t0;
+      sd.L = c->L;
+      sd.Lc = Lc;
+      sd.tb = c->bt1;
+      sd.d = c->dly;
+      sd.ds = c->dly_s;
+      sd.rowpart = c->rowpart;
+      sd.gpart = c->gpart;
+      ProfScope ps(c, K_U);
+      HIPCHK(c, launch_self_delay(sd, c->st));
+    }
     if (want_tau) {
       g1.mode = 1;
       g1.w_plain = c->resident ? 1 : 0;
@@ -637,6 +731,8 @@ glmr_status eval_finish(glmr_ctx* c, bool want_grad, bool want_tau) {
   HIPCHK(c, launch_rowpart_reduce(c->rowpart, ntiles_t, Np, c->rowsum, c->rp_tmp, c->st));
   if (want_tau)
     HIPCHK(c, launch_rowpart_reduce(c->rowpartV, ntiles_t, Np, c->rowsumV, c->rp_tmp, c->st));
+  if (want_grad && self_delayed(c))
+    HIPCHK(c, launch_rowpart_reduce(c->gpart, ntiles_t, Np, c->gself, c->rp_tmp, c->st));
   AssembleArgs aa{};
   aa.N = c->N;
   aa.Np = Np;
@@ -649,6 +745,7 @@ glmr_status eval_finish(glmr_ctx* c, bool want_grad, bool want_tau) {
   aa.rowsum = c->rowsum;
   aa.rowsumV = want_tau ? c->rowsumV : nullptr;
   aa.G64 = want_grad ? c->G64 : nullptr;
+  aa.gself = (want_grad && self_delayed(c)) ? c->gself : nullptr;
   aa.rowscale = c->rowscale;
   aa.ll_rows = c->ll_rows;
   aa.gJ = want_grad ? c->gJ : nullptr;
@@ -1189,7 +1286,7 @@ glmr_status batch_prepare(glmr_batch* b) {
   bool grouped = true;
   for (glmr_ctx* c : b->ctxs) {
     TRY(check_ready(c));
-    grouped = grouped && c->resident;
+    grouped = grouped && c->resident && !self_delayed(c);
   }
   b->grouped = grouped;
   if (grouped) {
@@ -1526,6 +1623,7 @@ glmr_status ingest_pairs(glmr_ctx* c, const int64_t* bin, const int32_t* neuron,
   c->planes = std::max(1, (int)hmax);
   const size_t nm = (size_t)c->planes * c->NS * c->Np;
   dfree(c, c->masks);
+  dfree(c, c->masks0);
   TRY(dalloc(c, c->masks, nm));
   HIPCHK(c, hipMemsetAsync(c->masks, 0, nm * sizeof(uint64_t), c->st));
   HIPCHK(c, launch_ingest_masks(b, c->masks, c->planes, c->Np, c->st));
@@ -1539,6 +1637,7 @@ glmr_status ingest_pairs(glmr_ctx* c, const int64_t* bin, const int32_t* neuron,
   dfree(c, scan_tmp);
   c->nspk = n;
   c->have_spikes = true;
+  TRY(apply_delays(c));
   c->all_spiking = true;
   for (int i = 0; i < c->N; ++i)
     if (c->q_host[i] == 0) c->all_spiking = false;
@@ -1695,6 +1794,25 @@ glmr_status glmr_set_kernel(glmr_ctx* c, double tau) {
   return build_kernel_caches(c, c->keep_y);
 }
 
+glmr_status glmr_set_delays(glmr_ctx* c, int64_t d, int64_t d_self) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (c->evm) return fail(c, GLMR_EINVAL, "delays are defined on the regular grid");
+  if (d < 0 || d_self < 0 || d >= c->B || d_self >= c->B)
+    return fail(c, GLMR_EINVAL, "delays must be in [0, n_bins)");
+  if (d != d_self && c->prec == PREC_FP8)
+    return fail(c, GLMR_EINVAL, "a self-delay other than d needs FP64, FP32 or BF16");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->dly = d;
+  c->dly_s = d_self;
+  if (!c->have_spikes) return GLMR_OK;  // applied when the spikes arrive
+  c->have_kernel = false;
+  TRY(apply_delays(c));
+  if (c->tau > 0) TRY(build_kernel_caches(c, c->keep_y));
+  return GLMR_OK;
+}
+
 glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int32_t where) {
   if (!c) return GLMR_EINVAL;
   c->err.clear();
@@ -1729,6 +1847,8 @@ glmr_status glmr_set_precision(glmr_ctx* c, int32_t precision) {
   if (precision == GLMR_FP8 && c->cfg.trace == GLMR_TRACE_RECOMPUTE)
     return fail(c, GLMR_EINVAL, "FP8 needs the resident trace");
   TRY(reject_event_grid_precision(c, precision));
+  if (precision == GLMR_FP8 && c->dly != c->dly_s)
+    return fail(c, GLMR_EINVAL, "a self-delay other than d needs FP64, FP32 or BF16");
   if (precision == c->prec) return GLMR_OK;
   HIPCHK(c, hipSetDevice(c->cfg.device));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1744,6 +1864,7 @@ glmr_status glmr_set_precision(glmr_ctx* c, int32_t precision) {
   c->Gp = nullptr;
   dfree(c, c->rowpart);
   dfree(c, c->rowpartV);
+  dfree(c, c->gpart);
   if (c->Jc) {
     unsigned char* jc = (unsigned char*)c->Jc;
     dfree(c, jc);
@@ -1784,6 +1905,8 @@ glmr_status glmr_eval(glmr_ctx* c, double* ll, double* ll_rows, double* grad_J, 
   if (want_tau && c->prec == PREC_FP8)
     return fail(c, GLMR_EINVAL, "dL/dtau is evaluated in FP64, FP32 or BF16, not FP8");
   if (want_tau && c->evm) return fail(c, GLMR_EINVAL, "dL/dtau is not available on the event grid");
+  if (want_tau && c->dly != c->dly_s)
+    return fail(c, GLMR_EINVAL, "dL/dtau needs the self-delay equal to the transmission delay");
   if (want_tau && !c->have_y) {
     c->keep_y = true;
     TRY(build_kernel_caches(c, true));

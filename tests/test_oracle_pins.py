@@ -424,3 +424,60 @@ def test_validation_likelihood_is_full_minus_training_prefix():
     m = rec.bins < bt
     head = O.loglik(rec.bins[m], rec.neurons[m], N, bt, rec.dt, rec.tau, J, rec.mu)
     assert np.allclose(full["ll_rows"] - head["ll_rows"], tail["ll_rows"], rtol=1e-12, atol=1e-9)
+
+
+# ---------------------------------------------------- delays (Sec. 2.4, Eq. (15))
+
+def _delayed_row_by_shifted_raster(S, i, d, ds, a, dt, J, mu):
+    """Eq. (15) literally for row i: shift every spike train S_j by its delay
+    (d, or d_self for j = i), filter the shifted raster, and take the spike
+    terms at the recorded spikes of i."""
+    B, N = S.shape
+    Sh = np.zeros_like(S)
+    for j in range(N):
+        D = ds if j == i else d
+        if D < B:
+            Sh[D:, j] = S[:B - D, j]
+    X = O.trace_recursive(Sh, a)
+    U = mu[i] + X @ J[i]
+    return float((S[:, i] * U).sum() - dt * np.exp(U).sum())
+
+
+@pytest.mark.parametrize("d,ds", [(0, 0), (3, 1), (2, 2), (0, 4), (70, 1)])
+def test_delayed_likelihood_is_eq15_row_by_row(d, ds):
+    bins, neu, S = tiny_raster(N=5, B=700, seed=21)
+    N, B, dt, tau = 5, 700, 0.001, 0.01
+    rng = np.random.default_rng(2)
+    J = rng.normal(0, 0.6, (N, N))
+    mu = rng.normal(3.0, 0.3, N)
+    r = O.loglik_delayed(bins, neu, N, B, dt, tau, J, mu, d, ds)
+    for i in range(N):
+        ref = _delayed_row_by_shifted_raster(S, i, d, ds, O.decay(dt, tau), dt, J, mu)
+        assert abs(r["ll_rows"][i] - ref) <= 1e-11 * abs(ref)
+    if d == ds == 0:
+        u = O.loglik(bins, neu, N, B, dt, tau, J, mu)
+        assert np.allclose(r["ll_rows"], u["ll_rows"], rtol=1e-13)
+        assert np.allclose(r["gJ"], u["gJ"], rtol=1e-12, atol=1e-12)
+
+
+def test_delayed_gradient_matches_finite_differences():
+    bins, neu, S = tiny_raster(N=4, B=600, seed=22)
+    N, B, dt, tau, d, ds = 4, 600, 0.001, 0.01, 3, 1
+    rng = np.random.default_rng(4)
+    J = rng.normal(0, 0.6, (N, N))
+    mu = rng.normal(3.0, 0.3, N)
+    r = O.loglik_delayed(bins, neu, N, B, dt, tau, J, mu, d, ds)
+    h = 1e-6
+    for (i, j) in [(0, 1), (2, 2), (3, 0), (1, 1)]:
+        Jp, Jm = J.copy(), J.copy()
+        Jp[i, j] += h
+        Jm[i, j] -= h
+        fd = (O.loglik_delayed(bins, neu, N, B, dt, tau, Jp, mu, d, ds)["ll_rows"][i]
+              - O.loglik_delayed(bins, neu, N, B, dt, tau, Jm, mu, d, ds)["ll_rows"][i]) / (2 * h)
+        assert abs(fd - r["gJ"][i, j]) < 1e-6 * (1 + abs(fd))
+    mp, mm = mu.copy(), mu.copy()
+    mp[2] += h
+    mm[2] -= h
+    fd = (O.loglik_delayed(bins, neu, N, B, dt, tau, J, mp, d, ds)["ll_rows"][2]
+          - O.loglik_delayed(bins, neu, N, B, dt, tau, J, mm, d, ds)["ll_rows"][2]) / (2 * h)
+    assert abs(fd - r["gmu"][2]) < 1e-6 * (1 + abs(fd))
