@@ -1,7 +1,7 @@
-"""Cross-validation scans over the kernel time constant and the penalty
-(Sec. 2.5 and Sec. 3.2: fit on a training part of the recording, score the
-fitted parameters by the likelihood of a held-out validation part, scan one
-hyper-parameter at a time).
+"""Cross-validation scans over the kernel time constant, the transmission
+delay and the penalty (Sec. 2.4, 2.5 and Sec. 3.2, Fig. 4: fit on a training
+part of the recording, score the fitted parameters by the likelihood of a
+held-out validation part, scan the hyper-parameters over a grid).
 
 The recording is split in time: bins [0, B_t) train, [B_t, B) validate.  For
 every grid point the training context is fitted (all grid points that share a
@@ -29,27 +29,39 @@ class CVResult:
     taus: List[float]
     alphas: List[float]
     train_bins: int
-    # [len(alphas)][len(taus)] arrays of per-row validation log-likelihoods
+    # [len(alphas)][len(taus)][N] per-row validation log-likelihoods (with
+    # delays: [len(alphas)][len(taus) * len(delays)][N], tau-major)
     val_rows: np.ndarray
     # fitted (J, mu) per grid point, keyed (alpha index, tau index)
     params: Dict[Tuple[int, int], Tuple[np.ndarray, np.ndarray]] = field(default_factory=dict)
     reports: Dict[Tuple[int, int], dict] = field(default_factory=dict)
+    # (d, d_self) in bins per delay grid point
+    delays: List[Tuple[int, int]] = field(default_factory=lambda: [(0, 0)])
+
+    def point(self, k: int) -> Tuple[float, Tuple[int, int]]:
+        """(tau, (d, d_self)) of grid column k."""
+        nd = len(self.delays)
+        return self.taus[k // nd], self.delays[k % nd]
 
     @property
     def val(self) -> np.ndarray:
         """Total validation log-likelihood per (alpha, tau)."""
         return self.val_rows.sum(axis=-1)
 
-    def best(self) -> Tuple[float, float]:
-        """(alpha, tau) with the largest total validation log-likelihood."""
-        a, t = np.unravel_index(np.argmax(self.val), self.val.shape)
-        return self.alphas[a], self.taus[t]
+    def best(self):
+        """(alpha, tau) with the largest total validation log-likelihood
+        ((alpha, tau, (d, d_self)) when delays were scanned)."""
+        a, k = np.unravel_index(np.argmax(self.val), self.val.shape)
+        if len(self.delays) == 1:
+            return self.alphas[a], self.taus[k]
+        tau, dl = self.point(k)
+        return self.alphas[a], tau, dl
 
     def mean_row_peak_tau(self, alpha_index: int = 0) -> float:
         """Mean over rows of the tau at which each row's validation curve peaks
         (the paper averages the peak locations of the per-neuron curves)."""
         peaks = np.argmax(self.val_rows[alpha_index], axis=0)
-        return float(np.mean(np.asarray(self.taus)[peaks]))
+        return float(np.mean([self.point(k)[0] for k in peaks]))
 
 
 def _split(bins, neurons, b_train):
@@ -62,21 +74,27 @@ def _split(bins, neurons, b_train):
 def cv_scan(bins: np.ndarray, neurons: np.ndarray, n_neurons: int, n_bins: int, dt: float,
             taus: Sequence[float], alphas: Sequence[float] = (0.0,), train_frac: float = 0.5,
             precision: str = "fp32", max_iter: int = 500, ftol: float = 0.0, l1_eps: float = 0.0, j_max: float = 0.0,
-            rate_min: float = 0.0, rate_max: float = 0.0, device: int = 0) -> CVResult:
-    """Fit on the first train_frac of the bins for every (alpha, tau) and score
-    each fit on the rest.  Returns a CVResult (per-row validation
-    log-likelihoods, fitted parameters and fit reports per grid point)."""
+            rate_min: float = 0.0, rate_max: float = 0.0, device: int = 0,
+            delays: Sequence[Tuple[int, int]] = ((0, 0),)) -> CVResult:
+    """Fit on the first train_frac of the bins for every (alpha, tau, delay)
+    and score each fit on the rest; delays are (d, d_self) pairs in bins.
+    Returns a CVResult (per-row validation log-likelihoods, fitted parameters
+    and fit reports per grid point)."""
     taus = [float(t) for t in taus]
     alphas = [float(a) for a in alphas]
+    dls = [(int(d), int(ds)) for d, ds in delays]
+    points = [(tau, dl) for tau in taus for dl in dls]
     b_train = int(round(n_bins * train_frac))
     if not 0 < b_train < n_bins:
         raise ValueError("train_frac must leave bins on both sides of the split")
     tb, tn = _split(bins, neurons, b_train)
-    val = np.zeros((len(alphas), len(taus), n_neurons))
-    out = CVResult(taus, alphas, b_train, val)
+    val = np.zeros((len(alphas), len(points), n_neurons))
+    out = CVResult(taus, alphas, b_train, val, delays=dls)
     fulls: List[Context] = []
-    for tau in taus:
+    for tau, (d, ds) in points:
         c = Context(n_neurons, n_bins, dt, precision=precision, device=device)
+        if (d, ds) != (0, 0):
+            c.set_delays(d, ds)
         c.set_spikes_allow_silent(bins, neurons)
         c.set_kernel(tau)
         fulls.append(c)
@@ -84,8 +102,10 @@ def cv_scan(bins: np.ndarray, neurons: np.ndarray, n_neurons: int, n_bins: int, 
         for ai, alpha in enumerate(alphas):
             trains: List[Context] = []
             try:
-                for tau in taus:
+                for tau, (d, ds) in points:
                     c = Context(n_neurons, b_train, dt, precision=precision, device=device)
+                    if (d, ds) != (0, 0):
+                        c.set_delays(d, ds)
                     c.set_spikes(tb, tn)
                     c.set_kernel(tau)
                     trains.append(c)

@@ -78,3 +78,30 @@ def test_cv_scan_matches_oracle_and_finds_tau():
     a, t = res.best()
     assert res.val[res.alphas.index(a), res.taus.index(t)] == res.val.max()
     assert 0.004 <= res.mean_row_peak_tau(0) <= 0.016
+
+
+def test_cv_scan_over_delays_scores_like_oracle_and_finds_no_delay():
+    """Delay axis of the scan (Sec. 2.4, Fig. 4): the data carry no
+    transmission delay beyond the grid's one bin, so d = 0 validates best; the
+    GPU's validation scores equal the oracle's scores of the same parameters,
+    and each fit is a stationary point of the oracle's delayed likelihood."""
+    from paper_1502_04993_amd.cv import cv_scan
+    rec = synth.balanced(N=20, B=60_000, in_frac=0.25, tau=0.008, seed=13)
+    N, B, dt = rec.n_neurons, rec.n_bins, rec.dt
+    delays = [(0, 0), (2, 0), (5, 1)]
+    res = cv_scan(rec.bins, rec.neurons, N, B, dt, [0.008], precision="fp64", max_iter=3000,
+                  delays=delays)
+    bt = res.train_bins
+    m = rec.bins < bt
+    tb, tn = rec.bins[m], rec.neurons[m]
+    for k, (d, ds) in enumerate(delays):
+        J, mu = res.params[(0, k)]
+        full = O.loglik_delayed(rec.bins, rec.neurons, N, B, dt, 0.008, J, mu, d, ds)
+        head = O.loglik_delayed(tb, tn, N, bt, dt, 0.008, J, mu, d, ds)
+        v = full["ll_rows"] - head["ll_rows"]
+        g = max(np.abs(head["gJ"]).max(), np.abs(head["gmu"]).max())
+        print(f"[cv delays] d={d} ds={ds}: gpu {res.val[0, k]:.6f} oracle {v.sum():.6f} max|grad| {g:.2e}",
+              flush=True)
+        assert np.allclose(res.val_rows[0, k], v, rtol=0, atol=1e-9 * abs(full["ll"]))
+        assert g <= 1e-4
+    assert res.best() == (0.0, 0.008, (0, 0))
