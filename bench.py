@@ -126,7 +126,7 @@ def main():
                     help="batch64: 64 recordings of uneven N and T (balanced and synfire), "
                          "evaluated together (grouped launches); events: the balanced N = 1000 "
                          "recording in continuous time (event grid, Ei integrals)")
-    ap.add_argument("--cpu-sample-events", type=int, default=4000,
+    ap.add_argument("--cpu-sample-events", type=int, default=12000,
                     help="events: network events of the oracle's bounded sample")
     ap.add_argument("--n-rec", type=int, default=64, help="batch64: number of recordings")
     ap.add_argument("--no-fp32", action="store_true")
