@@ -10,7 +10,8 @@
 //       (the lambda part of dL/dtau).
 //   kernel G (k_gemm2):  Gp[i][j] = sum_{t in split} W[i][t] x_j[t], the
 //       integral of Eq. (12) up to the factor dt e^{mu_i}, one partial per
-//       time split (no atomics; reduced in a fixed order in FP64).
+//       time split (no atomics; reduced in a fixed order in FP64).  FP64
+//       accumulation in the FP64 and FP32 modes (FP32 operands widened).
 //
 // The trace x never exists in HBM: each workgroup rebuilds the tile it needs
 // in LDS from the spike bitmasks and the per-subtile carries, in scaled form
@@ -122,6 +123,27 @@ template <> struct Pol<PREC_F32U> {
   __device__ static inline int row(int r, int lane) { return Pol<PREC_F64>::row(r, lane); }
   __device__ static inline int col(int lane) { return Pol<PREC_F64>::col(lane); }
   __device__ static inline double lam(double v) { return exp(v); }
+  __device__ static inline in_t cvt(double x, uint32_t r) { return (double)Pol<PREC_F32>::cvt(x, r); }
+};
+
+// FP32 mode, kernel G: the same FP32-rounded operands (W as kernel U stored
+// it, the trace rounded with the same stochastic bits) widened to FP64 in LDS
+// and accumulated on the FP64 MFMA, with FP64 partials per split.  FP32
+// accumulation over a split of tens of thousands of bins leaves a random-walk
+// error of ~1e-5 of the lambda term, which near the maximum of L is a large
+// part of the small gradient.
+constexpr int PREC_F32G = 17;
+template <> struct Pol<PREC_F32G> {
+  using in_t = double;
+  using c_t = double;
+  using w_t = float;
+  using gp_t = double;
+  using acc_t = f64x4;
+  using frag_t = f64x2;
+  static constexpr int MB = 16, EPL = 2, NACC = 4;
+  __device__ static inline void mma(acc_t& c, frag_t a, frag_t b) { Pol<PREC_F64>::mma(c, a, b); }
+  __device__ static inline int row(int r, int lane) { return Pol<PREC_F64>::row(r, lane); }
+  __device__ static inline int col(int lane) { return Pol<PREC_F64>::col(lane); }
   __device__ static inline in_t cvt(double x, uint32_t r) { return (double)Pol<PREC_F32>::cvt(x, r); }
 };
 
@@ -464,7 +486,9 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
   using frag_t = typename P::frag_t;
   using acc_t = typename P::acc_t;
   using T = c_t;
-  static_assert(sizeof(w_t) == sizeof(in_t), "W is staged as the A operand");
+  static_assert(sizeof(w_t) == sizeof(in_t) || 2 * sizeof(w_t) == sizeof(in_t),
+                "W is staged as the A operand, as is or widened to the operand type");
+  constexpr bool WIDEN = sizeof(w_t) != sizeof(in_t);
   constexpr int NW = WGM * WGN;
   constexpr int NT = NW * 64;
   constexpr int BK = 64;                               // bins per step (one subtile)
@@ -501,7 +525,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
 #pragma unroll
       for (int r = 0; r < P::NACC; ++r) acc[a][b][r] = 0;
 
-  constexpr int RP = BK * sizeof(in_t) / 16;   // 16-byte pieces per row
+  constexpr int RP = BK * sizeof(w_t) / 16;    // 16-byte pieces of W per row
   constexpr int APIECES = BI * RP;
   constexpr int APT = (APIECES + NT - 1) / NT;
   i32x4 areg[APT];
@@ -521,7 +545,16 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm2(Gemm2Args g) {
       int piece = tid + q * NT;
       if (piece < APIECES) {
         int r = piece / RP, c16 = piece % RP;
-        *(i32x4*)(As + r * ROWB + c16 * 16) = areg[q];
+        if constexpr (WIDEN) {
+          const float* f = (const float*)&areg[q];
+          in_t* d = (in_t*)(As + r * ROWB + c16 * 32);
+          d[0] = (in_t)f[0];
+          d[1] = (in_t)f[1];
+          d[2] = (in_t)f[2];
+          d[3] = (in_t)f[3];
+        } else {
+          *(i32x4*)(As + r * ROWB + c16 * 16) = areg[q];
+        }
       }
     }
   };
@@ -660,12 +693,12 @@ hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st) 
 hipError_t launch_gemm2(int prec, int tile, const Gemm2Args& a, hipStream_t st) {
   if (a.ev.pw) {
     if (prec == PREC_F64) return run_gemm2<PREC_F64, 128, 128, 2, 2, 1, true>(a, st);
-    if (prec == PREC_F32) return run_gemm2<PREC_F32, 128, 128, 2, 4, 2, true>(a, st);
+    if (prec == PREC_F32) return run_gemm2<PREC_F32G, 128, 128, 2, 2, 1, true>(a, st);
     return hipErrorInvalidValue;
   }
   switch (prec) {
     case PREC_F64: return run_gemm2<PREC_F64, 128, 128, 2, 2, 1>(a, st);
-    case PREC_F32: return run_gemm2<PREC_F32, 128, 128, 2, 4, 2>(a, st);
+    case PREC_F32: return run_gemm2<PREC_F32G, 128, 128, 2, 2, 1>(a, st);
     case PREC_BF16:
       if (tile == 128) return run_gemm2<PREC_BF16, 128, 128, 2, 4, 2>(a, st);
       return run_gemm2<PREC_BF16, 256, 256, 2, 4, 2>(a, st);

@@ -500,7 +500,7 @@ int grid_for(int64_t n, int threads) {
 hipError_t launch_gp_reduce(int prec, const void* Gp, int n_splits, int64_t Np, double* G64,
                             int first, hipStream_t st) {
   const int64_t n = Np * Np;
-  if (prec == PREC_F64)
+  if (prec == PREC_F64 || prec == PREC_F32)  // FP64 partials in both modes
     hipLaunchKernelGGL(k_gp_reduce_d, dim3(grid_for(n, 256)), dim3(256), 0, st, (const double*)Gp,
                        n_splits, n, G64, first);
   else

@@ -544,7 +544,7 @@ glmr_status ensure_workspace(glmr_ctx* c, bool want_grad, bool want_tau) {
     if (!c->gJ) TRY(dalloc(c, c->gJ, (size_t)Np * Np));
     if (!c->G64) TRY(dalloc(c, c->G64, (size_t)Np * Np));
     if (!c->Gp) {
-      const size_t gb = c->prec == PREC_F64 ? 8 : 4;
+      const size_t gb = (c->prec == PREC_F64 || c->prec == PREC_F32) ? 8 : 4;
       void* p = nullptr;
       TRY(dalloc(c, (unsigned char*&)p, (size_t)c->max_splits * Np * Np * gb));
       c->Gp = p;

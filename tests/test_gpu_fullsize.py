@@ -4,12 +4,12 @@ autotuned tile shapes), on sampled rows that the FP64 oracle evaluates over
 the whole recording: L is separable over rows (Sec. 2.2), so L_i, dL/dmu_i and
 the full row dL/dJ_i. of a few neurons are exact references at any N.
 
-L_i is compared at the simulated parameters, the gradient at theta = 0.  At
-the simulated parameters of a 3.6e6-bin recording the gradient is nearly
-zero (they are close to the maximum), a small difference of the spike term
-and the lambda term; the FP32 mode's lambda term is accumulated in FP32 over
-time splits of 32768 bins (relative error ~1e-5 of the term), which is 8.8e-4
-of that small difference.  At theta = 0 the gradient is not a cancellation.
+L_i and the gradient rows are compared at the simulated parameters and at
+theta = 0.  At the simulated parameters of a 3.6e6-bin recording the gradient
+is nearly zero (they are close to the maximum), a small difference of the
+spike term and the lambda term, which makes it the sensitive point: an FP32
+accumulation of the lambda term over long time splits (~1e-5 of the term)
+showed there as a 9e-4 error, hence the FP64 accumulation of kernel G.
 Needs an MI355X; about a minute and a half of host time for the oracle.
 """
 import numpy as np
@@ -51,18 +51,22 @@ def test_full_size_sampled_rows(tmp_path):
             ctx.set_params(J, rec.mu)
             ctx.autotune(str(tmp_path / "tune.txt"))
         ctx.set_params(J, rec.mu)
-        r = ctx.eval(grad=False)
+        r = ctx.eval(grad=True)
         ctx.set_params(Z, np.zeros(N))
         r0 = ctx.eval(grad=True)
         q = ctx.query()
         ctx.close()
         assert q["trace_resident"] == (prec != "fp32")
         rl = np.abs(r["ll_rows"][ROWS] - ref["ll_rows"]) / np.abs(ref["ll_rows"])
+        gt = np.concatenate([r["gmu"][ROWS], r["gJ"][ROWS].ravel()])
+        gtr = np.concatenate([ref["gmu"], ref["gJ"].ravel()])
+        rgt = np.linalg.norm(gt - gtr) / np.linalg.norm(gtr)
         z = refs["zero"]
         g = np.concatenate([r0["gmu"][ROWS], r0["gJ"][ROWS].ravel()])
         gr = np.concatenate([z["gmu"], z["gJ"].ravel()])
         rg = np.linalg.norm(g - gr) / np.linalg.norm(gr)
         rl0 = np.abs(r0["ll_rows"][ROWS] - z["ll_rows"]) / np.abs(z["ll_rows"])
-        print(f"[full {prec}] max rel L_i {rl.max():.3e} (theta = 0: {rl0.max():.3e}), rel grad rows at 0 {rg:.3e}",
-              flush=True)
-        assert rl.max() <= TOL[prec][0] and rl0.max() <= TOL[prec][0] and rg <= TOL[prec][1]
+        print(f"[full {prec}] max rel L_i {rl.max():.3e} (theta = 0: {rl0.max():.3e}), rel grad rows "
+              f"{rgt:.3e} (theta = 0: {rg:.3e})", flush=True)
+        assert rl.max() <= TOL[prec][0] and rl0.max() <= TOL[prec][0]
+        assert rgt <= TOL[prec][1] and rg <= TOL[prec][1]
