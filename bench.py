@@ -34,8 +34,10 @@ HBM_PEAK = 8.0e12
 
 
 def gemm_source_hash() -> str:
+    """Hash of the sources of the resident-trace kernels U and G (the kernels
+    the committed counter summary covers)."""
     h = hashlib.sha1()
-    for f in ("gemm.hip", "gemm_res.hip", "common.h"):
+    for f in ("gemm_res.hip", "common.h"):
         with open(os.path.join(ROOT, "paper_1502_04993_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
