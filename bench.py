@@ -276,7 +276,7 @@ def bench_events(args, G, torch):
     slots are the intervals between ~2.7e7 network events.  A step is one
     evaluation; value = slots * N^2 / (seconds per step)."""
     import synth
-    prec = args.precision if args.precision in ("fp64", "fp32") else "fp64"
+    prec = args.precision if args.precision in ("fp64", "fp32", "bf16") else "fp64"
     rec = synth.cached("config2", seed=0, B=args.bins)
     N = rec.n_neurons
     times, neu = synth.event_times(rec, seed=0)
@@ -298,14 +298,14 @@ def bench_events(args, G, torch):
     ms_total, launches = kt[dom]
     per_launch_s = ms_total / 1e3 / launches
     achieved = 2.0 * N * N * slots / launches / per_launch_s
-    # kernel U runs on the FP64 MFMA in both modes; kernel G on the FP32 one in FP32 mode
-    peak = PEAK["fp32"] if (prec == "fp32" and dom == "kernel_G") else PEAK["fp64"]
+    # FP64 and FP32 modes run both contractions on the FP64 MFMA; BF16 on the BF16 one
+    peak = PEAK["bf16"] if prec == "bf16" else PEAK["fp64"]
     units = float(slots) * N * N
     out = {
         "metric": "continuous-time LL+grad throughput (slots*N^2/s) at N=1000",
         "value": units / sec, "unit": "slots*N^2/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32"}[prec],
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[prec],
         "data": "synthetic",
         "config": {"workload": "balanced_n1000_indeg100_t3600s_event_grid", "n_neurons": N,
                    "n_events": int(times.shape[0]), "n_slots": slots, "precision": prec,

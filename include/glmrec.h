@@ -101,8 +101,9 @@ typedef struct {
   int32_t trace;       /* where the BF16 trace lives (glmr_trace_mode); other
                           precisions always rebuild it inside the contractions */
   int32_t time_mode;   /* glmr_time_mode: GLMR_TIME_EVENTS for continuous time
-                          (then n_bins = glmr_event_slots(...), precision FP64 or
-                          FP32, dt is not used) */
+                          (then n_bins = glmr_event_slots(...), precision FP64,
+                          FP32 or BF16 (the trace rebuilt inside the
+                          contractions), dt is not used) */
 } glmr_config;
 
 typedef enum { GLMR_TIME_GRID = 0, GLMR_TIME_EVENTS = 1 } glmr_time_mode;

@@ -278,13 +278,13 @@ class Context:
 
     @classmethod
     def from_events(cls, n_neurons: int, times, neurons, T0: float, T1: float, precision: str = "fp64",
-                    max_gap: float = 0.0, device: int = 0, stream=None, chunk_bins: int = 0):
+                    max_gap: float = 0.0, device: int = 0, stream=None, chunk_bins: int = 0, tile_n: int = 0):
         """Continuous-time context of spike times (seconds, host arrays sorted by
         (time, neuron)) on [T0, T1); the spikes are set, the kernel is not."""
         times = np.ascontiguousarray(times, dtype=np.float64)
         neurons = np.ascontiguousarray(neurons, dtype=np.int32)
         slots = glmr_event_slots(times, T0, T1, max_gap)
-        c = cls(n_neurons, slots, (T1 - T0) / slots, precision, device, stream, chunk_bins,
+        c = cls(n_neurons, slots, (T1 - T0) / slots, precision, device, stream, chunk_bins, tile_n,
                 time_mode="events")
         c.T0, c.T1, c.max_gap = float(T0), float(T1), float(max_gap)
         c.set_spike_times(times, neurons, T0, T1, max_gap)

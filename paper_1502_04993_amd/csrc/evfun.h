@@ -184,4 +184,44 @@ GLMR_HD inline void interval(double D, double delta, double* F, double* H) {
   interval(D, slot_consts(delta), F, H);
 }
 
+// The same in FP32 for the BF16 mode (whose potential D is an FP32 sum of
+// BF16 products): the short-interval branch in FP32 arithmetic, every other
+// interval through the FP64 evaluation.  Relative error of the FP32 branch a
+// few units of 2^-24.
+struct SlotF {
+  float delta, eh, c1, c2, c3, c4;
+};
+
+GLMR_HD inline SlotF slot_consts_f(const Slot& q) {
+  SlotF f;
+  f.delta = (float)q.delta;
+  f.eh = (float)q.eh;
+  f.c1 = (float)q.c1;
+  f.c2 = (float)q.c2;
+  f.c3 = (float)q.c3;
+  f.c4 = (float)q.c4;
+  return f;
+}
+
+GLMR_HD inline void interval_f(float D, const Slot& q, const SlotF& f, double* F, double* H) {
+  const float u = D * f.eh;
+  if (f.delta > 0.0f && f.delta * fmaxf(1.0f, fabsf(u)) <= 0.1f) {
+    const float T2 = u * (1.0f + u);
+    const float T4 = u * (1.0f + u * (7.0f + u * (6.0f + u)));
+    const float T6 = u * (1.0f + u * (31.0f + u * (90.0f + u * (65.0f + u * (15.0f + u)))));
+    const float T8 =
+        u * (1.0f + u * (127.0f + u * (966.0f + u * (1701.0f + u * (1050.0f + u * (266.0f + u * (28.0f + u)))))));
+    const float Q2 = 1.0f + u * (3.0f + u);
+    const float Q4 = 1.0f + u * (15.0f + u * (25.0f + u * (10.0f + u)));
+    const float Q6 = 1.0f + u * (63.0f + u * (301.0f + u * (350.0f + u * (140.0f + u * (21.0f + u)))));
+    const float Q8 =
+        1.0f + u * (255.0f + u * (3025.0f + u * (7770.0f + u * (6951.0f + u * (2646.0f + u * (462.0f + u * (36.0f + u)))))));
+    const float g = f.delta * expf(u);
+    *F = (double)(g * (1.0f + (f.c1 * T2 + (f.c2 * T4 + (f.c3 * T6 + f.c4 * T8)))));
+    *H = (double)(g * f.eh * (1.0f + (f.c1 * Q2 + (f.c2 * Q4 + (f.c3 * Q6 + f.c4 * Q8)))));
+    return;
+  }
+  interval((double)D, q, F, H);
+}
+
 }  // namespace glmr_ev

@@ -39,7 +39,7 @@
 // the bin and the column only, so both contractions see the identical rounded
 // trace.  Rounded values are unbiased and their errors average out over t.
 //
-// Event grid (continuous time, FP64 and FP32 modes): the bins are the slots
+// Event grid (continuous time, FP64, FP32 and BF16 modes): the bins are the slots
 // between network events, a^m and a^-(b+1) come from the per-slot tables
 // (pw, ainv relative to the subtile's first slot), and kernel U's epilogue
 // takes the closed forms of the interval integrals instead of exp: with
@@ -52,6 +52,8 @@
 // Pipelining: the J (or W) tile of the next step is fetched into registers
 // and the trace tile of the next step is rebuilt into the second LDS buffer
 // while the MFMAs of the current step run; one barrier per step.
+#include <type_traits>
+
 #include "common.h"
 #include "evfun.h"
 
@@ -178,6 +180,9 @@ template <> __device__ inline double tab_ainv<double>(const Tables* t, int b) { 
 template <> __device__ inline float tab_ainv<float>(const Tables* t, int b) { return t->ainv32[b]; }
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// the per-slot factor pw as the trace arithmetic of the mode holds it
+template <typename T> __device__ inline T pw_of(double pw) { return (T)pw; }
 
 constexpr uint32_t SR_T = 0x9E3779B9u, SR_J = 0x6C8E9CF5u;
 
@@ -405,13 +410,18 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
     // time, lanes over 64 consecutive slots: one table load per lane, the
     // accumulators die block by block, W stores are contiguous, and the
     // branches of the integrals follow one neuron's potential through time.
-    static_assert(P::MB == 16 && WN == 64, "event-grid epilogue expects the FP64 16x16 tile layout");
-    double* stage = (double*)smem + wave * (P::MB * WN);
+    static_assert(WN == 64, "event-grid epilogue: a wave's tile is 64 slots wide");
+    using st_t = typename std::remove_reference<decltype(acc[0][0][0])>::type;  // the accumulator type
+    static_assert((size_t)NW * P::MB * WN * sizeof(st_t) <= (size_t)DB * (ABUF + BBUF),
+                  "event-grid epilogue: the staged blocks fit in the operand buffers");
+    st_t* stage = (st_t*)smem + wave * (P::MB * WN);
     const int tl = wn * WN + lane;
     const bool valid = (tt0 + tl) < g.B;
     const double pwd = g.ev.pw[tt0 + tl];
+    const double pwm = (double)pw_of<T>(pwd);  // the factor the stored W' carries
     // zero length for padded slots: both integrals vanish
     const glmr_ev::Slot sc = glmr_ev::slot_consts(valid ? g.ev.delta[tt0 + tl] : 0.0);
+    const glmr_ev::SlotF scf = glmr_ev::slot_consts_f(sc);
 #pragma unroll
     for (int a = 0; a < WMB; ++a) {
       __syncthreads();
@@ -419,14 +429,17 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
       for (int b = 0; b < WNB; ++b)
 #pragma unroll
         for (int r = 0; r < P::NACC; ++r)
-          stage[P::row(r, lane) * WN + b * P::MB + P::col(lane)] = (double)acc[a][b][r];
+          stage[P::row(r, lane) * WN + b * P::MB + P::col(lane)] = acc[a][b][r];
       __syncthreads();
 #pragma unroll 2
       for (int e = 0; e < P::MB; ++e) {
         const int il = wm * WM + a * P::MB + e;
         double F, H;
-        glmr_ev::interval(pwd * stage[e * WN + lane], sc, &F, &H);
-        W[(i0 + il) * g.L + (tl0 + tl)] = (w_t)(H * pwd);
+        if constexpr (sizeof(st_t) == 4)  // BF16 mode: FP32 potential, FP32 short-interval branch
+          glmr_ev::interval_f((float)pwd * stage[e * WN + lane], sc, scf, &F, &H);
+        else
+          glmr_ev::interval(pwd * (double)stage[e * WN + lane], sc, &F, &H);
+        W[(i0 + il) * g.L + (tl0 + tl)] = (w_t)(H * pwm);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) F += __shfl_xor(F, off, 64);
         if (lane == 0) red[wn * BI + il] = F;
@@ -674,10 +687,14 @@ hipError_t run_gemm2(const Gemm2Args& a, hipStream_t st) {
 // Tile shapes: BI x BT for kernel U/V, BI x BJ for kernel G.  `tile` is the
 // neuron tile of the context (the padding unit of N).
 hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st) {
-  if (a.ev.pw) {  // event grid: FP64 and FP32 modes, likelihood kernel only
+  if (a.ev.pw) {  // event grid: FP64, FP32 and BF16 modes, likelihood kernel only
     if (a.mode != 0) return hipErrorInvalidValue;
     if (prec == PREC_F64) return run_gemm1<PREC_F64, 128, 128, 2, 2, 2, true, 256>(a, st);
     if (prec == PREC_F32) return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2, true, 256>(a, st);
+    if (prec == PREC_BF16) {
+      if (tile == 128) return run_gemm1<PREC_BF16, 128, 256, 2, 4, 2, true>(a, st);
+      return run_gemm1<PREC_BF16, 256, 256, 2, 4, 2, true>(a, st);
+    }
     return hipErrorInvalidValue;
   }
   switch (prec) {
@@ -694,6 +711,10 @@ hipError_t launch_gemm2(int prec, int tile, const Gemm2Args& a, hipStream_t st) 
   if (a.ev.pw) {
     if (prec == PREC_F64) return run_gemm2<PREC_F64, 128, 128, 2, 2, 1, true>(a, st);
     if (prec == PREC_F32) return run_gemm2<PREC_F32G, 128, 128, 2, 2, 1, true>(a, st);
+    if (prec == PREC_BF16) {
+      if (tile == 128) return run_gemm2<PREC_BF16, 128, 128, 2, 4, 2, true>(a, st);
+      return run_gemm2<PREC_BF16, 256, 256, 2, 4, 2, true>(a, st);
+    }
     return hipErrorInvalidValue;
   }
   switch (prec) {

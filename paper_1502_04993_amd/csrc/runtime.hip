@@ -1514,8 +1514,8 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
   if (cfg->precision == GLMR_FP8 && cfg->trace == GLMR_TRACE_RECOMPUTE)
     return GLMR_EINVAL;  // FP8 contractions exist only on the resident trace
   if (cfg->time_mode != GLMR_TIME_GRID && cfg->time_mode != GLMR_TIME_EVENTS) return GLMR_EINVAL;
-  if (cfg->time_mode == GLMR_TIME_EVENTS && cfg->precision != GLMR_FP64 && cfg->precision != GLMR_FP32)
-    return GLMR_EINVAL;  // the event grid's contractions run in FP64 or FP32
+  if (cfg->time_mode == GLMR_TIME_EVENTS && cfg->precision == GLMR_FP8)
+    return GLMR_EINVAL;  // the event grid's contractions run in FP64, FP32 or BF16
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -1774,8 +1774,8 @@ glmr_status glmr_set_spike_times(glmr_ctx* c, const double* times, const int32_t
 
 namespace {
 glmr_status reject_event_grid_precision(glmr_ctx* c, int prec) {
-  if (c->evm && prec != GLMR_FP64 && prec != GLMR_FP32)
-    return fail(c, GLMR_EINVAL, "the event grid is evaluated in FP64 or FP32");
+  if (c->evm && prec == GLMR_FP8)
+    return fail(c, GLMR_EINVAL, "the event grid is evaluated in FP64, FP32 or BF16");
   return GLMR_OK;
 }
 }  // namespace

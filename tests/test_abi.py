@@ -42,7 +42,7 @@ def test_create_rejects_bad_config_without_device():
     for kw in (dict(n_neurons=0), dict(n_bins=0), dict(dt=0.0), dict(dt=float("nan")),
                dict(precision=7), dict(tile_n=100), dict(chunk_bins=-1), dict(trace=3),
                dict(precision=3, trace=2),  # FP8 exists only on the resident trace
-               dict(time_mode=2), dict(time_mode=1, precision=2), dict(time_mode=1, precision=3)):
+               dict(time_mode=2), dict(time_mode=1, precision=3)):
         args = dict(n_neurons=10, n_bins=100, dt=0.001, chunk_bins=0, precision=1, device=0,
                     stream=None, tile_n=0, trace=0, time_mode=0)
         args.update(kw)

@@ -7,7 +7,9 @@ regular grid (the same arithmetic per slot; the interval integrals are FP64
 in both modes):
   FP64: L 1e-12, gradient 1e-10
   FP32: L 1e-10 sqrt(2e6 / (slots N)) (stochastically rounded FP32 trace),
-        gradient 1e-4 (FP32 accumulation of the trace integral per split).
+        gradient 1e-4.
+  BF16: L 1e-3, gradient 1e-3 (trace, J and the weights in BF16, the interval
+        integrals in FP64 from the FP32-accumulated potential).
 """
 import math
 
@@ -19,7 +21,7 @@ from oracle import glm_oracle as O
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4)}
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4), "bf16": (1e-3, 1e-3)}
 
 
 def _G():
@@ -58,14 +60,21 @@ def _compare(r, ref, prec, slots, N, label):
 
 
 def _round(J, prec):
+    if prec == "bf16":
+        import torch
+        return torch.tensor(J).to(torch.bfloat16).to(torch.float64).numpy()
     return J.astype(np.float32).astype(np.float64) if prec == "fp32" else J
 
 
 @pytest.mark.parametrize("prec,N,B,chunk", [("fp64", 70, 30_000, 0), ("fp32", 70, 30_000, 0),
-                                            ("fp64", 150, 12_000, 4096), ("fp32", 150, 12_000, 4096)])
+                                            ("bf16", 70, 30_000, 0),
+                                            ("fp64", 150, 12_000, 4096), ("fp32", 150, 12_000, 4096),
+                                            ("bf16", 150, 12_000, 4096), ("bf16", 300, 8_000, 0),
+                                            ("bf16", 400, 6_000, 0)])
 def test_event_grid_matches_oracle(prec, N, B, chunk):
     # N = 150 pads to two neuron tiles; chunk_bins = 4096 splits the slots
-    # into several chunks with a ragged last one
+    # into several chunks with a ragged last one; BF16 at N = 400 runs the
+    # 256-neuron tiles (the others 128)
     rec = synth.balanced(N=N, B=B, in_frac=0.3, seed=91 + N)
     times, neu = synth.event_times(rec, seed=5)
     T0, T1 = 0.0, rec.T
@@ -146,7 +155,7 @@ def test_event_grid_rejections():
     with pytest.raises(G.GlmrError):
         c.eval(want_tau=True)
     with pytest.raises(G.GlmrError):
-        c.set_precision("bf16")
+        c.set_precision("fp8")
     c.close()
     # a run of 64 slots longer than 600 tau is refused when the tables are built
     sparse = np.array([0.0, 50.0, 100.0])
