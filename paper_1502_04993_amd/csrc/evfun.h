@@ -185,40 +185,50 @@ GLMR_HD inline void interval(double D, double delta, double* F, double* H) {
 }
 
 // The same in FP32 for the BF16 mode (whose potential D is an FP32 sum of
-// BF16 products): the short-interval branch in FP32 arithmetic, every other
-// interval through the FP64 evaluation.  Relative error of the FP32 branch a
-// few units of 2^-24.
+// BF16 products): 6-point Gauss-Legendre in s on [0, delta],
+//   F = delta/2 sum_k w_k exp(D e^{-s_k}),  H = delta/2 sum_k w_k e^{-s_k} exp(D e^{-s_k}),
+// in FP32 for delta <= 0.5 and |D| delta <= 1 (the integrand is entire and
+// varies by at most a factor e over the interval; relative error a few units
+// of 2^-24), every other interval through the FP64 evaluation.  The nodes
+// e^{-s_k} depend on the interval only.
 struct SlotF {
-  float delta, eh, c1, c2, c3, c4;
+  float half;     // delta / 2 (0: empty interval)
+  float e[6];     // e^{-s_k}
+  float w[6];     // weights times delta / 2
+  bool ok;        // delta <= 0.5
 };
 
 GLMR_HD inline SlotF slot_consts_f(const Slot& q) {
+  const double xn[3] = {2.38619186083196932e-01, 6.61209386466264482e-01, 9.32469514203152050e-01};
+  const double wn[3] = {4.67913934572691370e-01, 3.60761573048138939e-01, 1.71324492379169746e-01};
   SlotF f;
-  f.delta = (float)q.delta;
-  f.eh = (float)q.eh;
-  f.c1 = (float)q.c1;
-  f.c2 = (float)q.c2;
-  f.c3 = (float)q.c3;
-  f.c4 = (float)q.c4;
+  const double h = 0.5 * q.delta;
+  f.half = (float)h;
+  f.ok = q.delta > 0.0 && q.delta <= 0.5;
+  for (int k = 0; k < 3; ++k) {
+    f.e[2 * k] = (float)exp(-h * (1.0 - xn[k]));
+    f.e[2 * k + 1] = (float)exp(-h * (1.0 + xn[k]));
+    f.w[2 * k] = f.w[2 * k + 1] = (float)(h * wn[k]);
+  }
   return f;
 }
 
 GLMR_HD inline void interval_f(float D, const Slot& q, const SlotF& f, double* F, double* H) {
-  const float u = D * f.eh;
-  if (f.delta > 0.0f && f.delta * fmaxf(1.0f, fabsf(u)) <= 0.1f) {
-    const float T2 = u * (1.0f + u);
-    const float T4 = u * (1.0f + u * (7.0f + u * (6.0f + u)));
-    const float T6 = u * (1.0f + u * (31.0f + u * (90.0f + u * (65.0f + u * (15.0f + u)))));
-    const float T8 =
-        u * (1.0f + u * (127.0f + u * (966.0f + u * (1701.0f + u * (1050.0f + u * (266.0f + u * (28.0f + u)))))));
-    const float Q2 = 1.0f + u * (3.0f + u);
-    const float Q4 = 1.0f + u * (15.0f + u * (25.0f + u * (10.0f + u)));
-    const float Q6 = 1.0f + u * (63.0f + u * (301.0f + u * (350.0f + u * (140.0f + u * (21.0f + u)))));
-    const float Q8 =
-        1.0f + u * (255.0f + u * (3025.0f + u * (7770.0f + u * (6951.0f + u * (2646.0f + u * (462.0f + u * (36.0f + u)))))));
-    const float g = f.delta * expf(u);
-    *F = (double)(g * (1.0f + (f.c1 * T2 + (f.c2 * T4 + (f.c3 * T6 + f.c4 * T8)))));
-    *H = (double)(g * f.eh * (1.0f + (f.c1 * Q2 + (f.c2 * Q4 + (f.c3 * Q6 + f.c4 * Q8)))));
+  if (f.ok && fabsf(D) * (2.0f * f.half) <= 1.0f) {
+    float sf = 0.0f, sh = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float v = f.w[k] * expf(D * f.e[k]);
+      sf += v;
+      sh += v * f.e[k];
+    }
+    *F = (double)sf;
+    *H = (double)sh;
+    return;
+  }
+  if (!(q.delta > 0.0)) {
+    *F = 0.0;
+    *H = 0.0;
     return;
   }
   interval((double)D, q, F, H);
