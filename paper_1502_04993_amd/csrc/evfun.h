@@ -13,7 +13,7 @@
 //
 // F by branch (every branch loses at most a small constant factor of FP64
 // precision):
-//  * short intervals, delta max(1, |u|) <= 0.1 with u = D e^{-delta/2} (the
+//  * short intervals, delta max(1, |u|) <= 0.25 with u = D e^{-delta/2} (the
 //    potential offset at the midpoint; nearly every interval between the
 //    events of a large network): Taylor expansion of the integrand about the
 //    midpoint.  With w = D e^{-s}, d/ds = -w d/dw, so the even derivatives of
@@ -21,8 +21,9 @@
 //    sum_k S(n, k) w^k, S the Stirling numbers of the second kind), and those
 //    of e^{-s} e^w are e^{-s} Q_2k(w) e^w with Q_n = T_{n+1}(w) / w; the
 //    midpoint rule's moments are delta^{2k+1} / (4^k (2k+1)!).  Terms up to
-//    k = 4; the first omitted one is below 3e-6 (delta max(1, |u|))^10
-//    relative.  One exponential, no loop.
+//    k = 6; the first omitted one is below Bell(15) x^14 / (4^7 15!) =
+//    2.4e-16 relative at x = delta max(1, |u|) = 0.25.  One exponential, no
+//    loop.
 //  * |D| <= 2: the series of Ei difference term by term,
 //      F = delta + (1 - xi) sum_{n>=1} D^n S_n / (n n!),  S_n = 1 + xi + ... + xi^{n-1},
 //    which keeps 1 - xi^n = (1 - xi) S_n exact for short intervals (no
@@ -107,7 +108,7 @@ GLMR_HD inline double gl16_weight(int k) {
 // Quantities of an interval that depend on its length only (a kernel lane
 // keeps one slot for many neurons and computes them once).
 struct Slot {
-  double delta, eh, c1, c2, c3, c4, e1, xi;
+  double delta, eh, c1, c2, c3, c4, c5, c6, e1, xi;
 };
 
 GLMR_HD inline Slot slot_consts(double delta) {
@@ -119,6 +120,8 @@ GLMR_HD inline Slot slot_consts(double delta) {
   q.c2 = d2 * d2 * (1.0 / 1920.0);
   q.c3 = d2 * d2 * d2 * (1.0 / 322560.0);
   q.c4 = d2 * d2 * d2 * d2 * (1.0 / 92897280.0);
+  q.c5 = q.c4 * d2 * (1.0 / 440.0);   // delta^10 / (4^5 11!)
+  q.c6 = q.c5 * d2 * (1.0 / 624.0);   // delta^12 / (4^6 13!)
   q.e1 = -expm1(-delta);  // 1 - xi, exact for short intervals
   q.xi = exp(-delta);
   return q;
@@ -134,7 +137,7 @@ GLMR_HD inline void interval(double D, const Slot& q, double* F, double* H) {
     return;
   }
   const double u = D * q.eh;
-  if (delta * fmax(1.0, fabs(u)) <= 0.1) {
+  if (delta * fmax(1.0, fabs(u)) <= 0.25) {
     const double T2 = u * (1.0 + u);
     const double T4 = u * (1.0 + u * (7.0 + u * (6.0 + u)));
     const double T6 = u * (1.0 + u * (31.0 + u * (90.0 + u * (65.0 + u * (15.0 + u)))));
@@ -145,9 +148,21 @@ GLMR_HD inline void interval(double D, const Slot& q, double* F, double* H) {
     const double Q6 = 1.0 + u * (63.0 + u * (301.0 + u * (350.0 + u * (140.0 + u * (21.0 + u)))));
     const double Q8 =
         1.0 + u * (255.0 + u * (3025.0 + u * (7770.0 + u * (6951.0 + u * (2646.0 + u * (462.0 + u * (36.0 + u)))))));
+    const double T10 =
+        u * (1.0 + u * (511.0 + u * (9330.0 + u * (34105.0 + u * (42525.0 + u * (22827.0 + u * (5880.0 +
+        u * (750.0 + u * (45.0 + u)))))))));
+    const double T12 =
+        u * (1.0 + u * (2047.0 + u * (86526.0 + u * (611501.0 + u * (1379400.0 + u * (1323652.0 + u * (627396.0 +
+        u * (159027.0 + u * (22275.0 + u * (1705.0 + u * (66.0 + u)))))))))));
+    const double Q10 =
+        1.0 + u * (1023.0 + u * (28501.0 + u * (145750.0 + u * (246730.0 + u * (179487.0 + u * (63987.0 +
+        u * (11880.0 + u * (1155.0 + u * (55.0 + u)))))))));
+    const double Q12 =
+        1.0 + u * (4095.0 + u * (261625.0 + u * (2532530.0 + u * (7508501.0 + u * (9321312.0 + u * (5715424.0 +
+        u * (1899612.0 + u * (359502.0 + u * (39325.0 + u * (2431.0 + u * (78.0 + u)))))))))));
     const double g = delta * exp(u);
-    *F = g * (1.0 + (q.c1 * T2 + (q.c2 * T4 + (q.c3 * T6 + q.c4 * T8))));
-    *H = g * q.eh * (1.0 + (q.c1 * Q2 + (q.c2 * Q4 + (q.c3 * Q6 + q.c4 * Q8))));
+    *F = g * (1.0 + (q.c1 * T2 + (q.c2 * T4 + (q.c3 * T6 + (q.c4 * T8 + (q.c5 * T10 + q.c6 * T12))))));
+    *H = g * q.eh * (1.0 + (q.c1 * Q2 + (q.c2 * Q4 + (q.c3 * Q6 + (q.c4 * Q8 + (q.c5 * Q10 + q.c6 * Q12))))));
     return;
   }
   const double e1 = q.e1, xi = q.xi;
@@ -213,6 +228,14 @@ GLMR_HD inline SlotF slot_consts_f(const Slot& q) {
   return f;
 }
 
+// the FP64 evaluation as a call (rare in the FP32 path; kept out of its registers)
+#if defined(__HIPCC__)
+__host__ __device__ __attribute__((noinline))
+#endif
+inline void interval_call(double D, double delta, double* F, double* H) {
+  interval(D, slot_consts(delta), F, H);
+}
+
 GLMR_HD inline void interval_f(float D, const Slot& q, const SlotF& f, double* F, double* H) {
   if (f.ok && fabsf(D) * (2.0f * f.half) <= 1.0f) {
     float sf = 0.0f, sh = 0.0f;
@@ -231,7 +254,7 @@ GLMR_HD inline void interval_f(float D, const Slot& q, const SlotF& f, double* F
     *H = 0.0;
     return;
   }
-  interval((double)D, q, F, H);
+  interval_call((double)D, q.delta, F, H);
 }
 
 }  // namespace glmr_ev
