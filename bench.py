@@ -12,8 +12,14 @@ tau, "trace": "resident"), otherwise ("--trace recompute", and in FP32/FP64)
 both contractions rebuild its tiles from the spike masks inside the step.
 The per-recording and per-tau set-up (spike ingest, carries, spike term,
 resident trace) runs once before the timed region and is reported as
-setup_ms; a short fit reports the ascent's iterations per second.
+setup_ms; after the timed evaluations the ascent reconstructs the network
+from J = 0 (reconstruct_s, with the misclassification rate of the fitted
+weights against the generating ones).
 value = B * N^2 / (seconds per step), in bins*N^2/s.
+
+Other workloads (--workload): batch64 (64 recordings evaluated together),
+events (the same recording in continuous time), reconstruct (BF16 ascent and
+FP32 polish, timed and classified).
 
 Prints one JSON line.  N > 1 GPUs is not supported (one-GPU build).
 """
@@ -139,7 +145,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 comparison line")
     ap.add_argument("--cpu-sample-bins", type=int, default=1_572_864)
-    ap.add_argument("--fit-iters", type=int, default=5)
+    ap.add_argument("--fit-iters", type=int, default=400,
+                    help="cap of the ascent from J = 0 timed after the evaluations (0: skip); "
+                         "the fitted weights are classified against the generating ones")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (a known-size "
                          "kernel for calibrating HBM byte counters)")
@@ -205,13 +213,19 @@ def main():
                 "issued_frac": achieved * (q["n_pad"] / N) ** 2 / peak,
                 "per_kernel_ms": {k: v[0] for k, v in kt.items()}}
 
-    # short fit from zero: the per-row L-BFGS ascent
+    # the reconstruction: per-row L-BFGS ascent from J = 0 to its stopping test,
+    # then the E/I/none classification of the fitted weights (Sec. 3.3)
     fit_info = None
     if args.fit_iters > 0:
+        from paper_1502_04993_amd.classify import classify, misclassification
         t0 = time.perf_counter()
         fr = ctx.fit(max_iter=args.fit_iters, from_zero=True)
-        fit_info = {"iters": fr["iters"], "evals": fr["evals"],
-                    "iters_per_s": fr["iters"] / (time.perf_counter() - t0)}
+        t_fit = time.perf_counter() - t0
+        Jf, _, _ = ctx.get_params()
+        m = misclassification(classify(Jf), rec.J)
+        fit_info = {"iters": fr["iters"], "evals": fr["evals"], "converged": fr["converged"],
+                    "rows_converged": fr["rows_converged"], "seconds": t_fit,
+                    "iters_per_s": fr["iters"] / t_fit, "mer": m["mer"], "mer_n2": m["mer_n2"]}
     ctx.close()
 
     extra = {}
@@ -248,6 +262,7 @@ def main():
         "setup_ms": setup * 1e3,
         "ll": r["ll"],
         "fit": fit_info,
+        "reconstruct_s": fit_info["seconds"] if fit_info else None,
     }
     out.update(extra)
     if not args.no_cpu:
