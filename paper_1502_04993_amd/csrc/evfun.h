@@ -127,6 +127,8 @@ GLMR_HD inline Slot slot_consts(double delta) {
   return q;
 }
 
+GLMR_HD inline void interval_long(double D, const Slot& q, double* F, double* H);
+
 // F and H of one interval of length q.delta (in units of tau) that starts with
 // potential offset D; delta = 0 gives 0 for both.
 GLMR_HD inline void interval(double D, const Slot& q, double* F, double* H) {
@@ -165,6 +167,17 @@ GLMR_HD inline void interval(double D, const Slot& q, double* F, double* H) {
     *H = g * q.eh * (1.0 + (q.c1 * Q2 + (q.c2 * Q4 + (q.c3 * Q6 + (q.c4 * Q8 + (q.c5 * Q10 + q.c6 * Q12))))));
     return;
   }
+  interval_long(D, q, F, H);
+}
+
+// Intervals past the short-interval branch (rare between the events of a
+// large network): a call, so that the kernels keep only the short branch in
+// their registers.
+#if defined(__HIPCC__)
+__host__ __device__ __attribute__((noinline))
+#endif
+inline void interval_long(double D, const Slot& q, double* F, double* H) {
+  const double delta = q.delta;
   const double e1 = q.e1, xi = q.xi;
   const double y = D * e1;
   *H = exp(D * xi) * e1 * (y == 0.0 ? 1.0 : expm1(y) / y);

@@ -689,8 +689,8 @@ hipError_t run_gemm2(const Gemm2Args& a, hipStream_t st) {
 hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st) {
   if (a.ev.pw) {  // event grid: FP64, FP32 and BF16 modes, likelihood kernel only
     if (a.mode != 0) return hipErrorInvalidValue;
-    if (prec == PREC_F64) return run_gemm1<PREC_F64, 128, 128, 2, 2, 2, true, 256>(a, st);
-    if (prec == PREC_F32) return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2, true, 256>(a, st);
+    if (prec == PREC_F64) return run_gemm1<PREC_F64, 128, 256, 2, 4, 2, true, 128>(a, st);
+    if (prec == PREC_F32) return run_gemm1<PREC_F32U, 128, 256, 2, 4, 2, true, 128>(a, st);
     if (prec == PREC_BF16) {
       if (tile == 128) return run_gemm1<PREC_BF16, 128, 256, 2, 4, 2, true>(a, st);
       return run_gemm1<PREC_BF16, 256, 256, 2, 4, 2, true>(a, st);
@@ -698,8 +698,8 @@ hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st) 
     return hipErrorInvalidValue;
   }
   switch (prec) {
-    case PREC_F64: return run_gemm1<PREC_F64, 128, 128, 2, 2, 2, false, 256>(a, st);
-    case PREC_F32: return run_gemm1<PREC_F32U, 128, 128, 2, 2, 2, false, 256>(a, st);
+    case PREC_F64: return run_gemm1<PREC_F64, 128, 256, 2, 4, 2, false, 128>(a, st);
+    case PREC_F32: return run_gemm1<PREC_F32U, 128, 256, 2, 4, 2, false, 128>(a, st);
     case PREC_BF16:
       if (tile == 128) return run_gemm1<PREC_BF16, 128, 256, 2, 4, 2>(a, st);
       return run_gemm1<PREC_BF16, 256, 256, 2, 4, 2>(a, st);
@@ -730,8 +730,8 @@ hipError_t launch_gemm2(int prec, int tile, const Gemm2Args& a, hipStream_t st) 
 // Tile sizes the runtime must respect (rows of the neuron tile, bins of the time tile).
 void gemm_tiles(int prec, int tile, int* bi1, int* bt1, int* bi2, int* bj2) {
   switch (prec) {
-    case PREC_F64: *bi1 = 128; *bt1 = 128; *bi2 = 128; *bj2 = 128; break;
-    case PREC_F32: *bi1 = 128; *bt1 = 128; *bi2 = 128; *bj2 = 128; break;
+    case PREC_F64: *bi1 = 128; *bt1 = 256; *bi2 = 128; *bj2 = 128; break;
+    case PREC_F32: *bi1 = 128; *bt1 = 256; *bi2 = 128; *bj2 = 128; break;
     default:
       if (tile == 128) { *bi1 = 128; *bt1 = 256; *bi2 = 128; *bj2 = 128; }
       else { *bi1 = 256; *bt1 = 256; *bi2 = 256; *bj2 = 256; }
