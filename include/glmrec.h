@@ -166,6 +166,15 @@ glmr_status glmr_set_spike_times(glmr_ctx* ctx, const double* times, const int32
  * Either output pointer may be NULL. */
 void glmr_ei_interval(double D, double delta, double* F, double* H);
 
+/* The same integrals as the BF16 event grid's resident kernels take them, in
+ * FP32 from an FP32 potential D, on the host, by the same code: the midpoint
+ * expansion (Touchard polynomials to h^6, within 4e-9 relative where
+ * delta max(1, |D e^{-delta/2}|) <= 0.25), else 6-point Gauss-Legendre where
+ * delta <= 0.5 and |D| delta <= 1, else the FP64 evaluation rounded.  The
+ * device's exponential differs from the host's by a few units of 2^-24.
+ * Either output pointer may be NULL. */
+void glmr_ei_interval_f32(float D, double delta, float* F, float* H);
+
 /* Kernel time constant tau (seconds) of h(t) = H(t) exp(-t/tau), Sec. 2.2.
  * Requires dt <= tau on the regular grid.  Computes the parameter-independent parts (the trace
  * carries at every 64-bin boundary and the spike term

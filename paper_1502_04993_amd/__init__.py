@@ -18,7 +18,7 @@ from ._lib import (GLMR_BF16, GLMR_DEVICE, GLMR_FP8, GLMR_FP32, GLMR_FP64, GLMR_
                    GLMR_NOT_CONVERGED, GlmrError, PRECISIONS)
 
 __all__ = ["Context", "Batch", "GlmrError", "glmr_create", "glmr_destroy", "glmr_set_spikes",
-           "glmr_event_slots", "glmr_set_spike_times", "glmr_ei_interval", "glmr_set_delays",
+           "glmr_event_slots", "glmr_set_spike_times", "glmr_ei_interval", "glmr_ei_interval_f32", "glmr_set_delays",
            "glmr_set_kernel", "glmr_set_precision", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
            "glmr_fit_defaults", "glmr_status_string", "glmr_last_error", "glmr_query",
            "glmr_batch_create", "glmr_batch_destroy", "glmr_batch_eval", "glmr_batch_get_grad",
@@ -111,6 +111,13 @@ def glmr_ei_interval(D, delta):
     """(F, H) of one event-grid interval, by the library's own code on the host."""
     F, H = ctypes.c_double(), ctypes.c_double()
     L.load().glmr_ei_interval(float(D), float(delta), ctypes.byref(F), ctypes.byref(H))
+    return F.value, H.value
+
+
+def glmr_ei_interval_f32(D, delta):
+    """(F, H) of one event-grid interval in FP32, as the resident BF16 kernels take it."""
+    F, H = ctypes.c_float(), ctypes.c_float()
+    L.load().glmr_ei_interval_f32(float(D), float(delta), ctypes.byref(F), ctypes.byref(H))
     return F.value, H.value
 
 

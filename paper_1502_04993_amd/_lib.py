@@ -64,6 +64,8 @@ SIGNATURES = {
     "glmr_set_spike_times": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_int32]),
     "glmr_ei_interval": (None, [ctypes.c_double, ctypes.c_double, _dp, _dp]),
+    "glmr_ei_interval_f32": (None, [ctypes.c_float, ctypes.c_double, ctypes.POINTER(ctypes.c_float),
+                                    ctypes.POINTER(ctypes.c_float)]),
     "glmr_set_kernel": (ctypes.c_int, [_vp, ctypes.c_double]),
     "glmr_set_delays": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64]),
     "glmr_set_precision": (ctypes.c_int, [_vp, ctypes.c_int32]),

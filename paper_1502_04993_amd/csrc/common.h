@@ -107,6 +107,7 @@ struct EvTableArgs {
   double tau;
   int64_t NS;
   double *pw, *ainv, *left, *delta, *asub;
+  float* gl;                    // [NS*64][16]: the FP32 evaluation's per-slot table (null: none)
   unsigned long long* maxspan;  // max over subtiles of the span / tau (double bits), zero on entry
 };
 hipError_t launch_ev_tables(const EvTableArgs& a, hipStream_t st);
@@ -237,6 +238,7 @@ struct ResXArgs {
   int64_t L;               // FP8: bins per scaling chunk (the evaluation's time chunk)
   unsigned* xmax;          // FP8: [ceil(Bp / L)] chunk maxima (float bits), zero on entry
   float* xscale;           // FP8: [ceil(Bp / L)] power-of-two chunk scales
+  EvSlots ev;              // event grid: per-slot decays (null on the regular grid)
 };
 hipError_t launch_build_x(const ResXArgs& a, hipStream_t st);
 hipError_t launch_build_x8(const ResXArgs& a, hipStream_t st);
@@ -252,6 +254,8 @@ struct ResUArgs {
   double* rowpart;         // [Bp/256][Np]
   const float* xscale;     // FP8: this chunk's trace scale (one value)
   const float* jscale;     // FP8: [Np] row scales of J
+  const float* evgl;       // event grid: [Bp][16] per-slot table of the FP32 integrals (null on the grid)
+  const double* evdelta;   // event grid: [Bp] interval lengths / tau
 };
 struct ResGArgs {
   const void* W;           // [Np][L] bf16

@@ -166,6 +166,13 @@ __global__ void k_ev_tables(EvTableArgs a) {
     a.ainv[k] = exp((tk1 - tb) * r);
     a.left[k] = exp(-(tk1 - tb) * r);
     a.delta[k] = (tk1 - tk) * r;
+    if (a.gl) {
+      float o[16];
+      glmr_ev::table_f((tk1 - tk) * r, o);
+      float4* d = (float4*)(a.gl + k * 16);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[q] = float4{o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]};
+    }
     if (k == k0) {
       const double span = (a.tslot[k0 + 64] - tb) * r;
       a.asub[k0 / 64] = exp(-span);
@@ -249,6 +256,13 @@ extern "C" glmr_status glmr_event_slots(const double* times, int64_t n, double T
 extern "C" void glmr_ei_interval(double D, double delta, double* F, double* H) {
   double f = 0.0, h = 0.0;
   glmr_ev::interval(D, delta, &f, &h);
+  if (F) *F = f;
+  if (H) *H = h;
+}
+
+extern "C" void glmr_ei_interval_f32(float D, double delta, float* F, float* H) {
+  float f = 0.0f, h = 0.0f;
+  glmr_ev::interval_f32(D, delta, &f, &h);
   if (F) *F = f;
   if (H) *H = h;
 }

@@ -270,4 +270,128 @@ GLMR_HD inline void interval_f(float D, const Slot& q, const SlotF& f, double* F
   interval_call((double)D, q.delta, F, H);
 }
 
+// FP32 exponential: the hardware's base-2 exponential on the device (a few
+// units of 2^-24, more for |x| >> 1 through the rounding of x log2 e), the
+// C library's on the host.
+GLMR_HD inline float exp_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __expf(x);
+#else
+  return expf(x);
+#endif
+}
+
+// The first tier of the FP32 evaluation (the resident BF16 trace): the
+// midpoint expansion of the short-interval branch above, to k = 3.  With
+// h = delta / 2 and u = D e^{-h},
+//   F = delta e^u sum_k T_2k(u) h^2k / (2k+1)!,
+//   H = delta e^{-h} e^u sum_k Q_2k(u) h^2k / (2k+1)!,   Q_n = T_{n+1} / u,
+// (the Touchard generating function exp(u (e^t - 1)) = sum_n T_n(u) t^n / n!
+// with t = -(s - h), odd powers of t integrating to zero).  Where
+// delta max(1, |u|) <= 0.25 the first omitted terms are below
+// Bell(8) 0.125^8 / 9! = 6.8e-10 (F) and Bell(9) 0.125^8 / 9! = 3.5e-9 (H)
+// relative (T_n(m) <= Bell(n) m^n for m >= 1, and both sums lie within
+// e^{+-0.14} of their first term, so relative means relative to the result).
+// The sums are polynomials in u whose coefficients depend on the interval
+// only, with delta and delta e^{-h} folded in: one exponential and two
+// degree-6 Horner evaluations per potential.  The 16 coefficients of an
+// interval (stage_f): [0..6] F / e^u = sum_j c_j u^j, [7] e^{-h},
+// [8..14] H / e^u = sum_j c_{8+j} u^j, [15] the bound on |u| (0.25 / delta,
+// negative where delta > 0.25, so that delta max(1, |u|) <= 0.25 reads
+// |u| <= [15]).
+GLMR_HD inline void stage_f(float delta, float emh, float* o) {
+  const float h = 0.5f * delta;
+  const float c2 = h * h * (1.0f / 6.0f);    // h^2 / 3!
+  const float c4 = 0.3f * c2 * c2;           // h^4 / 5!
+  const float c6 = c4 * c2 * (1.0f / 7.0f);  // h^6 / 7!
+  const float dq = delta * emh;
+  // T_0 = 1, T_2 = u + u^2, T_4 = u + 7u^2 + 6u^3 + u^4,
+  // T_6 = u + 31u^2 + 90u^3 + 65u^4 + 15u^5 + u^6
+  o[0] = delta;
+  o[1] = delta * (c2 + c4 + c6);
+  o[2] = delta * (c2 + 7.0f * c4 + 31.0f * c6);
+  o[3] = delta * (6.0f * c4 + 90.0f * c6);
+  o[4] = delta * (c4 + 65.0f * c6);
+  o[5] = delta * (15.0f * c6);
+  o[6] = delta * c6;
+  o[7] = emh;
+  // Q_0 = 1, Q_2 = 1 + 3u + u^2, Q_4 = 1 + 15u + 25u^2 + 10u^3 + u^4,
+  // Q_6 = 1 + 63u + 301u^2 + 350u^3 + 140u^4 + 21u^5 + u^6
+  o[8] = dq * (1.0f + c2 + c4 + c6);
+  o[9] = dq * (3.0f * c2 + 15.0f * c4 + 63.0f * c6);
+  o[10] = dq * (c2 + 25.0f * c4 + 301.0f * c6);
+  o[11] = dq * (10.0f * c4 + 350.0f * c6);
+  o[12] = dq * (c4 + 140.0f * c6);
+  o[13] = dq * (21.0f * c6);
+  o[14] = dq * c6;
+  o[15] = delta <= 0.25f ? (delta > 0.0f ? 0.25f / delta : 3.0e38f) : -1.0f;
+}
+
+// F, H by the expansion from an interval's 16 coefficients; returns whether
+// the interval is within its bound (otherwise F, H are to be taken from the
+// next tier).
+GLMR_HD inline bool taylor_f(const float* c, float D, float* F, float* H) {
+  const float u = D * c[7];
+  const float E = exp_f32(u);
+  float pf = c[6], ph = c[14];
+#pragma unroll
+  for (int k = 5; k >= 0; --k) {
+    pf = pf * u + c[k];
+    ph = ph * u + c[8 + k];
+  }
+  *F = E * pf;
+  *H = E * ph;
+  return fabsf(u) <= c[15];
+}
+
+// The per-interval table of the FP32 evaluation, 16 floats: [0] delta,
+// [1] e^{-delta/2} (the expansion), [8] delta/2, [9..14] the Gauss-Legendre
+// nodes e^{-s_k}, [15] 1 where delta <= 0.5 (the quadrature), the rest 0.
+GLMR_HD inline void table_f(double delta, float* o) {
+  const SlotF f = slot_consts_f(slot_consts(delta));
+  o[0] = (float)delta;
+  o[1] = (float)exp(-0.5 * delta);
+  for (int k = 2; k < 8; ++k) o[k] = 0.0f;
+  o[8] = f.half;
+  for (int k = 0; k < 6; ++k) o[9 + k] = f.e[k];
+  o[15] = f.ok ? 1.0f : 0.0f;
+}
+
+// The second and third tiers from the table's quadrature half: 6-point
+// Gauss-Legendre in FP32 where delta <= 0.5 and |D| delta <= 1, else the FP64
+// evaluation.
+GLMR_HD inline void gl_tier_f(const float* o, double delta, float D, float* F, float* H) {
+  const float half = o[8];
+  if (o[15] != 0.0f && fabsf(D) * (2.0f * half) <= 1.0f) {
+    const float wn[3] = {4.67913934572691370e-01f, 3.60761573048138939e-01f, 1.71324492379169746e-01f};
+    float sf = 0.0f, sh = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float v = half * wn[k >> 1] * expf(D * o[9 + k]);
+      sf += v;
+      sh += v * o[9 + k];
+    }
+    *F = sf;
+    *H = sh;
+    return;
+  }
+  if (!(delta > 0.0)) {
+    *F = 0.0f;
+    *H = 0.0f;
+    return;
+  }
+  double Fd, Hd;
+  interval_call((double)D, delta, &Fd, &Hd);
+  *F = (float)Fd;
+  *H = (float)Hd;
+}
+
+// The whole FP32 chain for one interval, as the resident BF16 kernels take it.
+GLMR_HD inline void interval_f32(float D, double delta, float* F, float* H) {
+  float o[16], c[16];
+  table_f(delta, o);
+  stage_f(o[0], o[1], c);
+  if (!taylor_f(c, D, F, H)) gl_tier_f(o, delta, D, F, H);
+}
+
 }  // namespace glmr_ev

@@ -28,9 +28,17 @@
 //          whose range covers exp(V) for V in about [-7, 15] without a scale.
 // Scales are powers of two, so applying and removing them is exact; the row
 // sums of exp(V) are taken in FP32/FP64 before W is rounded.
+//
+// Event grid (continuous time, BF16): the trace is built with the per-slot
+// decays (x_{m+1} = e^{-delta_m} x_m + spikes) and kernel U's epilogue takes
+// the interval integrals of Eq. (10), (14) in place of exp, in FP32 by the
+// midpoint expansion (one exponential per potential; intervals past its
+// bound by 6-point Gauss-Legendre or in FP64) from a per-slot table; W then
+// holds (e^D - e^{D xi}) / D and the row sums Ei(D) - Ei(D xi).
 #include <type_traits>
 
 #include "common.h"
+#include "evfun.h"
 
 namespace {
 
@@ -62,23 +70,29 @@ __global__ __launch_bounds__(256) void k_build_x(ResXArgs g) {
   const int64_t j = jb * 64 + jj;
   const int m0 = 16 * gq;
   const double a = g.tab->pw[1];
+  const bool ev = g.ev.pw != nullptr;  // event grid: per-slot decays
 
-  double x = g.C64[s * g.Np + j] * g.tab->pw[m0];
+  // trace at bin (slot) 64 s + m0: the carry decayed, plus the spikes of the
+  // subtile before m0
+  double x, zs = 0.0;
   uint32_t cnt[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) cnt[e] = 0;
+  x = ev ? 0.0 : g.C64[s * g.Np + j] * g.tab->pw[m0];
   for (int p = 0; p < g.planes; ++p) {
     const uint64_t mk = g.masks[((int64_t)p * g.NS + s) * g.Np + j];
     uint64_t below = (m0 == 0) ? 0ull : (mk & ((1ull << m0) - 1));
     while (below) {
       const int b = __builtin_ctzll(below);
       below &= below - 1;
-      x += g.tab->pw[m0 - b - 1];
+      if (ev) zs += g.ev.ainv[s * 64 + b];
+      else x += g.tab->pw[m0 - b - 1];
     }
     const uint32_t win = (uint32_t)((mk >> m0) & 0xffffu);
 #pragma unroll
     for (int e = 0; e < 16; ++e) cnt[e] += (win >> e) & 1u;
   }
+  if (ev) x = g.ev.pw[s * 64 + m0] * (g.C64[s * g.Np + j] + zs);
 
   // round pairs of bins to BF16; w[e/2] holds bins m0+e (low half) and m0+e+1
   uint32_t w[8];
@@ -86,10 +100,12 @@ __global__ __launch_bounds__(256) void k_build_x(ResXArgs g) {
 #pragma unroll
   for (int e = 0; e < 16; e += 2) {
     const int64_t t = s * 64 + m0 + e;
+    const double a0 = ev ? exp(-g.ev.delta[t]) : a;      // decay over bin (slot) t
+    const double a1 = ev ? exp(-g.ev.delta[t + 1]) : a;
     const float x0 = (float)x;
-    x = a * x + (double)cnt[e];
+    x = a0 * x + (double)cnt[e];
     const float x1 = (float)x;
-    x = a * x + (double)cnt[e + 1];
+    x = a1 * x + (double)cnt[e + 1];
     bf16x2 p = {};
     p = __builtin_amdgcn_cvt_sr_bf16_f32(p, x0, (uint32_t)t * SR_T + rj, false);
     p = __builtin_amdgcn_cvt_sr_bf16_f32(p, x1, (uint32_t)(t + 1) * SR_T + rj, true);
@@ -333,7 +349,9 @@ __device__ __forceinline__ void zero_acc(f32x16 (&acc)[MB][NB]) {
 // is staged in LDS so that each neuron's 256 bins leave as one run.
 constexpr uint32_t SR_WT = 0x85EBCA6Bu, SR_WI = 0xC2B2AE35u;  // rounding bits of the FP8 weights
 
-template <int BI, int WGM, int WGN, bool F8>
+constexpr int EVTS = 20;  // floats per slot of kernel U's staged expansion table (80 B: 16 used)
+
+template <int BI, int WGM, int WGN, bool F8, bool EV = false>
 __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int64_t ttile,
                                            unsigned char* smem) {
   constexpr int BT = GLMR_TT;
@@ -359,6 +377,77 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
   unsigned char* wl = smem;                                // [BI][WP]
   double* red = (double*)(smem + (size_t)BI * WP);         // [WGM][BI]
   const float xs_inv = F8 ? 1.f / g.xscale[0] : 1.f;
+  if constexpr (EV) {
+    // Event grid: W = (e^D - e^{D xi}) / D and row sums of Ei(D) - Ei(D xi)
+    // (Eq. (10), (14)) in place of exp(V).  The 16 expansion coefficients of
+    // each of the tile's slots are formed once into LDS (after W's staging
+    // rows and the row-sum partials); a lane reads its slot's with four
+    // broadcast loads and uses them for its NB neuron blocks.  Intervals
+    // outside the expansion's bound take the quadrature or FP64 tier from
+    // the table in memory.
+    static_assert(!F8, "the event grid's resident trace is BF16");
+    float* ctab = (float*)(smem + (size_t)BI * WP + (size_t)WGM * BI * sizeof(double));  // [BT][EVTS]
+    for (int k = tid; k < BT; k += T::NT) {
+      const int64_t t = tt0 + k;
+      // past the last slot: zero length and u = 0, so F = H = 0
+      const float2 de = t < g.B ? *(const float2*)(g.evgl + t * 16) : float2{0.f, 0.f};
+      float c[16];
+      glmr_ev::stage_f(de.x, de.y, c);
+      float4* o = (float4*)(ctab + k * EVTS);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[v] = float4{c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]};
+    }
+    __syncthreads();
+    float cs[T::NB];
+#pragma unroll
+    for (int b = 0; b < T::NB; ++b) cs[b] = 0.f;
+#pragma unroll
+    for (int a = 0; a < T::MB; ++a) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int tq = wm * T::WM + a * 32 + 8 * q + 4 * hi;  // first of 4 consecutive slots
+        float lam[T::NB][4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float c[16];
+          const float4* src = (const float4*)(ctab + (tq + e) * EVTS);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float4 w = src[v];
+            c[4 * v] = w.x;
+            c[4 * v + 1] = w.y;
+            c[4 * v + 2] = w.z;
+            c[4 * v + 3] = w.w;
+          }
+#pragma unroll
+          for (int b = 0; b < T::NB; ++b) {
+            const float D = acc[a][b][4 * q + e];
+            float F, H;
+            if (!glmr_ev::taylor_f(c, D, &F, &H)) {
+              const int64_t t = tt0 + tq + e;  // t < B: slots past it are within the bound
+              glmr_ev::gl_tier_f(g.evgl + t * 16, g.evdelta[t], D, &F, &H);
+            }
+            lam[b][e] = H;
+            cs[b] += F;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < T::NB; ++b) {
+          const int il = wn * T::WN + b * 32 + l32;
+          bf16x2 p0 = {(__bf16)lam[b][0], (__bf16)lam[b][1]}, p1 = {(__bf16)lam[b][2], (__bf16)lam[b][3]};
+          *(uint2*)(wl + il * WP + tq * 2) =
+              uint2{__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < T::NB; ++b) {
+      const int il = wn * T::WN + b * 32 + l32;
+      double v = (double)cs[b];
+      v += __shfl_xor(v, 32, 64);
+      if (hi == 0) red[wm * BI + il] = v;
+    }
+  } else
 #pragma unroll
   for (int b = 0; b < T::NB; ++b) {
     const int il = wn * T::WN + b * 32 + l32;  // neuron within the tile
@@ -411,11 +500,11 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
   }
 }
 
-template <int BI, int WGM, int WGN, bool F8>
+template <int BI, int WGM, int WGN, bool F8, bool EV = false>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_res_u(ResUArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
-  res_u_tile<BI, WGM, WGN, F8>(g, logical % g.n_itiles, logical / g.n_itiles, smem);
+  res_u_tile<BI, WGM, WGN, F8, EV>(g, logical % g.n_itiles, logical / g.n_itiles, smem);
 }
 
 // index r with prefix[r] <= k < prefix[r + 1] (prefix ascending, prefix[0] = 0)
@@ -514,12 +603,13 @@ hipError_t set_lds(K kern, size_t lds) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int BI, int WGM, int WGN, bool F8>
+template <int BI, int WGM, int WGN, bool F8, bool EV = false>
 hipError_t run_u(const ResUArgs& a, hipStream_t st) {
   using T = Nt<GLMR_TT, BI, WGM, WGN>;
-  const size_t epi = (size_t)BI * (GLMR_TT * (F8 ? 1 : 2) + 16) + (size_t)WGM * BI * sizeof(double);
+  const size_t epi = (size_t)BI * (GLMR_TT * (F8 ? 1 : 2) + 16) + (size_t)WGM * BI * sizeof(double) +
+                     (EV ? (size_t)GLMR_TT * EVTS * sizeof(float) : 0);
   const size_t lds = T::LDS > epi ? T::LDS : epi;
-  auto kern = k_res_u<BI, WGM, WGN, F8>;
+  auto kern = k_res_u<BI, WGM, WGN, F8, EV>;
   hipError_t e = set_lds(kern, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)a.n_itiles * a.n_ttiles)), dim3(T::NT), lds, st, a);
@@ -605,16 +695,16 @@ const ResShape* res_shapes(int* n) {
   return s;
 }
 
-template <bool F8>
+template <bool F8, bool EV = false>
 hipError_t res_u(int shape, const ResUArgs& a, hipStream_t st) {
   switch (shape) {
-    case 0: return run_u<256, 2, 2, F8>(a, st);
-    case 1: return run_u<256, 2, 4, F8>(a, st);
-    case 2: return run_u<256, 4, 2, F8>(a, st);
-    case 3: return run_u<128, 2, 2, F8>(a, st);
-    case 4: return run_u<128, 1, 4, F8>(a, st);
-    case 5: return run_u<128, 4, 2, F8>(a, st);
-    case 6: return run_u<128, 2, 4, F8>(a, st);
+    case 0: return run_u<256, 2, 2, F8, EV>(a, st);
+    case 1: return run_u<256, 2, 4, F8, EV>(a, st);
+    case 2: return run_u<256, 4, 2, F8, EV>(a, st);
+    case 3: return run_u<128, 2, 2, F8, EV>(a, st);
+    case 4: return run_u<128, 1, 4, F8, EV>(a, st);
+    case 5: return run_u<128, 4, 2, F8, EV>(a, st);
+    case 6: return run_u<128, 2, 4, F8, EV>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -672,6 +762,7 @@ hipError_t launch_res_g_group(int shape, int fp8, const ResGGroup& q, hipStream_
 
 // Kernel U / kernel G on the resident trace, BF16 or FP8 (fp8 != 0).
 hipError_t launch_res_u(int shape, int fp8, const ResUArgs& a, hipStream_t st) {
+  if (a.evgl) return fp8 ? hipErrorInvalidValue : res_u<false, true>(shape, a, st);  // event grid: BF16
   return fp8 ? res_u<true>(shape, a, st) : res_u<false>(shape, a, st);
 }
 

@@ -81,6 +81,7 @@ struct glmr_ctx {
   double T0 = 0, T1 = 0, max_gap = 0;
   double* tslot = nullptr;  // [NS*64 + 1]
   double* evtab = nullptr;  // [4 * NS*64 + NS]: pw, ainv, left, delta, asub
+  float* evgl = nullptr;    // BF16: [NS*64][16] per-slot table of kernel U's interval integrals
   double max_span = 0;      // largest 64-slot span / tau of the current tables
 
   // transmission delays in bins (regular grid): d on j -> i (j != i), d_s on i -> i
@@ -325,6 +326,12 @@ glmr_status build_ev_tables(glmr_ctx* c) {
   ta.left = c->evtab + 2 * n;
   ta.delta = c->evtab + 3 * n;
   ta.asub = c->evtab + 4 * n;
+  if (c->prec == PREC_BF16) {
+    if (!c->evgl) TRY(dalloc(c, c->evgl, (size_t)(16 * n)));
+    ta.gl = c->evgl;
+  } else {
+    dfree(c, c->evgl);
+  }
   ta.maxspan = ms;
   HIPCHK(c, launch_ev_tables(ta, c->st));
   unsigned long long h = 0;
@@ -341,7 +348,7 @@ glmr_status build_ev_tables(glmr_ctx* c) {
 }
 
 bool want_resident(glmr_ctx* c) {
-  if (c->evm) return false;
+  if (c->evm && c->prec != PREC_BF16) return false;  // the event grid's resident trace is BF16
   if (c->prec == PREC_FP8) return true;  // FP8 contractions exist only on the resident trace
   if (c->prec != PREC_BF16 || c->cfg.trace == GLMR_TRACE_RECOMPUTE) return false;
   if (c->cfg.trace == GLMR_TRACE_RESIDENT) return true;
@@ -381,6 +388,7 @@ glmr_status build_resident_trace(glmr_ctx* c) {
   xa.Bp = c->Bp;
   xa.Xtj = c->Xtj;
   xa.Xjt = c->Xjt;
+  xa.ev = ev_slots(c);
   if (f8) {
     const int64_t nchunks = (c->Bp + c->L - 1) / c->L;
     TRY(dalloc(c, c->xmax, (size_t)nchunks));
@@ -575,6 +583,15 @@ bool shape_ok(const glmr_ctx* c, int k) {
   return k >= 0 && k < n && c->Np % sh[k].bm == 0 && (c->prec != PREC_FP8 || sh[k].fp8_ok);
 }
 
+// kernel U's shapes: on the event grid only the 128-neuron tiles (the
+// 256-neuron ones would need the whole LDS for the staged rows and the
+// expansion table)
+bool shape_ok_u(const glmr_ctx* c, int k) {
+  int n = 0;
+  const ResShape* sh = res_shapes(&n);
+  return shape_ok(c, k) && !(c->evm && sh[k].bm != 128);
+}
+
 ResShape res_shape(int k) {
   int n = 0;
   const ResShape* s = res_shapes(&n);
@@ -599,6 +616,10 @@ ResUArgs make_u_args(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
   if (c->prec == PREC_FP8) {
     ua.xscale = c->xscale + t0 / c->L;
     ua.jscale = c->jscale;
+  }
+  if (c->evm) {
+    ua.evgl = c->evgl;
+    ua.evdelta = ev_slots(c).delta;
   }
   return ua;
 }
@@ -776,9 +797,10 @@ void setup_precision(glmr_ctx* c) {
   // resident-trace shapes: 256-neuron tiles when the padding allows
   if (c->prec == PREC_FP8) c->res_shape_u = c->res_shape_g = 5;
   else c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 2 : 3;
+  if (c->evm) c->res_shape_u = 5;  // the interval integrals: 128-neuron tiles keep kernel U unspilled
   if (const char* e = std::getenv("GLMR_RES_SHAPE")) {
     int u = -1, g = -1;
-    if (std::sscanf(e, "%d,%d", &u, &g) == 2 && shape_ok(c, u) && shape_ok(c, g)) {
+    if (std::sscanf(e, "%d,%d", &u, &g) == 2 && shape_ok_u(c, u) && shape_ok(c, g)) {
       c->res_shape_u = u;
       c->res_shape_g = g;
     }
@@ -1059,7 +1081,7 @@ std::string tune_key(glmr_ctx* c) {
     if (ch == ' ') ch = '_';
   char buf[256];
   std::snprintf(buf, sizeof(buf), "%s %lld %lld %d", arch.c_str(), (long long)c->Np, (long long)c->L,
-                c->prec);
+                c->prec + (c->evm ? 16 : 0));  // the event grid's kernel U differs
   return buf;
 }
 
@@ -1286,7 +1308,7 @@ glmr_status batch_prepare(glmr_batch* b) {
   bool grouped = true;
   for (glmr_ctx* c : b->ctxs) {
     TRY(check_ready(c));
-    grouped = grouped && c->resident && !self_delayed(c);
+    grouped = grouped && c->resident && !self_delayed(c) && !c->evm;
   }
   b->grouped = grouped;
   if (grouped) {
@@ -1999,7 +2021,7 @@ extern "C" glmr_status glmr_autotune(glmr_ctx* c, const char* cache_path, int32_
         if (std::sscanf(line, "glmrec-tune %127s %lld %lld %d %d %d", arch, &np, &l, &prec, &u, &g) == 6) {
           char k2[256];
           std::snprintf(k2, sizeof(k2), "%s %lld %lld %d", arch, np, l, prec);
-          if (key == k2 && shape_ok(c, u) && shape_ok(c, g)) {
+          if (key == k2 && shape_ok_u(c, u) && shape_ok(c, g)) {
             best_u = u;  // the last matching line wins
             best_g = g;
           }
@@ -2015,8 +2037,10 @@ extern "C" glmr_status glmr_autotune(glmr_ctx* c, const char* cache_path, int32_
     for (int k = 0; k < n; ++k) {
       if (!shape_ok(c, k)) continue;
       double ms = 0;
-      TRY(time_launches(c, [&] { return launch_u_chunk(c, k, 0, Lc); }, 3, &ms));
-      if (ms < tu) { tu = ms; best_u = k; }
+      if (shape_ok_u(c, k)) {
+        TRY(time_launches(c, [&] { return launch_u_chunk(c, k, 0, Lc); }, 3, &ms));
+        if (ms < tu) { tu = ms; best_u = k; }
+      }
       int ns = 0;
       TRY(time_launches(c, [&] { return launch_g_chunk(c, k, 0, Lc, &ns); }, 3, &ms));
       if (ms < tg) { tg = ms; best_g = k; }

@@ -63,3 +63,53 @@ def test_interval_integrals_limits():
         F, H = G.glmr_ei_interval(D, a + b)
         assert F1 + F2 == pytest.approx(F, rel=1e-13)
         assert H1 + np.exp(-a) * H2 == pytest.approx(H, rel=1e-13)
+
+
+def _tier_f32(D, delta):
+    """Which tier of the FP32 chain takes (D, delta): 0 the midpoint expansion,
+    1 the 6-point quadrature, 2 the FP64 evaluation."""
+    D = float(np.float32(D))
+    u = D * float(np.float32(np.exp(-0.5 * delta)))
+    if float(np.float32(delta)) * max(1.0, abs(u)) <= 0.25:
+        return 0
+    return 1 if (delta <= 0.5 and abs(D) * delta <= 1.0) else 2
+
+
+def test_fp32_interval_chain_matches_mpmath_in_every_tier():
+    # the BF16 event grid's integrals: an FP32 potential, FP32 arithmetic;
+    # relative error within a few units of 2^-24 per unit of |u| (the
+    # exponential of a rounded argument), in each of the three tiers
+    import paper_1502_04993_amd as G
+    rng = np.random.default_rng(11)
+    D = np.concatenate([rng.uniform(-3, 3, 400), rng.uniform(-12, 12, 400), rng.uniform(-30, 30, 200),
+                        [0.0, 1.0, -1.0, 1e-7]])
+    delta = np.concatenate([10 ** rng.uniform(-6, -0.3, 800), 10 ** rng.uniform(-3, 1.5, 200),
+                            [0.25, 0.25, 0.25, 0.3]])
+    seen = [0, 0, 0]
+    worst = 0.0
+    for d_, dl in zip(D.tolist(), delta.tolist()):
+        Df = float(np.float32(d_))
+        F, H = G.glmr_ei_interval_f32(Df, dl)
+        Fr, Hr = _ref(Df, dl)
+        scale = 1e-7 * (8.0 + abs(Df))
+        ef, eh = float(abs((F - Fr) / Fr)), float(abs((H - Hr) / Hr))
+        seen[_tier_f32(Df, dl)] += 1
+        worst = max(worst, ef / scale, eh / scale)
+        assert ef <= scale and eh <= scale, (Df, dl, ef, eh)
+    assert min(seen) >= 20, seen
+    print(f"[fp32 chain] tiers {seen} worst {worst:.3f} of the bound")
+
+
+def test_fp32_expansion_at_its_bound_and_degenerate_intervals():
+    import paper_1502_04993_amd as G
+    # on the bound delta max(1, |u|) = 0.25 from both sides: the expansion's
+    # truncation stays far below FP32 rounding
+    for D in (-6.0, -1.0, 0.5, 1.0, 4.0):
+        for dl in np.linspace(0.2, 0.3, 21):
+            u = D * np.exp(-dl / 2)
+            F, H = G.glmr_ei_interval_f32(D, dl)
+            Fr, Hr = _ref(D, dl)
+            assert abs((F - Fr) / Fr) < 1e-6 and abs((H - Hr) / Hr) < 1e-6, (D, dl, u)
+    assert G.glmr_ei_interval_f32(2.5, 0.0) == (0.0, 0.0)
+    F, H = G.glmr_ei_interval_f32(0.0, 0.1)
+    assert F == pytest.approx(0.1, rel=2e-7) and H == pytest.approx(-np.expm1(-0.1), rel=2e-7)

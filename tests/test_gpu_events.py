@@ -9,7 +9,9 @@ in both modes):
   FP32: L 1e-10 sqrt(2e6 / (slots N)) (stochastically rounded FP32 trace),
         gradient 1e-4.
   BF16: L 1e-3, gradient 1e-3 (trace, J and the weights in BF16, the interval
-        integrals in FP64 from the FP32-accumulated potential).
+        integrals from the FP32-accumulated potential).  "bf16" runs the
+        resident BF16 trace (kernel U takes the integrals in its epilogue),
+        "bf16-rc" the kernels that rebuild the trace from the spike masks.
 """
 import math
 
@@ -21,7 +23,7 @@ from oracle import glm_oracle as O
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4), "bf16": (1e-3, 1e-3)}
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4), "bf16": (1e-3, 1e-3), "bf16-rc": (1e-3, 1e-3)}
 
 
 def _G():
@@ -36,7 +38,9 @@ def _lists(times, neurons, N):
 def _ctx(N, times, neurons, T0, T1, prec, max_gap=0.0, chunk_bins=0, allow_silent=False):
     G = _G()
     slots = G.glmr_event_slots(times, T0, T1, max_gap)
-    c = G.Context(N, slots, (T1 - T0) / slots, prec, chunk_bins=chunk_bins, time_mode="events")
+    trace = "recompute" if prec.endswith("-rc") else "auto"
+    c = G.Context(N, slots, (T1 - T0) / slots, prec.split("-")[0], chunk_bins=chunk_bins,
+                  time_mode="events", trace=trace)
     try:
         c.set_spike_times(times, neurons, T0, T1, max_gap)
     except G.GlmrError as e:
@@ -60,7 +64,7 @@ def _compare(r, ref, prec, slots, N, label):
 
 
 def _round(J, prec):
-    if prec == "bf16":
+    if prec.startswith("bf16"):
         import torch
         return torch.tensor(J).to(torch.bfloat16).to(torch.float64).numpy()
     return J.astype(np.float32).astype(np.float64) if prec == "fp32" else J
@@ -70,7 +74,8 @@ def _round(J, prec):
                                             ("bf16", 70, 30_000, 0),
                                             ("fp64", 150, 12_000, 4096), ("fp32", 150, 12_000, 4096),
                                             ("bf16", 150, 12_000, 4096), ("bf16", 300, 8_000, 0),
-                                            ("bf16", 400, 6_000, 0)])
+                                            ("bf16", 400, 6_000, 0), ("bf16-rc", 70, 30_000, 0),
+                                            ("bf16-rc", 150, 12_000, 4096), ("bf16-rc", 400, 6_000, 0)])
 def test_event_grid_matches_oracle(prec, N, B, chunk):
     # N = 150 pads to two neuron tiles; chunk_bins = 4096 splits the slots
     # into several chunks with a ragged last one; BF16 at N = 400 runs the
@@ -83,7 +88,9 @@ def test_event_grid_matches_oracle(prec, N, B, chunk):
     J = _round(rec.J, prec)
     c.set_params(J, rec.mu)
     r = c.eval(grad=True)
+    resident = c.query()["trace_resident"]
     c.close()
+    assert resident == (prec == "bf16")
     ref = O.continuous_eval(_lists(times, neu, N), T0, T1, rec.tau, J, rec.mu)
     _compare(r, ref, prec, slots, N, f"N={N} q={times.shape[0]} chunk={chunk}")
 
