@@ -306,7 +306,8 @@ def bench_events(args, G, torch):
     T0, T1 = 0.0, rec.T
     print(f"[events] {times.shape[0]} events ready", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    ctx = G.Context.from_events(N, times, neu, T0, T1, precision=prec)
+    ctx = G.Context.from_events(N, times, neu, T0, T1, precision=prec,
+                                trace=args.trace if prec == "bf16" else "auto")
     ctx.set_kernel(rec.tau)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
@@ -332,7 +333,7 @@ def bench_events(args, G, torch):
         "data": "synthetic",
         "config": {"workload": "balanced_n1000_indeg100_t3600s_event_grid", "n_neurons": N,
                    "n_events": int(times.shape[0]), "n_slots": slots, "precision": prec,
-                   "chunk_slots": q["chunk_bins"], "n_pad": q["n_pad"]},
+                   "chunk_slots": q["chunk_bins"], "n_pad": q["n_pad"], "trace_resident": q["trace_resident"]},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None, "kernel": dom,
                      "launch_ms": per_launch_s * 1e3, "launches_per_step": launches,

@@ -241,6 +241,13 @@ typedef struct {
   double j_max;           /* bound on |J_ij| (0: none) */
   double rate_min;        /* lower bound on e^{mu_i} in 1/s (0: none) */
   double rate_max;        /* upper bound on e^{mu_i} in 1/s (0: none) */
+  int32_t resume;         /* 1: continue the ascent the context holds (that of its last glmr_fit,
+                             or one restored by glmr_set_state) with its histories, step sizes,
+                             row status, history length, penalty and bounds; max_iter, ftol
+                             and max_backtracks come from these opts, the rest is ignored.
+                             A fit of a + b steps equals one of a steps resumed for b.
+                             GLMR_ESTATE if there is none: changing the spikes, kernel,
+                             delays, precision or parameters ends an ascent. */
 } glmr_fit_opts;
 
 typedef struct {
@@ -268,6 +275,32 @@ void glmr_fit_defaults(glmr_fit_opts* opts);
  * Requires q_i >= 1 for every neuron (else GLMR_ENOSPIKES).  Returns
  * GLMR_NOT_CONVERGED (a warning) if max_iter is reached.  report may be NULL. */
 glmr_status glmr_fit(glmr_ctx* ctx, const glmr_fit_opts* opts, glmr_fit_report* report);
+
+/* Checkpoint of a fit (resume support): the parameters J, mu, tau, the
+ * delays, the precision and, when the context holds a resumable ascent, its
+ * whole state (per-row L-BFGS histories, iterates, gradients, step sizes,
+ * row status, penalty and bounds), as one flat host buffer in this machine's
+ * byte order with a fixed head.  buf NULL: *len receives the size in bytes
+ * (about 8 (2m + 6) N^2 with history length m, m = 10 by default).
+ * Otherwise *len must hold the buffer's size; it receives the bytes
+ * written (GLMR_EINVAL, with the size needed in *len, if too small).  The
+ * buffer belongs to the caller.  GLMR_ESTATE before spikes and parameters. */
+glmr_status glmr_get_state(glmr_ctx* ctx, void* buf, size_t* len);
+
+/* Restore a checkpoint into a context of the same recording: same N,
+ * n_bins, dt and time mode, and the same spikes (their count and the
+ * per-neuron counts are checked; set them first, GLMR_ESTATE otherwise).
+ * Applies the precision, delays and tau of the checkpoint, its parameters,
+ * and its ascent (glmr_fit with opts.resume = 1 then continues it).  In a
+ * context created with the same configuration the resumed fit ends bit for
+ * bit where the interrupted one would have; a context created in another
+ * precision may pad the neurons differently (the padding is fixed at
+ * creation), which regroups the sums: the same fit within that precision's
+ * rounding.  GLMR_EINVAL on a buffer that is not
+ * a checkpoint of this library, is truncated, or belongs to another
+ * recording; the context then keeps what it had, except that a failure
+ * after the checks (device errors) may leave it partly restored. */
+glmr_status glmr_set_state(glmr_ctx* ctx, const void* buf, size_t len);
 
 /* ---------------------------------------------------------------- batching
  * Many independent recordings (contexts of possibly different N and B, all

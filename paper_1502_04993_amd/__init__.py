@@ -9,6 +9,7 @@ memory, GLMR_DEVICE); torch is used for device memory and streams only.
 from __future__ import annotations
 
 import ctypes
+import sys
 from typing import Optional
 
 import numpy as np
@@ -19,6 +20,7 @@ from ._lib import (GLMR_BF16, GLMR_DEVICE, GLMR_FP8, GLMR_FP32, GLMR_FP64, GLMR_
 
 __all__ = ["Context", "Batch", "GlmrError", "glmr_create", "glmr_destroy", "glmr_set_spikes",
            "glmr_event_slots", "glmr_set_spike_times", "glmr_ei_interval", "glmr_ei_interval_f32", "glmr_set_delays",
+           "glmr_get_state", "glmr_set_state",
            "glmr_set_kernel", "glmr_set_precision", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
            "glmr_fit_defaults", "glmr_status_string", "glmr_last_error", "glmr_query",
            "glmr_batch_create", "glmr_batch_destroy", "glmr_batch_eval", "glmr_batch_get_grad",
@@ -181,6 +183,19 @@ def glmr_fit(ctx, opts=None):
     return st, rep
 
 
+def glmr_get_state(ctx):
+    """The context's checkpoint (parameters, tau, delays, precision, ascent) as bytes."""
+    n = ctypes.c_size_t(0)
+    _check(L.load().glmr_get_state(ctx, None, ctypes.byref(n)), ctx)
+    buf = ctypes.create_string_buffer(n.value)
+    _check(L.load().glmr_get_state(ctx, buf, ctypes.byref(n)), ctx)
+    return buf.raw[:n.value]
+
+
+def glmr_set_state(ctx, state: bytes):
+    return _check(L.load().glmr_set_state(ctx, bytes(state), len(state)), ctx)
+
+
 def glmr_status_string(status):
     return L.load().glmr_status_string(status).decode()
 
@@ -285,14 +300,17 @@ class Context:
 
     @classmethod
     def from_events(cls, n_neurons: int, times, neurons, T0: float, T1: float, precision: str = "fp64",
-                    max_gap: float = 0.0, device: int = 0, stream=None, chunk_bins: int = 0, tile_n: int = 0):
+                    max_gap: float = 0.0, device: int = 0, stream=None, chunk_bins: int = 0, tile_n: int = 0,
+                    trace: str = "auto"):
         """Continuous-time context of spike times (seconds, host arrays sorted by
-        (time, neuron)) on [T0, T1); the spikes are set, the kernel is not."""
+        (time, neuron)) on [T0, T1); the spikes are set, the kernel is not.
+        trace: "auto" keeps the BF16 trace resident when it fits, "recompute"
+        rebuilds it inside the contractions."""
         times = np.ascontiguousarray(times, dtype=np.float64)
         neurons = np.ascontiguousarray(neurons, dtype=np.int32)
         slots = glmr_event_slots(times, T0, T1, max_gap)
         c = cls(n_neurons, slots, (T1 - T0) / slots, precision, device, stream, chunk_bins, tile_n,
-                time_mode="events")
+                trace=trace, time_mode="events")
         c.T0, c.T1, c.max_gap = float(T0), float(T1), float(max_gap)
         c.set_spike_times(times, neurons, T0, T1, max_gap)
         return c
@@ -358,13 +376,15 @@ class Context:
 
     def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
             from_zero=False, polish=None, polish_iter=200, l1_alpha=0.0, l1_eps=0.0, j_max=0.0,
-            rate_min=0.0, rate_max=0.0):
+            rate_min=0.0, rate_max=0.0, resume=False):
         """Per-row L-BFGS ascent.  polish="fp32" finishes a BF16 ascent with FP32
         evaluations from the BF16 optimum (then switches back).  l1_alpha /
-        l1_eps: the smooth epsilon-l1 penalty; j_max, rate_min, rate_max: bounds."""
+        l1_eps: the smooth epsilon-l1 penalty; j_max, rate_min, rate_max: bounds.
+        resume=True continues the ascent the context holds (an earlier fit's, or
+        one restored by set_state)."""
         o = glmr_fit_defaults()
         o.max_iter, o.ftol, o.lbfgs_m, o.max_backtracks = max_iter, ftol, lbfgs_m, max_backtracks
-        o.warm_start_mu, o.from_zero = int(warm_start_mu), int(from_zero)
+        o.warm_start_mu, o.from_zero, o.resume = int(warm_start_mu), int(from_zero), int(resume)
         o.l1_alpha, o.l1_eps, o.j_max, o.rate_min, o.rate_max = l1_alpha, l1_eps, j_max, rate_min, rate_max
         st, rep = glmr_fit(self._c, o)
         out = dict(status=st, converged=(st == GLMR_OK), iters=rep.iters, evals=rep.evals,
@@ -380,6 +400,17 @@ class Context:
                        polish_evals=rep2.evals, ll=rep2.ll, max_eta=rep2.max_eta,
                        rows_converged=rep2.rows_converged, seconds=out["seconds"] + rep2.seconds)
         return out
+
+    def get_state(self) -> bytes:
+        """Checkpoint: parameters, tau, delays, precision and the ascent's state."""
+        return glmr_get_state(self._c)
+
+    def set_state(self, state: bytes):
+        """Restore a checkpoint of this recording; fit(resume=True) then continues it."""
+        glmr_set_state(self._c, state)
+        # the head's precision field (after magic, N, time mode, n_bins, dt, tau, d, d_self)
+        code = int.from_bytes(bytes(state[56:60]), sys.byteorder, signed=True)
+        self.precision = {v: k for k, v in PRECISIONS.items()}[code]
 
     def query(self):
         return glmr_query(self._c)
@@ -431,10 +462,11 @@ class Batch:
         return gJ, gmu
 
     def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
-            from_zero=False, l1_alpha=0.0, l1_eps=0.0, j_max=0.0, rate_min=0.0, rate_max=0.0):
+            from_zero=False, l1_alpha=0.0, l1_eps=0.0, j_max=0.0, rate_min=0.0, rate_max=0.0,
+            resume=False):
         o = glmr_fit_defaults()
         o.max_iter, o.ftol, o.lbfgs_m, o.max_backtracks = max_iter, ftol, lbfgs_m, max_backtracks
-        o.warm_start_mu, o.from_zero = int(warm_start_mu), int(from_zero)
+        o.warm_start_mu, o.from_zero, o.resume = int(warm_start_mu), int(from_zero), int(resume)
         o.l1_alpha, o.l1_eps, o.j_max, o.rate_min, o.rate_max = l1_alpha, l1_eps, j_max, rate_min, rate_max
         st, reps = glmr_batch_fit(self._b, len(self.ctxs), o)
         return st, [dict(iters=r.iters, evals=r.evals, ll=r.ll, max_eta=r.max_eta,

@@ -43,7 +43,7 @@ class glmr_fit_opts(ctypes.Structure):
                 ("max_backtracks", ctypes.c_int32), ("warm_start_mu", ctypes.c_int32),
                 ("from_zero", ctypes.c_int32), ("l1_alpha", ctypes.c_double),
                 ("l1_eps", ctypes.c_double), ("j_max", ctypes.c_double), ("rate_min", ctypes.c_double),
-                ("rate_max", ctypes.c_double)]
+                ("rate_max", ctypes.c_double), ("resume", ctypes.c_int32)]
 
 
 class glmr_fit_report(ctypes.Structure):
@@ -67,6 +67,8 @@ SIGNATURES = {
     "glmr_ei_interval_f32": (None, [ctypes.c_float, ctypes.c_double, ctypes.POINTER(ctypes.c_float),
                                     ctypes.POINTER(ctypes.c_float)]),
     "glmr_set_kernel": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "glmr_get_state": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "glmr_set_state": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "glmr_set_delays": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64]),
     "glmr_set_precision": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "glmr_set_params": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),

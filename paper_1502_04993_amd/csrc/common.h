@@ -205,6 +205,7 @@ struct Gemm1Args {
   int mode;                // 0: U -> W, 1: V = Y J^T -> sum W V
   int w_plain;             // mode 1: W holds exp(V) (resident trace) instead of exp(V) a^m
   EvSlots ev;              // event grid (mode 0 only): W = H(D, delta) pw, row sums of F(D, delta)
+  const float* evgl;       // event grid, BF16: [slots][16] per-slot table of the FP32 integrals
 };
 hipError_t launch_gemm1(int prec, int tile, const Gemm1Args& a, hipStream_t st);
 

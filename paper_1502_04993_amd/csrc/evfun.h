@@ -212,12 +212,13 @@ GLMR_HD inline void interval(double D, double delta, double* F, double* H) {
   interval(D, slot_consts(delta), F, H);
 }
 
-// The same in FP32 for the BF16 mode (whose potential D is an FP32 sum of
-// BF16 products): 6-point Gauss-Legendre in s on [0, delta],
+// FP32 evaluation for the BF16 mode (whose potential D is an FP32 sum of
+// BF16 products), in three tiers: the midpoint expansion below; 6-point
+// Gauss-Legendre in s on [0, delta],
 //   F = delta/2 sum_k w_k exp(D e^{-s_k}),  H = delta/2 sum_k w_k e^{-s_k} exp(D e^{-s_k}),
-// in FP32 for delta <= 0.5 and |D| delta <= 1 (the integrand is entire and
-// varies by at most a factor e over the interval; relative error a few units
-// of 2^-24), every other interval through the FP64 evaluation.  The nodes
+// for delta <= 0.5 and |D| delta <= 1 (the integrand is entire and varies by
+// at most a factor e over the interval; relative error a few units of
+// 2^-24); every other interval through the FP64 evaluation.  The nodes
 // e^{-s_k} depend on the interval only.
 struct SlotF {
   float half;     // delta / 2 (0: empty interval)
@@ -247,27 +248,6 @@ __host__ __device__ __attribute__((noinline))
 #endif
 inline void interval_call(double D, double delta, double* F, double* H) {
   interval(D, slot_consts(delta), F, H);
-}
-
-GLMR_HD inline void interval_f(float D, const Slot& q, const SlotF& f, double* F, double* H) {
-  if (f.ok && fabsf(D) * (2.0f * f.half) <= 1.0f) {
-    float sf = 0.0f, sh = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float v = f.w[k] * expf(D * f.e[k]);
-      sf += v;
-      sh += v * f.e[k];
-    }
-    *F = (double)sf;
-    *H = (double)sh;
-    return;
-  }
-  if (!(q.delta > 0.0)) {
-    *F = 0.0;
-    *H = 0.0;
-    return;
-  }
-  interval_call((double)D, q.delta, F, H);
 }
 
 // FP32 exponential: the hardware's base-2 exponential on the device (a few

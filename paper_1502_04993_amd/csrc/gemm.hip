@@ -419,9 +419,19 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
     const bool valid = (tt0 + tl) < g.B;
     const double pwd = g.ev.pw[tt0 + tl];
     const double pwm = (double)pw_of<T>(pwd);  // the factor the stored W' carries
-    // zero length for padded slots: both integrals vanish
-    const glmr_ev::Slot sc = glmr_ev::slot_consts(valid ? g.ev.delta[tt0 + tl] : 0.0);
-    const glmr_ev::SlotF scf = glmr_ev::slot_consts_f(sc);
+    // The lane's slot is fixed: its constants are formed once.  BF16 mode
+    // takes the FP32 chain of the resident kernels (expansion coefficients,
+    // quadrature and FP64 tiers from the per-slot table), the others the FP64
+    // evaluation.  Padded slots have zero length: both integrals vanish.
+    constexpr bool F32 = sizeof(st_t) == 4;
+    glmr_ev::Slot sc{};
+    float cf[16];
+    if constexpr (F32) {
+      const float2 de = valid ? *(const float2*)(g.evgl + (tt0 + tl) * 16) : float2{0.f, 0.f};
+      glmr_ev::stage_f(de.x, de.y, cf);
+    } else {
+      sc = glmr_ev::slot_consts(valid ? g.ev.delta[tt0 + tl] : 0.0);
+    }
 #pragma unroll
     for (int a = 0; a < WMB; ++a) {
       __syncthreads();
@@ -435,10 +445,16 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
       for (int e = 0; e < P::MB; ++e) {
         const int il = wm * WM + a * P::MB + e;
         double F, H;
-        if constexpr (sizeof(st_t) == 4)  // BF16 mode: FP32 potential, FP32 short-interval branch
-          glmr_ev::interval_f((float)pwd * stage[e * WN + lane], sc, scf, &F, &H);
-        else
+        if constexpr (F32) {  // BF16 mode: FP32 potential
+          const float D = (float)pwd * stage[e * WN + lane];
+          float Ff, Hf;
+          if (!glmr_ev::taylor_f(cf, D, &Ff, &Hf))
+            glmr_ev::gl_tier_f(g.evgl + (tt0 + tl) * 16, g.ev.delta[tt0 + tl], D, &Ff, &Hf);
+          F = Ff;
+          H = Hf;
+        } else {
           glmr_ev::interval(pwd * (double)stage[e * WN + lane], sc, &F, &H);
+        }
         W[(i0 + il) * g.L + (tl0 + tl)] = (w_t)(H * pwm);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) F += __shfl_xor(F, off, 64);

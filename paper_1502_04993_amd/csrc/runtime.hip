@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -139,6 +140,7 @@ struct glmr_ctx {
   // ascent state
   AscentArgs asc{};
   bool have_asc = false;
+  bool asc_live = false;  // asc holds an ascent of the current objective that a fit can resume
   int32_t* counters = nullptr;
   int32_t* host_cnt = nullptr;  // pinned copy of counters
   bool capturing = false;       // work is being captured into a graph (no profiling events)
@@ -679,6 +681,7 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
     g1.rowpart = c->rowpart;
     g1.mode = 0;
     g1.ev = ev_slots(c);
+    g1.evgl = c->evgl;
     if (c->resident) {
       ProfScope ps(c, K_U);
       HIPCHK(c, launch_u_chunk(c, c->res_shape_u, t0, Lc));
@@ -953,8 +956,12 @@ glmr_status check_fit_opts(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_opts
       !(o->l1_alpha >= 0) || !(o->l1_eps >= 0) || !(o->j_max >= 0) || !(o->rate_min >= 0) ||
       !(o->rate_max >= 0) || (o->rate_min > 0 && o->rate_max > 0 && o->rate_min >= o->rate_max))
     return fail(c, GLMR_EINVAL, "bad fit options");
+  if (o->resume != 0 && o->resume != 1) return fail(c, GLMR_EINVAL, "bad fit options");
   if (!c->have_spikes || !c->have_kernel) return fail(c, GLMR_ESTATE, "set spikes and kernel first");
   if (!c->all_spiking) return fail(c, GLMR_ENOSPIKES, "some neuron has no spike: its MLE does not exist");
+  if (o->resume && !c->asc_live)
+    return fail(c, GLMR_ESTATE, "no ascent to resume (fit or glmr_set_state first; changing spikes, "
+                                "kernel, delays, precision or parameters ends it)");
   return GLMR_OK;
 }
 
@@ -962,6 +969,7 @@ glmr_status check_fit_opts(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_opts
 glmr_status fit_begin(glmr_ctx* c, const glmr_fit_opts& o) {
   const int N = c->N;
   const int64_t Np = c->Np;
+  c->asc_live = false;
   if (!c->have_params || o.from_zero) {
     if (!c->J64) {
       std::vector<double> z((size_t)N * N, 0.0), zm(N, 0.0);
@@ -996,6 +1004,7 @@ glmr_status fit_begin(glmr_ctx* c, const glmr_fit_opts& o) {
 glmr_status fit_end(glmr_ctx* c, int iters, int evals, double seconds, glmr_fit_report* rep) {
   const int N = c->N;
   AscentArgs& a = c->asc;
+  c->asc_live = true;
   HIPCHK(c, launch_pack_theta(N, c->Np, a.P, a.theta, c->J64, c->mu, c->st));
   TRY(prepare_params(c));
   std::vector<double> f(N), eta(N);
@@ -1023,18 +1032,32 @@ glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep
   TRY(check_fit_opts(c, o_in, &o));
   HIPCHK(c, hipSetDevice(c->cfg.device));
   auto t_start = std::chrono::steady_clock::now();
-  TRY(fit_begin(c, o));
   AscentArgs& a = c->asc;
   const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c->prec);
   int evals = 0, iters = 0;
-  TRY(eval_theta(c, a.theta, a.g, a.f));
-  ++evals;
-  HIPCHK(c, launch_lbfgs_direction(a, 1, c->st));
+  if (o.resume) {
+    // every step ends with the next directions in place: carry on from there.
+    // A context restored from a checkpoint has not evaluated yet: its
+    // workspace is made here, since nothing may allocate inside the capture.
+    c->asc_live = false;
+    TRY(ensure_workspace(c, true, false));
+  } else {
+    TRY(fit_begin(c, o));
+    TRY(eval_theta(c, a.theta, a.g, a.f));
+    ++evals;
+    HIPCHK(c, launch_lbfgs_direction(a, 1, c->st));
+  }
   // one ascent step, captured once into a graph and replayed
   auto step = [&]() -> glmr_status { return ascent_step(c, ftol, o.max_backtracks); };
   GraphRun gr;
   if (use_graphs()) TRY(gr.capture(c, c->st, step));
   int active = c->N;
+  if (o.resume) {
+    HIPCHK(c, launch_count_active(a, c->counters, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->host_cnt, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    active = c->host_cnt[0];
+  }
   for (iters = 0; iters < o.max_iter && active > 0; ++iters) {
     if (gr.exec) HIPCHK(c, hipGraphLaunch(gr.exec, c->st));
     else TRY(step());
@@ -1265,6 +1288,158 @@ glmr_status glmr_fit(glmr_ctx* c, const glmr_fit_opts* o, glmr_fit_report* rep) 
   return fit_one(c, o, rep);
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------ checkpoints
+namespace {
+
+// Fixed head of a checkpoint; the arrays follow in the order of state_arrays.
+struct StateHead {
+  char magic[8];  // "GLMRST01"
+  int32_t n_neurons, time_mode;
+  int64_t n_bins;
+  double dt, tau;
+  int64_t d, d_self;
+  int32_t precision, m;  // m = 0: parameters only, no ascent
+  uint64_t spikes_fp;    // FNV-1a over the spike count and the per-neuron counts q_i
+  double alpha, eps, jmax, mu_lo, mu_hi;
+};
+constexpr char kStateMagic[8] = {'G', 'L', 'M', 'R', 'S', 'T', '0', '1'};
+static_assert(offsetof(StateHead, precision) == 56, "the Python binding reads the precision at byte 56");
+
+uint64_t spikes_fingerprint(const glmr_ctx* c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)c->nspk);
+  for (int i = 0; i < c->N; ++i) mix((uint64_t)c->q_host[i]);
+  return h;
+}
+
+// One device array of the ascent state: pointer and byte count.
+struct Span {
+  void* p;
+  size_t bytes;
+};
+
+std::vector<Span> state_arrays(glmr_ctx* c) {
+  AscentArgs& a = c->asc;
+  const size_t N = (size_t)c->N, np = N * (size_t)(c->N + 1), m = (size_t)a.m, d8 = sizeof(double),
+               i4 = sizeof(int32_t);
+  return {{a.theta, np * d8}, {a.theta_try, np * d8}, {a.g, np * d8},       {a.g_try, np * d8},
+          {a.d, np * d8},     {a.S, np * m * d8},     {a.Y, np * m * d8},   {a.rho, m * N * d8},
+          {a.f, N * d8},      {a.f_try, N * d8},      {a.step, N * d8},     {a.gd, N * d8},
+          {a.eta, N * d8},    {a.gstep, N * d8},      {a.hist_len, N * i4}, {a.hist_head, N * i4},
+          {a.state, N * i4},  {a.accepted, N * i4},   {a.bt, N * i4}};
+}
+
+size_t state_bytes(glmr_ctx* c, int m) {
+  const size_t N = (size_t)c->N, np = N * (size_t)(c->N + 1), d8 = sizeof(double), i4 = sizeof(int32_t);
+  size_t n = sizeof(StateHead) + (N * N + N) * d8;
+  if (m > 0) n += (5 * np + 2 * np * (size_t)m + (size_t)m * N + 6 * N) * d8 + 5 * N * i4;
+  return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+glmr_status glmr_get_state(glmr_ctx* c, void* buf, size_t* len) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (!len) return fail(c, GLMR_EINVAL, "null length");
+  if (!c->have_spikes || !c->have_params) return fail(c, GLMR_ESTATE, "set spikes and parameters first");
+  const int m = c->asc_live ? c->asc.m : 0;
+  const size_t need = state_bytes(c, m);
+  if (!buf) {
+    *len = need;
+    return GLMR_OK;
+  }
+  if (*len < need) {
+    *len = need;
+    return fail(c, GLMR_EINVAL, "the buffer holds %zu bytes, the state %zu", *len, need);
+  }
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  StateHead h{};
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.n_neurons = c->N;
+  h.time_mode = c->evm ? GLMR_TIME_EVENTS : GLMR_TIME_GRID;
+  h.n_bins = c->B;
+  h.dt = c->dt;
+  h.tau = c->tau;
+  h.d = c->dly;
+  h.d_self = c->dly_s;
+  h.precision = c->prec;
+  h.m = m;
+  h.spikes_fp = spikes_fingerprint(c);
+  h.alpha = c->asc.alpha;
+  h.eps = c->asc.eps;
+  h.jmax = c->asc.jmax;
+  h.mu_lo = c->asc.mu_lo;
+  h.mu_hi = c->asc.mu_hi;
+  unsigned char* o = (unsigned char*)buf;
+  std::memcpy(o, &h, sizeof h);
+  o += sizeof h;
+  const size_t N = (size_t)c->N;
+  HIPCHK(c, hipMemcpy2DAsync(o, N * sizeof(double), c->J64, c->Np * sizeof(double), N * sizeof(double), N,
+                             hipMemcpyDeviceToHost, c->st));
+  o += N * N * sizeof(double);
+  HIPCHK(c, hipMemcpyAsync(o, c->mu, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  o += N * sizeof(double);
+  if (m > 0)
+    for (const Span& s : state_arrays(c)) {
+      HIPCHK(c, hipMemcpyAsync(o, s.p, s.bytes, hipMemcpyDeviceToHost, c->st));
+      o += s.bytes;
+    }
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  *len = need;
+  return GLMR_OK;
+}
+
+glmr_status glmr_set_state(glmr_ctx* c, const void* buf, size_t len) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (!buf) return fail(c, GLMR_EINVAL, "null state");
+  if (!c->have_spikes) return fail(c, GLMR_ESTATE, "set the spikes of the checkpointed recording first");
+  StateHead h{};
+  if (len < sizeof h) return fail(c, GLMR_EINVAL, "state too short");
+  std::memcpy(&h, buf, sizeof h);
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0) return fail(c, GLMR_EINVAL, "not a checkpoint of this library");
+  const int32_t tm = c->evm ? GLMR_TIME_EVENTS : GLMR_TIME_GRID;
+  if (h.n_neurons != c->N || h.n_bins != c->B || h.time_mode != tm || h.dt != c->dt)
+    return fail(c, GLMR_EINVAL, "the checkpoint is of another recording shape (N, n_bins, dt or time mode)");
+  if (h.spikes_fp != spikes_fingerprint(c))
+    return fail(c, GLMR_EINVAL, "the checkpoint is of other spikes (spike counts differ)");
+  if (h.m < 0 || h.m > 64 || len != state_bytes(c, h.m)) return fail(c, GLMR_EINVAL, "state length or history");
+  if (!(h.tau > 0) || !std::isfinite(h.tau)) return fail(c, GLMR_EINVAL, "bad tau in the checkpoint");
+  TRY(glmr_set_precision(c, h.precision));
+  if (!c->evm && (h.d != c->dly || h.d_self != c->dly_s)) TRY(glmr_set_delays(c, h.d, h.d_self));
+  if (!c->have_kernel || h.tau != c->tau) TRY(glmr_set_kernel(c, h.tau));
+  const unsigned char* p = (const unsigned char*)buf + sizeof h;
+  const size_t N = (size_t)c->N;
+  TRY(glmr_set_params(c, (const double*)p, (const double*)(p + N * N * sizeof(double)), GLMR_HOST));
+  p += (N * N + N) * sizeof(double);
+  if (h.m > 0) {
+    TRY(alloc_ascent(c, h.m));
+    for (const Span& s : state_arrays(c)) {
+      HIPCHK(c, hipMemcpyAsync(s.p, p, s.bytes, hipMemcpyHostToDevice, c->st));
+      p += s.bytes;
+    }
+    c->asc.alpha = h.alpha;
+    c->asc.eps = h.eps;
+    c->asc.jmax = h.jmax;
+    c->asc.mu_lo = h.mu_lo;
+    c->asc.mu_hi = h.mu_hi;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->asc_live = true;
+  }
+  return GLMR_OK;
+}
+
 glmr_status glmr_batch_create(glmr_ctx* const* ctxs, int32_t n, glmr_batch** out) {
   if (!out) return GLMR_EINVAL;
   *out = nullptr;
@@ -1436,6 +1611,7 @@ glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* o_in, glmr_fit_re
   for (glmr_ctx* c : b->ctxs) {
     c->err.clear();
     TRY(check_fit_opts(c, o_in, &o));
+    if (o.resume) return fail(c, GLMR_EINVAL, "a batch fit starts afresh (resume each context on its own)");
   }
   auto t_start = std::chrono::steady_clock::now();
   OnBatchStream on(b);
@@ -1523,6 +1699,7 @@ void glmr_fit_defaults(glmr_fit_opts* o) {
   o->j_max = 0.0;
   o->rate_min = 0.0;
   o->rate_max = 0.0;
+  o->resume = 0;
 }
 
 glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
@@ -1594,6 +1771,7 @@ namespace {
 // regular grid, or the pseudo-bins of the event grid).
 glmr_status ingest_pairs(glmr_ctx* c, const int64_t* bin, const int32_t* neuron, int64_t n) {
   ProfScope ps(c, K_INGEST);
+  c->asc_live = false;
   const int64_t nseg = c->NS * c->NIB;
   IngestBufs b{};
   b.n = n;
@@ -1808,6 +1986,7 @@ glmr_status glmr_set_kernel(glmr_ctx* c, double tau) {
   if (!(tau > 0) || !std::isfinite(tau)) return fail(c, GLMR_EINVAL, "tau must be positive");
   if (!c->evm && tau < c->dt) return fail(c, GLMR_EINVAL, "tau must be >= dt");
   HIPCHK(c, hipSetDevice(c->cfg.device));
+  c->asc_live = false;
   c->tau = tau;
   c->a = std::exp(-c->dt / tau);
   c->have_kernel = false;
@@ -1826,6 +2005,7 @@ glmr_status glmr_set_delays(glmr_ctx* c, int64_t d, int64_t d_self) {
     return fail(c, GLMR_EINVAL, "a self-delay other than d needs FP64, FP32 or BF16");
   HIPCHK(c, hipSetDevice(c->cfg.device));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  c->asc_live = false;
   c->dly = d;
   c->dly_s = d_self;
   if (!c->have_spikes) return GLMR_OK;  // applied when the spikes arrive
@@ -1841,6 +2021,7 @@ glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int3
   if (!J || !mu) return fail(c, GLMR_EINVAL, "null parameter arrays");
   if (where != GLMR_HOST && where != GLMR_DEVICE) return fail(c, GLMR_EINVAL, "bad where");
   HIPCHK(c, hipSetDevice(c->cfg.device));
+  c->asc_live = false;
   const int64_t Np = c->Np;
   if (!c->J64) {
     TRY(dalloc(c, c->J64, (size_t)Np * Np));
@@ -1874,6 +2055,7 @@ glmr_status glmr_set_precision(glmr_ctx* c, int32_t precision) {
   if (precision == c->prec) return GLMR_OK;
   HIPCHK(c, hipSetDevice(c->cfg.device));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  c->asc_live = false;
   c->prec = precision;
   c->cfg.precision = precision;
   setup_precision(c);

@@ -143,6 +143,9 @@ template <bool WANT_Y, bool EV>
 __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
   __shared__ double acc[64][64];
   __shared__ double accy[WANT_Y ? 64 : 1][64];
+  // event grid: the subtile's per-slot tables, staged once per subtile (one
+  // wave per block: every lane reads them after its own wave's writes)
+  __shared__ double sleft[EV ? 64 : 1], sainv[EV ? 64 : 1];
   const int lane = threadIdx.x;
   const int64_t jb = blockIdx.x, ib = blockIdx.y, split = blockIdx.z;
   const int64_t j = jb * 64 + lane;
@@ -162,6 +165,12 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
     const double C = a.C64[s * a.Np + j];
     const double CY = WANT_Y ? a.CY64[s * a.Np + j] : 0.0;
     const uint64_t m0 = a.masks[s * a.Np + j];
+    if constexpr (EV) {
+      __syncthreads();
+      sleft[lane] = a.ev.left[s * 64 + lane];
+      sainv[lane] = a.ev.ainv[s * 64 + lane];
+      __syncthreads();
+    }
     double run = C, P0 = 0.0, P1 = 0.0;
     int bcur = 0;
     for (int32_t eb = e0; eb < e1; eb += 64) {
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
           while (m) {
             const int bb = __builtin_ctzll(m);
             m &= m - 1;
-            const double w = EV ? a.ev.ainv[s * 64 + bb] : a.tab->ainv[bb];
+            const double w = EV ? sainv[bb] : a.tab->ainv[bb];
             run += w;
             if (WANT_Y) { P0 += w; P1 += (double)(bb + 1) * w; }
           }
@@ -186,14 +195,14 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
             while (mp) {
               const int bb = __builtin_ctzll(mp);
               mp &= mp - 1;
-              const double w = EV ? a.ev.ainv[s * 64 + bb] : a.tab->ainv[bb];
+              const double w = EV ? sainv[bb] : a.tab->ainv[bb];
               run += w;
               if (WANT_Y) { P0 += w; P1 += (double)(bb + 1) * w; }
             }
           }
           bcur = b;
         }
-        const double pw = EV ? a.ev.left[s * 64 + b] : a.tab->pw[b];
+        const double pw = EV ? sleft[b] : a.tab->pw[b];
         acc[il][lane] += pw * run;
         if (WANT_Y) accy[il][lane] += pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
       }

@@ -198,3 +198,49 @@ def test_event_grid_fit_reaches_oracle_optimum():
     strong = np.abs(rec.J) >= 0.5
     np.fill_diagonal(strong, False)
     assert np.mean(np.sign(J[strong]) == np.sign(rec.J[strong])) > 0.8
+
+
+def test_event_grid_bf16_tile_shapes_and_autotune(tmp_path):
+    # kernel U's event-grid variant runs on the 128-neuron tiles (shapes 3-6);
+    # every one matches the oracle, they agree with each other far inside the
+    # tolerance, and the autotuner keeps the event grid's choice apart from
+    # the regular grid's in a shared cache
+    import os
+    G = _G()
+    N = 512
+    rec = synth.balanced(N=N, B=5_000, in_frac=0.3, seed=93)
+    times, neu = synth.event_times(rec, seed=6)
+    T0, T1 = 0.0, rec.T
+    J = _round(rec.J, "bf16")
+    ref = O.continuous_eval(_lists(times, neu, N), T0, T1, rec.tau, J, rec.mu)
+    lls = []
+    for k in (3, 4, 5, 6):
+        os.environ["GLMR_RES_SHAPE"] = f"{k},2"
+        try:
+            c, slots = _ctx(N, times, neu, T0, T1, "bf16")
+        finally:
+            os.environ.pop("GLMR_RES_SHAPE", None)
+        c.set_kernel(rec.tau)
+        c.set_params(J, rec.mu)
+        r = c.eval(grad=True)
+        assert c.query()["trace_resident"]
+        c.close()
+        _compare(r, ref, "bf16", slots, N, f"shape {k}")
+        lls.append(r["ll"])
+    assert max(abs(v - lls[0]) for v in lls) <= 1e-9 * abs(lls[0])
+    cache = str(tmp_path / "tune.txt")
+    c, _ = _ctx(N, times, neu, T0, T1, "bf16")
+    c.set_kernel(rec.tau)
+    c.set_params(J, rec.mu)
+    u, g = c.autotune(cache)
+    c.close()
+    assert u in (3, 4, 5, 6) and 0 <= g <= 6
+    grid = G.Context(N, rec.n_bins, rec.dt, "bf16")
+    grid.set_spikes(rec.bins, rec.neurons)
+    grid.set_kernel(rec.tau)
+    grid.set_params(J, rec.mu)
+    grid.autotune(cache)
+    grid.close()
+    lines = open(cache).read().splitlines()
+    print(f"[events autotune] u={u} g={g}; cache {lines}", flush=True)
+    assert len(lines) == 2 and lines[0].split()[1:5] != lines[1].split()[1:5]
