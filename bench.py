@@ -313,7 +313,9 @@ def bench_events(args, G, torch):
     setup = time.perf_counter() - t0
     slots = ctx.B
     ctx.set_params(rec.J, rec.mu)
-    print(f"[events] context ready: {slots} slots, setup {setup:.2f} s", file=sys.stderr, flush=True)
+    tiles = ctx.autotune() if prec == "bf16" and not args.no_tune else (-1, -1)
+    print(f"[events] context ready: {slots} slots, setup {setup:.2f} s, tile shapes {tiles}",
+          file=sys.stderr, flush=True)
     sec, r = time_steps(ctx, args.steps, args.warmup)
     kt = kernel_times(ctx, reps=1)
     q = ctx.query()
@@ -333,7 +335,8 @@ def bench_events(args, G, torch):
         "data": "synthetic",
         "config": {"workload": "balanced_n1000_indeg100_t3600s_event_grid", "n_neurons": N,
                    "n_events": int(times.shape[0]), "n_slots": slots, "precision": prec,
-                   "chunk_slots": q["chunk_bins"], "n_pad": q["n_pad"], "trace_resident": q["trace_resident"]},
+                   "chunk_slots": q["chunk_bins"], "n_pad": q["n_pad"], "trace_resident": q["trace_resident"],
+                   "tile_shapes": list(tiles)},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None, "kernel": dom,
                      "launch_ms": per_launch_s * 1e3, "launches_per_step": launches,
