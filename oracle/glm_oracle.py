@@ -400,6 +400,118 @@ def newton_fit(bins, neurons, N: int, B: int, dt: float, tau: float,
     return J, mu, dict(iters=iters)
 
 
+def _trace_chunks(S, a: float, chunk: int):
+    """The trace of a recording chunk by chunk, (b0, X_chunk) with the value at
+    each chunk's first bin carried over from the chunk before."""
+    N = S.shape[1]
+    B = S.shape[0]
+    x0 = np.zeros(N)
+    for b0 in range(0, B, chunk):
+        b1 = min(B, b0 + chunk)
+        Sc = S[b0:b1].toarray().astype(np.float64)
+        X = trace_lfilter(Sc, a, x0)
+        # the trace at bin b1: one more step of the recursion from the chunk's last row
+        x0 = a * X[-1] + Sc[-1]
+        yield b0, X
+
+
+def _rows_pass(chunks, s_rows: Dict[int, np.ndarray], dt: float, thetas: Dict[int, np.ndarray],
+               hessian: bool):
+    """One pass over the time axis for the rows in `thetas` (row -> (mu_i, J_i)):
+    L_i and, if `hessian`, the gradient and the Hessian of Eq. (18), each summed
+    chunk by chunk.  `chunks` yields (b0, trace chunk); s_rows[i] is row i's
+    spike counts per bin."""
+    parts = {i: [] for i in thetas}
+    P = None
+    g = H = None
+    for b0, X in chunks:
+        if P is None:
+            P = X.shape[1] + 1
+            g = {i: np.zeros(P) for i in thetas} if hessian else None
+            H = {i: np.zeros((P, P)) for i in thetas} if hessian else None
+        b1 = b0 + X.shape[0]
+        for i, th in thetas.items():
+            s = s_rows[i][b0:b1]
+            U = th[0] + X @ th[1:]
+            lam = np.exp(U)
+            parts[i].append(float(np.sum(s * U)) - dt * float(np.sum(lam)))
+            if hessian:
+                r = s - dt * lam
+                g[i][0] += r.sum()
+                g[i][1:] += X.T @ r
+                w = dt * lam
+                Xw = X.T @ w
+                H[i][0, 0] -= w.sum()
+                H[i][0, 1:] -= Xw
+                H[i][1:, 0] -= Xw
+                H[i][1:, 1:] -= (X * w[:, None]).T @ X
+    L = {i: math.fsum(v) for i, v in parts.items()}
+    return L, g, H
+
+
+def newton_rows(bins, neurons, N: int, B: int, dt: float, tau: float, rows: Sequence[int],
+                max_iter: int = 60, eta_tol: float = 1e-15, chunk: int = DEFAULT_CHUNK,
+                log=None, cache_bytes: float = 40e9):
+    """Exact per-row Newton ascent for the rows `rows` of a recording too long
+    for one dense trace matrix: L is separable over rows (Sec. 2.2) and each
+    row's problem is concave (App. A), so each row's maximiser is found on its
+    own with the Hessian of Eq. (18), summed over time chunks.  Start:
+    J_i = 0 and mu_i = log(q_i / T) (the maximiser at J_i = 0).  A step is the
+    Newton step scaled by t = 1, 1/2, 1/4, ... until the Armijo condition
+    holds; the trial point's gradient and Hessian are taken in the same pass as
+    its L.  A row stops when the fractional change of L_i is below eta_tol
+    (Sec. 2.6.3) or its Newton decrement vanishes.  The trace chunks are kept
+    in memory when they take at most cache_bytes.
+    Returns dict(row -> dict(mu, J, ll, iters, decrement, se)); se holds the
+    standard errors sqrt(diag(-H^-1)) of (mu_i, J_i) at the result (the
+    curvature of Eq. (18), the resolution the data allow)."""
+    S = spike_matrix(bins, neurons, N, B)
+    a = decay(dt, tau)
+    q = spike_counts(neurons, N)
+    Sc = S.tocsc()
+    s_rows = {int(i): Sc[:, int(i)].toarray().ravel().astype(np.float64) for i in rows}
+    if 8.0 * N * B <= cache_bytes:
+        cached = list(_trace_chunks(S, a, chunk))
+        chunks = lambda: iter(cached)  # noqa: E731
+    else:
+        chunks = lambda: _trace_chunks(S, a, chunk)  # noqa: E731
+    th = {int(i): np.concatenate([[math.log(q[i] / (B * dt))], np.zeros(N)]) for i in rows}
+    L, g, H = _rows_pass(chunks(), s_rows, dt, th, True)
+    out = {}
+    active = set(th)
+    for k in range(1, max_iter + 1):
+        if not active:
+            break
+        step = {i: np.linalg.solve(H[i], -g[i]) for i in active}
+        dec = {i: float(g[i] @ step[i]) for i in active}
+        t = {i: 1.0 for i in active}
+        L_old = {i: L[i] for i in active}
+        pending = set(active)
+        while pending:
+            trial = {i: th[i] + t[i] * step[i] for i in pending}
+            Lt, gt, Ht = _rows_pass(chunks(), s_rows, dt, trial, True)
+            for i in list(pending):
+                if np.isfinite(Lt[i]) and Lt[i] >= L[i] + 1e-4 * t[i] * dec[i]:
+                    th[i], L[i], g[i], H[i] = trial[i], Lt[i], gt[i], Ht[i]
+                    pending.discard(i)
+                else:
+                    t[i] *= 0.5
+                    if t[i] < 1e-12:
+                        pending.discard(i)  # no ascent left: stay
+        for i in list(active):
+            eta = abs(L[i] - L_old[i]) / max(abs(L[i]), 1e-300)
+            if log is not None:
+                log(f"row {i} iter {k}: L {L[i]!r} eta {eta:.3e} decrement {dec[i]:.3e} step {t[i]}")
+            if eta <= eta_tol or dec[i] <= 1e-13 * max(abs(L[i]), 1.0):
+                out[i] = dict(mu=float(th[i][0]), J=th[i][1:].copy(), ll=L[i], iters=k, decrement=dec[i],
+                              se=np.sqrt(np.diag(np.linalg.inv(-H[i]))))
+                active.discard(i)
+    for i in active:  # iteration cap
+        out[i] = dict(mu=float(th[i][0]), J=th[i][1:].copy(), ll=L[i], iters=max_iter, decrement=float("nan"),
+                      se=np.sqrt(np.diag(np.linalg.inv(-H[i]))))
+    return out
+
+
 def lbfgs_fit(bins, neurons, N: int, B: int, dt: float, tau: float,
               J0: Optional[np.ndarray] = None, mu0: Optional[np.ndarray] = None,
               ftol: float = 1e-15, gtol: float = 1e-10, maxiter: int = 5000,

@@ -38,7 +38,7 @@ def test_autograd_matches_oracle_and_fd():
     L.backward()
     gJ, gmu, gtau = J.grad.cpu().numpy(), mu.grad.cpu().numpy(), float(tau.grad)
     ref = O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, 0.015, J0, rec.mu, want_tau=True)
-    rl = abs(float(L) - ref["ll"]) / abs(ref["ll"])
+    rl = abs(float(L.detach()) - ref["ll"]) / abs(ref["ll"])
     rg = np.linalg.norm(np.concatenate([gmu - ref["gmu"], (gJ - ref["gJ"]).ravel()])) / \
         np.linalg.norm(np.concatenate([ref["gmu"], ref["gJ"].ravel()]))
     rt = abs(gtau - ref["gtau"]) / abs(ref["gtau"])

@@ -481,3 +481,35 @@ def test_delayed_gradient_matches_finite_differences():
     fd = (O.loglik_delayed(bins, neu, N, B, dt, tau, J, mp, d, ds)["ll_rows"][2]
           - O.loglik_delayed(bins, neu, N, B, dt, tau, J, mm, d, ds)["ll_rows"][2]) / (2 * h)
     assert abs(fd - r["gmu"][2]) < 1e-6 * (1 + abs(fd))
+
+
+def test_newton_rows_chunked_matches_dense_newton_and_kkt():
+    """The oracle's chunked per-row Newton (the full-size reference fits) reaches
+    the dense per-row Newton's optimum with chunk boundaries inside the
+    recording (2e4 bins in chunks of 3000: a ragged last chunk), and the
+    likelihood's own gradient vanishes there (App. A: a concave row problem
+    has one maximiser)."""
+    import synth
+    rec = synth.config1(0)
+    N, B = rec.n_neurons, rec.n_bins
+    rows = [0, 7, 45]
+    res = O.newton_rows(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, rows, chunk=3000)
+    # the trace rebuilt on every pass instead of kept: the same iterates
+    res2 = O.newton_rows(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, rows, chunk=3000, cache_bytes=0)
+    for i in rows:
+        assert np.array_equal(res[i]["J"], res2[i]["J"]) and res[i]["iters"] == res2[i]["iters"]
+    Jn, mun, _ = O.newton_fit(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, rows=rows)
+    J = np.zeros((N, N))
+    mu = np.zeros(N)
+    for i in rows:
+        assert np.abs(res[i]["J"] - Jn[i]).max() < 1e-8 and abs(res[i]["mu"] - mun[i]) < 1e-9
+        J[i], mu[i] = res[i]["J"], res[i]["mu"]
+    r = O.loglik(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, J, mu, rows=rows)
+    q = O.spike_counts(rec.neurons, N)
+    r0 = O.loglik(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, np.zeros((N, N)), np.log(q / (B * rec.dt)),
+                  rows=rows)
+    for k, i in enumerate(rows):
+        assert res[i]["ll"] == pytest.approx(float(r["ll_rows"][k]), rel=1e-13)
+        g = np.abs(np.concatenate([[r["gmu"][k]], r["gJ"][k]])).max()
+        g0 = np.abs(np.concatenate([[r0["gmu"][k]], r0["gJ"][k]])).max()
+        assert g <= 1e-9 * g0
