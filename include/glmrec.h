@@ -305,10 +305,14 @@ glmr_status glmr_set_state(glmr_ctx* ctx, const void* buf, size_t len);
 /* ---------------------------------------------------------------- batching
  * Many independent recordings (contexts of possibly different N and B, all
  * on one device, all in GLMR_BF16 or all in the same precision) evaluated in
- * one persistent launch per contraction, with a work queue over
- * (recording, time tile, neuron tile).  The contexts must each have had
- * set_spikes, set_kernel and set_params called.  The batch does not own the
- * contexts; they must outlive it. */
+ * persistent launches with a work queue over (recording, time tile, neuron
+ * tile): recordings with the same tile shapes share one launch per
+ * contraction.  Each recording takes the shapes the batch autotuner chose
+ * for its class (padding that allows 256-neuron tiles, or not), else its
+ * context's own, so that a batch evaluation equals each context's own
+ * evaluation with those shapes.  The contexts must each have had set_spikes,
+ * set_kernel and set_params called.  The batch does not own the contexts;
+ * they must outlive it. */
 typedef struct glmr_batch glmr_batch;
 
 glmr_status glmr_batch_create(glmr_ctx* const* ctxs, int32_t n, glmr_batch** out);
@@ -329,11 +333,14 @@ glmr_status glmr_batch_get_grad(glmr_batch* b, int32_t r, double* grad_J, double
  * (nullable). */
 glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* opts, glmr_fit_report* reports);
 
-/* Autotuner of the grouped launches: times every tile shape that all the
- * batch's recordings allow on the batch's first time chunk (three launches of
- * each grouped kernel) and keeps the fastest for later batch calls.  Cache as
- * in glmr_autotune, keyed by the architecture, precision and the recordings'
- * padded sizes.  Reports -1 when the batch is not grouped (some trace not
+/* Autotuner of the grouped launches: for each class of recordings (padding
+ * that allows 256-neuron tiles, and the rest) times every tile shape that all
+ * its recordings allow, by the batch's first time chunk (three rounds of
+ * every grouped launch of each contraction, the other class at its current
+ * shapes), and keeps the fastest for later batch calls.  Reports the shapes
+ * of the first class present.  Cache as in glmr_autotune (one line per
+ * batch), keyed by the architecture, precision and the recordings' padded
+ * sizes.  Reports -1 when the batch is not grouped (some trace not
  * resident).  Clobbers the contexts' evaluation workspaces. */
 glmr_status glmr_batch_autotune(glmr_batch* b, const char* cache_path, int32_t* shape_u,
                                 int32_t* shape_g);

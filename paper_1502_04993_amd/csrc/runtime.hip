@@ -1115,15 +1115,22 @@ struct glmr_batch {
   std::vector<glmr_ctx*> ctxs;
   int dev = 0;
   hipStream_t st = nullptr;
-  bool grouped = false;  // one persistent launch per contraction over every recording
-  int shape_u = -1, shape_g = -1;
-  int tuned_u = -1, tuned_g = -1;  // set by glmr_batch_autotune
-  struct Chunk {         // the recordings that have time chunk ci, as work queues
+  bool grouped = false;  // persistent launches over the recordings, one per tile shape and contraction
+  // Tile shapes per recording: those the autotuner chose for its class (the
+  // recordings whose padding allows 256-neuron tiles, and the rest), else the
+  // context's own.  Recordings with the same pair share one launch.
+  int tuned_u[2] = {-1, -1}, tuned_g[2] = {-1, -1};
+  std::vector<int> rec_u, rec_g;
+  struct Group {         // recordings of one chunk with the same shapes, as work queues
+    int su = -1, sg = -1;
     std::vector<int> recs, nsplits;
     ResUArgs* du = nullptr;
     ResGArgs* dg = nullptr;
     int64_t *pu = nullptr, *pg = nullptr;
     int64_t tu = 0, tg = 0;
+  };
+  struct Chunk {         // the recordings that have time chunk ci
+    std::vector<Group> groups;
   };
   std::vector<Chunk> chunks;
   int32_t** dcnt = nullptr;  // [n] each context's counters
@@ -1170,19 +1177,8 @@ struct OnBatchStream {
   }
 };
 
-// first tile shape valid for every recording, preferring the given one
-int common_shape(glmr_batch* b, int pref) {
-  static const int order[] = {2, 5, 3, 6, 0, 4, 1};
-  auto ok_all = [&](int k) {
-    for (glmr_ctx* c : b->ctxs)
-      if (!shape_ok(c, k)) return false;
-    return true;
-  };
-  if (ok_all(pref)) return pref;
-  for (int k : order)
-    if (ok_all(k)) return k;
-  return -1;
-}
+// shape class of a recording: 0 if its padding allows the 256-neuron tiles
+int shape_class(const glmr_ctx* c) { return c->Np % 256 == 0 ? 0 : 1; }
 
 // Work queues for the grouped launches (after every context's workspace exists).
 glmr_status build_queues(glmr_batch* b) {
@@ -1203,32 +1199,67 @@ glmr_status build_queues(glmr_batch* b) {
   b->chunks.resize(nch);
   for (int64_t ci = 0; ci < nch; ++ci) {
     glmr_batch::Chunk& ch = b->chunks[ci];
-    std::vector<ResUArgs> ua;
-    std::vector<ResGArgs> ga;
-    std::vector<int64_t> pu{0}, pg{0};
+    struct Lists {
+      std::vector<ResUArgs> ua;
+      std::vector<ResGArgs> ga;
+      std::vector<int64_t> pu{0}, pg{0};
+    };
+    std::vector<Lists> lists;
     for (int r = 0; r < n; ++r) {
       glmr_ctx* c = b->ctxs[r];
       const int64_t t0 = ci * c->L;
       if (t0 >= c->Bp) continue;
       const int64_t Lc = std::min<int64_t>(c->L, c->Bp - t0);
-      ua.push_back(make_u_args(c, b->shape_u, t0, Lc));
-      ga.push_back(make_g_args(c, b->shape_g, t0, Lc));
-      pu.push_back(pu.back() + (int64_t)ua.back().n_itiles * ua.back().n_ttiles);
-      pg.push_back(pg.back() + (int64_t)ga.back().n_splits * ga.back().n_itiles * ga.back().n_jtiles);
-      ch.recs.push_back(r);
-      ch.nsplits.push_back(ga.back().n_splits);
+      size_t q = 0;
+      while (q < ch.groups.size() && !(ch.groups[q].su == b->rec_u[r] && ch.groups[q].sg == b->rec_g[r])) ++q;
+      if (q == ch.groups.size()) {
+        ch.groups.emplace_back();
+        ch.groups.back().su = b->rec_u[r];
+        ch.groups.back().sg = b->rec_g[r];
+        lists.emplace_back();
+      }
+      glmr_batch::Group& gr = ch.groups[q];
+      Lists& li = lists[q];
+      li.ua.push_back(make_u_args(c, gr.su, t0, Lc));
+      li.ga.push_back(make_g_args(c, gr.sg, t0, Lc));
+      li.pu.push_back(li.pu.back() + (int64_t)li.ua.back().n_itiles * li.ua.back().n_ttiles);
+      li.pg.push_back(li.pg.back() + (int64_t)li.ga.back().n_splits * li.ga.back().n_itiles * li.ga.back().n_jtiles);
+      gr.recs.push_back(r);
+      gr.nsplits.push_back(li.ga.back().n_splits);
     }
-    const size_t m = ch.recs.size();
-    HIPCHK(c0, balloc(b, ch.du, m));
-    HIPCHK(c0, balloc(b, ch.dg, m));
-    HIPCHK(c0, balloc(b, ch.pu, m + 1));
-    HIPCHK(c0, balloc(b, ch.pg, m + 1));
-    HIPCHK(c0, hipMemcpy(ch.du, ua.data(), m * sizeof(ResUArgs), hipMemcpyHostToDevice));
-    HIPCHK(c0, hipMemcpy(ch.dg, ga.data(), m * sizeof(ResGArgs), hipMemcpyHostToDevice));
-    HIPCHK(c0, hipMemcpy(ch.pu, pu.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-    HIPCHK(c0, hipMemcpy(ch.pg, pg.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-    ch.tu = pu.back();
-    ch.tg = pg.back();
+    for (size_t q = 0; q < ch.groups.size(); ++q) {
+      glmr_batch::Group& gr = ch.groups[q];
+      const Lists& li = lists[q];
+      const size_t m = gr.recs.size();
+      HIPCHK(c0, balloc(b, gr.du, m));
+      HIPCHK(c0, balloc(b, gr.dg, m));
+      HIPCHK(c0, balloc(b, gr.pu, m + 1));
+      HIPCHK(c0, balloc(b, gr.pg, m + 1));
+      HIPCHK(c0, hipMemcpy(gr.du, li.ua.data(), m * sizeof(ResUArgs), hipMemcpyHostToDevice));
+      HIPCHK(c0, hipMemcpy(gr.dg, li.ga.data(), m * sizeof(ResGArgs), hipMemcpyHostToDevice));
+      HIPCHK(c0, hipMemcpy(gr.pu, li.pu.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+      HIPCHK(c0, hipMemcpy(gr.pg, li.pg.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+      gr.tu = li.pu.back();
+      gr.tg = li.pg.back();
+    }
+  }
+  return GLMR_OK;
+}
+
+// The grouped launches of kernel U (want_u) and kernel G (want_g) over chunk ci.
+glmr_status launch_chunk_groups(glmr_batch* b, size_t ci, bool want_u, bool want_g) {
+  glmr_ctx* c0 = b->ctxs[0];
+  const int fp8 = c0->prec == PREC_FP8 ? 1 : 0;
+  for (const glmr_batch::Group& gr : b->chunks[ci].groups) {
+    const int m = (int)gr.recs.size();
+    if (want_u) {
+      ProfScope ps(c0, K_BU);
+      HIPCHK(c0, launch_res_u_group(gr.su, fp8, ResUGroup{gr.du, gr.pu, m, gr.tu}, b->st));
+    }
+    if (want_g) {
+      ProfScope ps(c0, K_BG);
+      HIPCHK(c0, launch_res_g_group(gr.sg, fp8, ResGGroup{gr.dg, gr.pg, m, gr.tg}, b->st));
+    }
   }
   return GLMR_OK;
 }
@@ -1239,23 +1270,13 @@ glmr_status batch_eval_core(glmr_batch* b) {
     for (glmr_ctx* c : b->ctxs) TRY(eval_core(c, true, false));
     return GLMR_OK;
   }
-  glmr_ctx* c0 = b->ctxs[0];
-  const int fp8 = c0->prec == PREC_FP8 ? 1 : 0;
   for (size_t ci = 0; ci < b->chunks.size(); ++ci) {
-    const glmr_batch::Chunk& ch = b->chunks[ci];
-    const int m = (int)ch.recs.size();
-    {
-      ProfScope ps(c0, K_BU);
-      HIPCHK(c0, launch_res_u_group(b->shape_u, fp8, ResUGroup{ch.du, ch.pu, m, ch.tu}, b->st));
-    }
-    {
-      ProfScope ps(c0, K_BG);
-      HIPCHK(c0, launch_res_g_group(b->shape_g, fp8, ResGGroup{ch.dg, ch.pg, m, ch.tg}, b->st));
-    }
-    for (int q = 0; q < m; ++q) {
-      glmr_ctx* c = b->ctxs[ch.recs[q]];
-      HIPCHK(c, launch_gp_reduce(c->prec, c->Gp, ch.nsplits[q], c->Np, c->G64, ci == 0, b->st));
-    }
+    TRY(launch_chunk_groups(b, ci, true, true));
+    for (const glmr_batch::Group& gr : b->chunks[ci].groups)
+      for (size_t q = 0; q < gr.recs.size(); ++q) {
+        glmr_ctx* c = b->ctxs[gr.recs[q]];
+        HIPCHK(c, launch_gp_reduce(c->prec, c->Gp, gr.nsplits[q], c->Np, c->G64, ci == 0, b->st));
+      }
   }
   for (glmr_ctx* c : b->ctxs) TRY(eval_finish(c, true, false));
   return GLMR_OK;
@@ -1486,10 +1507,15 @@ glmr_status batch_prepare(glmr_batch* b) {
     grouped = grouped && c->resident && !self_delayed(c) && !c->evm;
   }
   b->grouped = grouped;
-  if (grouped) {
-    b->shape_u = common_shape(b, b->tuned_u >= 0 ? b->tuned_u : b->ctxs[0]->res_shape_u);
-    b->shape_g = common_shape(b, b->tuned_g >= 0 ? b->tuned_g : b->ctxs[0]->res_shape_g);
-    b->grouped = b->shape_u >= 0 && b->shape_g >= 0;
+  const size_t n = b->ctxs.size();
+  b->rec_u.assign(n, -1);
+  b->rec_g.assign(n, -1);
+  for (size_t r = 0; r < n; ++r) {
+    glmr_ctx* c = b->ctxs[r];
+    const int k = shape_class(c);
+    const int u = b->tuned_u[k], g = b->tuned_g[k];
+    b->rec_u[r] = (u >= 0 && shape_ok_u(c, u)) ? u : c->res_shape_u;
+    b->rec_g[r] = (g >= 0 && shape_ok(c, g)) ? g : c->res_shape_g;
   }
   return build_queues(b);
 }
@@ -1533,7 +1559,7 @@ glmr_status glmr_batch_autotune(glmr_batch* b, const char* cache_path, int32_t* 
   glmr_ctx* c0 = b->ctxs[0];
   HIPCHK(c0, hipSetDevice(b->dev));
   OnBatchStream on(b);
-  b->tuned_u = b->tuned_g = -1;
+  for (int k = 0; k < 2; ++k) b->tuned_u[k] = b->tuned_g[k] = -1;
   TRY(batch_prepare(b));
   if (!b->grouped) {
     if (shape_u) *shape_u = -1;
@@ -1550,56 +1576,88 @@ glmr_status glmr_batch_autotune(glmr_batch* b, const char* cache_path, int32_t* 
   }
   char kb[64];
   std::snprintf(kb, sizeof(kb), "batch%zu-%016llx", b->ctxs.size(), (unsigned long long)h);
-  std::string key = tune_key(c0);
-  key = key.substr(0, key.find(' ')) + " " + kb + " 0 " + std::to_string(c0->prec);
-  int best_u = -1, best_g = -1;
+  std::string arch = tune_key(c0);
+  arch = arch.substr(0, arch.find(' '));
+  const std::string key = arch + " " + kb + " " + std::to_string(c0->prec);
+  bool have[2] = {false, false};
+  for (glmr_ctx* c : b->ctxs) have[shape_class(c)] = true;
+  auto all_ok = [&](int cls, int k, bool u) {
+    for (glmr_ctx* c : b->ctxs)
+      if (shape_class(c) == cls && !(u ? shape_ok_u(c, k) : shape_ok(c, k))) return false;
+    return true;
+  };
+  bool cached = false;
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
       char line[512];
       while (std::fgets(line, sizeof(line), f)) {
-        char arch[128], k2[128];
-        long long l = 0;
-        int prec = -1, u = -1, g = -1;
-        if (std::sscanf(line, "glmrec-tune %127s %127s %lld %d %d %d", arch, k2, &l, &prec, &u, &g) == 6) {
-          const std::string kk = std::string(arch) + " " + k2 + " " + std::to_string(l) + " " + std::to_string(prec);
-          if (kk == key && common_shape(b, u) == u && common_shape(b, g) == g) {
-            best_u = u;
-            best_g = g;
+        char a[128], k2[128];
+        int prec = -1, u0 = -1, g0 = -1, u1 = -1, g1 = -1;
+        if (std::sscanf(line, "glmrec-tune-batch %127s %127s %d %d %d %d %d", a, k2, &prec, &u0, &g0, &u1, &g1) ==
+            7) {
+          const std::string kk = std::string(a) + " " + k2 + " " + std::to_string(prec);
+          const int us[2] = {u0, u1}, gs[2] = {g0, g1};
+          bool ok = kk == key;
+          for (int c = 0; c < 2 && ok; ++c)
+            if (have[c]) ok = all_ok(c, us[c], true) && all_ok(c, gs[c], false);
+          if (ok) {
+            for (int c = 0; c < 2; ++c) {
+              b->tuned_u[c] = have[c] ? us[c] : -1;
+              b->tuned_g[c] = have[c] ? gs[c] : -1;
+            }
+            cached = true;
           }
         }
       }
       std::fclose(f);
     }
   }
-  if (best_u < 0) {
+  if (!cached) {
+    // one class at a time (the other at its current shapes): the time of the
+    // first chunk's launches of each contraction, every group included
     int n = 0;
     (void)res_shapes(&n);
-    const int fp8 = c0->prec == PREC_FP8 ? 1 : 0;
-    double tu = 1e300, tg = 1e300;
-    for (int k = 0; k < n; ++k) {
-      if (common_shape(b, k) != k) continue;
-      b->shape_u = b->shape_g = k;
-      TRY(build_queues(b));
-      const glmr_batch::Chunk& ch = b->chunks[0];
-      const int m = (int)ch.recs.size();
-      double ms = 0;
-      TRY(time_launches(c0, [&] { return launch_res_u_group(k, fp8, ResUGroup{ch.du, ch.pu, m, ch.tu}, b->st); }, 3, &ms));
-      if (ms < tu) { tu = ms; best_u = k; }
-      TRY(time_launches(c0, [&] { return launch_res_g_group(k, fp8, ResGGroup{ch.dg, ch.pg, m, ch.tg}, b->st); }, 3, &ms));
-      if (ms < tg) { tg = ms; best_g = k; }
+    double tu = 0, tg = 0;
+    for (int cls = 0; cls < 2; ++cls) {
+      if (!have[cls]) continue;
+      int best_u = -1, best_g = -1;
+      double bu = 1e300, bg = 1e300;
+      for (int k = 0; k < n; ++k) {
+        const bool oku = all_ok(cls, k, true), okg = all_ok(cls, k, false);
+        if (!oku && !okg) continue;
+        const int su = b->tuned_u[cls], sg = b->tuned_g[cls];
+        b->tuned_u[cls] = oku ? k : su;
+        b->tuned_g[cls] = okg ? k : sg;
+        TRY(batch_prepare(b));
+        double ms = 0;
+        if (oku) {
+          TRY(time_launches(c0, [&] { return launch_chunk_groups(b, 0, true, false) == GLMR_OK ? hipSuccess : hipErrorUnknown; }, 3, &ms));
+          if (ms < bu) { bu = ms; best_u = k; }
+        }
+        if (okg) {
+          TRY(time_launches(c0, [&] { return launch_chunk_groups(b, 0, false, true) == GLMR_OK ? hipSuccess : hipErrorUnknown; }, 3, &ms));
+          if (ms < bg) { bg = ms; best_g = k; }
+        }
+        b->tuned_u[cls] = su;
+        b->tuned_g[cls] = sg;
+      }
+      b->tuned_u[cls] = best_u;
+      b->tuned_g[cls] = best_g;
+      tu = bu;
+      tg = bg;
     }
-    if (cache_path && best_u >= 0) {
+    if (cache_path) {
       if (FILE* f = std::fopen(cache_path, "a")) {
-        std::fprintf(f, "glmrec-tune %s %d %d %.4f %.4f\n", key.c_str(), best_u, best_g, tu, tg);
+        std::fprintf(f, "glmrec-tune-batch %s %d %d %d %d %.4f %.4f\n", key.c_str(), b->tuned_u[0], b->tuned_g[0],
+                     b->tuned_u[1], b->tuned_g[1], tu, tg);
         std::fclose(f);
       }
     }
   }
-  b->tuned_u = best_u;
-  b->tuned_g = best_g;
   TRY(batch_prepare(b));
-  if (shape_u) *shape_u = b->shape_u;
-  if (shape_g) *shape_g = b->shape_g;
+  const int cls = have[0] ? 0 : 1;
+  if (shape_u) *shape_u = b->tuned_u[cls];
+  if (shape_g) *shape_g = b->tuned_g[cls];
   return GLMR_OK;
 }
 

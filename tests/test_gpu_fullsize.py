@@ -70,3 +70,67 @@ def test_full_size_sampled_rows(tmp_path):
               f"{rgt:.3e} (theta = 0: {rg:.3e})", flush=True)
         assert rl.max() <= TOL[prec][0] and rl0.max() <= TOL[prec][0]
         assert rgt <= TOL[prec][1] and rg <= TOL[prec][1]
+
+
+def _fingerprint(rec):
+    """Spike count and a checksum of the (bin, neuron) pairs (as the reference stores them)."""
+    b = rec.bins.astype(np.int64)
+    n = rec.neurons.astype(np.int64)
+    return dict(n_spikes=int(b.shape[0]), checksum=int(np.sum((b * 1009 + n) % 1000003)))
+
+
+def test_full_size_fit_reaches_oracle_row_optima():
+    """The headline reconstruction (BF16 ascent from J = 0 to its stopping
+    test, then an FP32 polish from the BF16 optimum) against the oracle's exact
+    optimum of sampled rows of the same recording (per-row Newton on the
+    Hessian of Eq. (18), stored by tests/golden/make_config2_newton.py with the
+    entries' standard errors).  Distances are in standard errors, the
+    resolution the data allow.  Classes: the fit's k-means centroids (Sec. 3.3)
+    applied to the oracle's rows give the fit's classes except for entries
+    that the fit's own error could carry across a class boundary."""
+    import json
+    import os
+    import paper_1502_04993_amd as G
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config2_newton_rows.json")))
+    rec = synth.cached("config2", seed=0, B=3_600_000)
+    fp = _fingerprint(rec)
+    assert (fp["n_spikes"], fp["checksum"]) == (ref["recording"]["n_spikes"], ref["recording"]["checksum"])
+    N, B = rec.n_neurons, rec.n_bins
+    ctx = G.Context(N, B, rec.dt, precision="bf16")
+    ctx.set_spikes(rec.bins, rec.neurons)
+    ctx.set_kernel(rec.tau)
+    rb = ctx.fit(max_iter=400, from_zero=True)
+    Jb, mub, _ = ctx.get_params()
+    ctx.set_precision("fp32")
+    rp = ctx.fit(max_iter=60)
+    Jp, mup, _ = ctx.get_params()
+    ctx.close()
+    print(f"[full fit] bf16 {rb}\n[full fit] fp32 polish {rp}", flush=True)
+    _, c = O.kmeans3(Jp[~np.eye(N, dtype=bool)])
+    bounds = np.array([(c[0] + c[1]) / 2, (c[1] + c[2]) / 2])
+    lab = O.classify(Jp)
+    zb = zp = zmu = 0.0
+    flips = near = 0
+    for r in ref["rows"]:
+        i = r["row"]
+        Jr = np.array([float(v) for v in r["J"]])
+        se = np.array(r["se_J"])
+        zb = max(zb, float(np.max(np.abs(Jb[i] - Jr) / se)))
+        zp = max(zp, float(np.max(np.abs(Jp[i] - Jr) / se)))
+        zmu = max(zmu, abs(mup[i] - float(r["mu"])) / r["se_mu"])
+        off = np.arange(N) != i
+        lab_ref = np.argmin(np.abs(Jr[:, None] - c[None, :]), axis=1)
+        close = np.min(np.abs(Jr[:, None] - bounds[None, :]), axis=1) <= 2 * np.abs(Jp[i] - Jr) + 1e-12
+        differ = (lab[i] != lab_ref) & off
+        flips += int(np.sum(differ))
+        near += int(np.sum(differ & close))
+        assert np.all(~differ | close), (i, np.nonzero(differ & ~close))
+    print(f"[full fit] max |J - J_oracle| / SE: BF16 {zb:.3f}, after the FP32 polish {zp:.4f}; "
+          f"mu {zmu:.4f}; class differences {flips} (all within the fit's error of a boundary: {near})",
+          flush=True)
+    # BF16 evaluates the likelihood at bf16(J) with a stochastically rounded
+    # trace (gradient error ~3e-4): its optimum lies within the data's own
+    # resolution, one standard error, of the exact one (0.50 measured on these
+    # rows); the FP32 polish brings it to a small fraction of it (0.004)
+    assert rb["converged"] and zb < 1.0
+    assert zp < 0.05 and zmu < 0.05
