@@ -309,7 +309,7 @@ def loglik_delayed(bins, neurons, N: int, B: int, dt: float, tau: float, J: np.n
 
 def spike_term_matrix(bins, neurons, N: int, B: int, dt: float, tau: float,
                       chunk: int = DEFAULT_CHUNK) -> np.ndarray:
-    """partial^Sigma_ij = sum_t s_i[t] x_j[t] (Eq. (12)); parameter-free (L212)."""
+    """partial^Sigma_ij = sum_t s_i[t] x_j[t] (Eq. (12)); parameter-free; computed once per tau (Sec. 2.3.3)."""
     S = spike_matrix(bins, neurons, N, B)
     a = decay(dt, tau)
     D = np.zeros((N, N))
