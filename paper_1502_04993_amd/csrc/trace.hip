@@ -137,15 +137,18 @@ __global__ void k_carry_apply(CarryArgs c) {
 
 // ------------------------------------------------------------ spike term
 __device__ inline int lane_bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline double lane_bcast_d(double v, int l) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 // EV: event grid; the trace at a spike is its left limit at the event time
 template <bool WANT_Y, bool EV>
 __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
   __shared__ double acc[64][64];
   __shared__ double accy[WANT_Y ? 64 : 1][64];
-  // event grid: the subtile's per-slot tables, staged once per subtile (one
-  // wave per block: every lane reads them after its own wave's writes)
-  __shared__ double sleft[EV ? 64 : 1], sainv[EV ? 64 : 1];
   const int lane = threadIdx.x;
   const int64_t jb = blockIdx.x, ib = blockIdx.y, split = blockIdx.z;
   const int64_t j = jb * 64 + lane;
@@ -157,54 +160,139 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
   const int64_t sb = split * per;
   const int64_t se = (sb + per < a.NS) ? sb + per : a.NS;
   const double ctau = a.ctau;
-  for (int64_t s = sb; s < se; ++s) {
+  // The loads of a subtile (its segment bounds, this lane's carry and mask,
+  // the event grid's slot tables) are issued one subtile ahead, so that their
+  // latency overlaps the walk of the spikes before.
+  struct Pre {
+    int32_t e0, e1;
+    double C, CY, left, ainv;
+    uint64_t m0;
+  };
+  auto fetch = [&](int64_t s) {
+    Pre p;
     const int64_t sg = s * a.NIB + ib;
-    const int32_t e0 = a.seg_off[sg], e1 = a.seg_off[sg + 1];
+    p.e0 = a.seg_off[sg];
+    p.e1 = a.seg_off[sg + 1];
+    p.C = a.C64[s * a.Np + j];
+    p.CY = WANT_Y ? a.CY64[s * a.Np + j] : 0.0;
+    p.m0 = a.masks[s * a.Np + j];
+    p.left = EV ? a.ev.left[s * 64 + lane] : 0.0;
+    p.ainv = EV ? a.ev.ainv[s * 64 + lane] : 0.0;
+    return p;
+  };
+  // lane b holds the factors of bin b: the decay a^b and a^-(b+1) (the event
+  // grid's are per subtile)
+  const double pw_grid = EV ? 0.0 : a.tab->pw[lane];
+  const double ainv_grid = EV ? 0.0 : a.tab->ainv[lane];
+  Pre nxt{};
+  if (sb < se) nxt = fetch(sb);
+  for (int64_t s = sb; s < se; ++s) {
+    const Pre cur = nxt;
+    if (s + 1 < se) nxt = fetch(s + 1);
+    const int32_t e0 = cur.e0, e1 = cur.e1;
     if (e0 == e1) continue;
     // this lane's column: carry and masks of subtile s
-    const double C = a.C64[s * a.Np + j];
-    const double CY = WANT_Y ? a.CY64[s * a.Np + j] : 0.0;
-    const uint64_t m0 = a.masks[s * a.Np + j];
-    if constexpr (EV) {
-      __syncthreads();
-      sleft[lane] = a.ev.left[s * 64 + lane];
-      sainv[lane] = a.ev.ainv[s * 64 + lane];
-      __syncthreads();
+    const double C = cur.C;
+    const double CY = cur.CY;
+    const uint64_t m0 = cur.m0;
+    // lane b holds the decay to bin (slot) b of the subtile; a spike's bin is
+    // the same for the whole wave, so its factor is broadcast from that lane
+    const double pw_lane = EV ? cur.left : pw_grid;
+    const double ainv_lane = EV ? cur.ainv : ainv_grid;
+    // This lane's column: the first four spike bins of the subtile and their
+    // factors, so that the trace at a spike's bin b is C plus those below b,
+    // added in bin order, with no loop or memory access.  A column with more
+    // spikes in the subtile, or several spikes in one bin (more than one
+    // mask plane), takes the loop over its bits instead.
+    int bt[4];
+    double wt[4], ut[4];
+    uint64_t mm = m0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      bt[q] = mm ? __builtin_ctzll(mm) : 64;
+      mm &= mm - 1;
+      // every lane takes part in the exchange (a permute reads active lanes only)
+      const double w = __shfl(ainv_lane, bt[q] & 63, 64);
+      wt[q] = bt[q] < 64 ? w : 0.0;
+      ut[q] = (double)(bt[q] + 1) * wt[q];
     }
-    double run = C, P0 = 0.0, P1 = 0.0;
-    int bcur = 0;
+    bool slow = mm != 0;
+    for (int p = 1; p < a.planes; ++p) slow = slow || a.masks[((int64_t)p * a.NS + s) * a.Np + j] != 0;
+    // the term of one spike (entry v: bin b = v >> 6, row il = v & 63) by
+    // the four registered bins
+    auto fast = [&](int v, double* ty) {
+      const int b = v >> 6;
+      double run = C, P0 = 0.0, P1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool in = bt[q] < b;
+        run += in ? wt[q] : 0.0;
+        if (WANT_Y) {
+          P0 += in ? wt[q] : 0.0;
+          P1 += in ? ut[q] : 0.0;
+        }
+      }
+      const double pw = lane_bcast_d(pw_lane, b);
+      if (WANT_Y) *ty = pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
+      return pw * run;
+    };
+    const bool wave_fast = __ballot(slow) == 0;  // uniform over the wave
     for (int32_t eb = e0; eb < e1; eb += 64) {
       // one entry per lane, then walk them in order (bin order within the segment)
       const int cnt = (e1 - eb < 64) ? e1 - eb : 64;
       const int mine = lane < cnt ? (int)a.seg_ent[eb + lane] : 0;
-      for (int k = 0; k < cnt; ++k) {
+      int k = 0;
+      if (wave_fast) {
+        // four spikes at a time: their sums are independent, so their
+        // instruction chains interleave; the adds keep the spikes' order
+        for (; k + 4 <= cnt; k += 4) {
+          const int v0 = lane_bcast(mine, k), v1 = lane_bcast(mine, k + 1);
+          const int v2 = lane_bcast(mine, k + 2), v3 = lane_bcast(mine, k + 3);
+          double y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
+          const double x0 = fast(v0, &y0), x1 = fast(v1, &y1), x2 = fast(v2, &y2), x3 = fast(v3, &y3);
+          atomicAdd(&acc[v0 & 63][lane], x0);
+          if (WANT_Y) atomicAdd(&accy[v0 & 63][lane], y0);
+          atomicAdd(&acc[v1 & 63][lane], x1);
+          if (WANT_Y) atomicAdd(&accy[v1 & 63][lane], y1);
+          atomicAdd(&acc[v2 & 63][lane], x2);
+          if (WANT_Y) atomicAdd(&accy[v2 & 63][lane], y2);
+          atomicAdd(&acc[v3 & 63][lane], x3);
+          if (WANT_Y) atomicAdd(&accy[v3 & 63][lane], y3);
+        }
+      }
+      for (; k < cnt; ++k) {
         const int v = lane_bcast(mine, k);
         const int il = v & 63, b = v >> 6;
-        if (b > bcur) {
-          const uint64_t win = ((1ull << b) - 1) & ~((1ull << bcur) - 1);
-          uint64_t m = m0 & win;
-          while (m) {
-            const int bb = __builtin_ctzll(m);
-            m &= m - 1;
-            const double w = EV ? sainv[bb] : a.tab->ainv[bb];
-            run += w;
-            if (WANT_Y) { P0 += w; P1 += (double)(bb + 1) * w; }
+        double run = C, P0 = 0.0, P1 = 0.0;
+        if (!slow) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const bool in = bt[q] < b;
+            run += in ? wt[q] : 0.0;
+            if (WANT_Y) {
+              P0 += in ? wt[q] : 0.0;
+              P1 += in ? ut[q] : 0.0;
+            }
           }
-          for (int p = 1; p < a.planes; ++p) {
-            uint64_t mp = a.masks[((int64_t)p * a.NS + s) * a.Np + j] & win;
-            while (mp) {
-              const int bb = __builtin_ctzll(mp);
-              mp &= mp - 1;
-              const double w = EV ? sainv[bb] : a.tab->ainv[bb];
+        } else {
+          const uint64_t below = (1ull << b) - 1;
+          for (int p = 0; p < a.planes; ++p) {
+            uint64_t m = (p == 0 ? m0 : a.masks[((int64_t)p * a.NS + s) * a.Np + j]) & below;
+            while (m) {
+              const int bb = __builtin_ctzll(m);
+              m &= m - 1;
+              const double w = EV ? a.ev.ainv[s * 64 + bb] : a.tab->ainv[bb];
               run += w;
               if (WANT_Y) { P0 += w; P1 += (double)(bb + 1) * w; }
             }
           }
-          bcur = b;
         }
-        const double pw = EV ? sleft[b] : a.tab->pw[b];
-        acc[il][lane] += pw * run;
-        if (WANT_Y) accy[il][lane] += pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
+        const double pw = lane_bcast_d(pw_lane, b);
+        // LDS add without return: no wait on the sum before the next spike.
+        // One wave owns the block's sums and its lanes add to distinct
+        // addresses, so the order of the additions is the program order.
+        atomicAdd(&acc[il][lane], pw * run);
+        if (WANT_Y) atomicAdd(&accy[il][lane], pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1)));
       }
     }
   }
