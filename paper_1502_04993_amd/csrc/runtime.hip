@@ -1503,6 +1503,10 @@ namespace {
 glmr_status batch_prepare(glmr_batch* b) {
   bool grouped = true;
   for (glmr_ctx* c : b->ctxs) {
+    // the grouped launches take one precision for all (a context may have
+    // been switched since the batch was made)
+    if (c->prec != b->ctxs[0]->prec)
+      return fail(c, GLMR_ESTATE, "the batch's recordings no longer share one precision");
     TRY(check_ready(c));
     grouped = grouped && c->resident && !self_delayed(c) && !c->evm;
   }

@@ -176,3 +176,24 @@ def test_batch_with_default_shapes_equals_each_context():
     b.close()
     for c in ctxs:
         c.close()
+
+
+def test_batch_refuses_mixed_precisions():
+    # a context switched to another precision after the batch was made: the
+    # grouped launches take one precision for all, so the batch refuses
+    G = _G()
+    recs = _recs()[:2]
+    ctxs = [_ctx(r, "bf16") for r in recs]
+    for r, c in zip(recs, ctxs):
+        c.set_params(_bf16(r.J), r.mu)
+    b = G.Batch(ctxs)
+    b.eval()
+    ctxs[1].set_precision("fp8")
+    with pytest.raises(G.GlmrError) as e:
+        b.eval()
+    assert e.value.status == G.L.GLMR_ESTATE
+    ctxs[1].set_precision("bf16")
+    b.eval()
+    b.close()
+    for c in ctxs:
+        c.close()
