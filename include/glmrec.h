@@ -227,7 +227,8 @@ typedef struct {
   int32_t max_iter;       /* iteration cap (default 500) */
   double ftol;            /* per-row stop when |L_i^k - L_i^(k-1)| / |L_i^k| <= ftol
                              (Sec. 2.6.3); 0 = precision default */
-  int32_t lbfgs_m;        /* history length (default 10) */
+  int32_t lbfgs_m;        /* history length, 1..64 (default 40; the state takes 2 m N (N+1)
+                             doubles) */
   int32_t max_backtracks; /* Armijo halvings per iteration (default 30) */
   int32_t warm_start_mu;  /* 1: start mu_i at log(q_i / T) instead of the current mu */
   int32_t from_zero;      /* 1: start from J = 0, mu = 0 (overrides the current params) */
@@ -281,7 +282,7 @@ glmr_status glmr_fit(glmr_ctx* ctx, const glmr_fit_opts* opts, glmr_fit_report* 
  * whole state (per-row L-BFGS histories, iterates, gradients, step sizes,
  * row status, penalty and bounds), as one flat host buffer in this machine's
  * byte order with a fixed head.  buf NULL: *len receives the size in bytes
- * (about 8 (2m + 6) N^2 with history length m, m = 10 by default).
+ * (about 8 (2m + 6) N^2 with history length m, m = 40 by default).
  * Otherwise *len must hold the buffer's size; it receives the bytes
  * written (GLMR_EINVAL, with the size needed in *len, if too small).  The
  * buffer belongs to the caller.  GLMR_ESTATE before spikes and parameters. */

@@ -374,7 +374,7 @@ class Context:
         ll, gt = glmr_eval(self._c, ll_rows, gJ, gmu, want_tau)
         return dict(ll=ll, ll_rows=ll_rows, gJ=gJ, gmu=gmu, gtau=gt)
 
-    def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
+    def fit(self, max_iter=500, ftol=0.0, lbfgs_m=40, max_backtracks=30, warm_start_mu=False,
             from_zero=False, polish=None, polish_iter=200, l1_alpha=0.0, l1_eps=0.0, j_max=0.0,
             rate_min=0.0, rate_max=0.0, resume=False):
         """Per-row L-BFGS ascent.  polish="fp32" finishes a BF16 ascent with FP32
@@ -461,7 +461,7 @@ class Batch:
         glmr_batch_get_grad(self._b, r, gJ, gmu)
         return gJ, gmu
 
-    def fit(self, max_iter=500, ftol=0.0, lbfgs_m=10, max_backtracks=30, warm_start_mu=False,
+    def fit(self, max_iter=500, ftol=0.0, lbfgs_m=40, max_backtracks=30, warm_start_mu=False,
             from_zero=False, l1_alpha=0.0, l1_eps=0.0, j_max=0.0, rate_min=0.0, rate_max=0.0,
             resume=False):
         o = glmr_fit_defaults()

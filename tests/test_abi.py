@@ -32,7 +32,7 @@ def test_status_strings_and_defaults():
     assert G.glmr_status_string(0) == "ok"
     assert "invalid" in G.glmr_status_string(-1)
     o = G.glmr_fit_defaults()
-    assert o.max_iter == 500 and o.lbfgs_m == 10
+    assert o.max_iter == 500 and o.lbfgs_m == 40
 
 
 def test_create_rejects_bad_config_without_device():
