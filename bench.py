@@ -131,12 +131,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--workload", default="balanced_n1000",
-                    choices=["balanced_n1000", "batch64", "events", "reconstruct"],
+                    choices=["balanced_n1000", "batch64", "events", "reconstruct", "cv"],
                     help="batch64: 64 recordings of uneven N and T (balanced and synfire), "
                          "evaluated together (grouped launches); events: the balanced N = 1000 "
                          "recording in continuous time (event grid, Ei integrals); reconstruct: "
                          "time to reconstruct the N = 1000 network (BF16 fit from zero, FP32 polish) "
-                         "and the misclassification rate against the generated weights")
+                         "and the misclassification rate against the generated weights; cv: a "
+                         "cross-validation scan over tau on the N = 500, 600 s recording")
     ap.add_argument("--fit-max-iter", type=int, default=400, help="reconstruct: BF16 ascent cap")
     ap.add_argument("--polish-iter", type=int, default=60, help="reconstruct: FP32 polish cap")
     ap.add_argument("--cpu-sample-events", type=int, default=12000,
@@ -171,6 +172,9 @@ def main():
         return
     if args.workload == "reconstruct":
         bench_reconstruct(args, G, torch)
+        return
+    if args.workload == "cv":
+        bench_cv(args, G, torch)
         return
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -346,6 +350,39 @@ def bench_events(args, G, torch):
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_events(times, neu, N, rec.tau, rec.J, rec.mu,
                                                   min(args.cpu_sample_events, times.shape[0] - 1))
+    print(json.dumps(out))
+
+
+def bench_cv(args, G, torch):
+    """Cross-validation scan over the kernel time constant (Sec. 3.2, Fig. 4):
+    the N = 500 balanced recording of 600 s (true tau = 8 ms) split in halves,
+    one batched fit from J = 0 over the tau grid, each fit scored on the
+    held-out half.  Value: the wall time of the whole scan, context set-up
+    included (the spikes start on the host)."""
+    from paper_1502_04993_amd.cv import cv_scan
+    import synth
+    rec = synth.cached("config4", seed=0)
+    taus = [0.004, 0.006, 0.008, 0.012, 0.016]
+    prec = args.precision if args.precision in ("fp32", "bf16", "fp64") else "bf16"
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = cv_scan(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, taus, alphas=(0.0,), precision=prec)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    best = res.best()
+    tot = res.val[0]
+    iters = [res.reports[(0, k)]["iters"] for k in range(len(taus))]
+    out = {
+        "metric": "cross-validation scan over tau (5 points), N=500, 600 s",
+        "value": sec, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": sec * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[prec], "data": "synthetic",
+        "config": {"workload": "balanced_n500_indeg50_t600s_tau8ms_cv", "n_neurons": rec.n_neurons,
+                   "n_bins": rec.n_bins, "taus_s": taus, "alphas": [0.0], "train_frac": 0.5, "precision": prec},
+        "roofline": None,
+        "best_tau_s": best[1], "true_tau_s": rec.tau, "mean_row_peak_tau_s": res.mean_row_peak_tau(0),
+        "validation_ll": [float(v) for v in tot], "fit_iters": iters,
+    }
     print(json.dumps(out))
 
 
