@@ -144,6 +144,8 @@ def main():
                     help="events: network events of the oracle's bounded sample")
     ap.add_argument("--n-rec", type=int, default=64, help="batch64: number of recordings")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--delays", default="",
+                    help="d,d_self: transmission delays in bins (Eq. (15)) on the default workload")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 comparison line")
     ap.add_argument("--cpu-sample-bins", type=int, default=1_572_864)
     ap.add_argument("--fit-iters", type=int, default=400,
@@ -188,9 +190,13 @@ def main():
     N, B = rec.n_neurons, rec.n_bins
     units = float(B) * N * N
 
+    delays = tuple(int(v) for v in args.delays.split(",")) if args.delays else (0, 0)
+
     def run(prec):
         ctx = G.Context(N, B, rec.dt, precision=prec, trace=args.trace if prec == "bf16" else "auto")
         t0 = time.perf_counter()
+        if delays != (0, 0):
+            ctx.set_delays(*delays)
         ctx.set_spikes(rec.bins, rec.neurons)
         ctx.set_kernel(rec.tau)
         torch.cuda.synchronize()
@@ -233,7 +239,7 @@ def main():
     ctx.close()
 
     extra = {}
-    if not args.no_fp8 and args.precision == "bf16":
+    if not args.no_fp8 and args.precision == "bf16" and delays[0] == delays[1]:  # FP8 needs d_self = d
         c8, setup8, sec8, r8, kt8, tiles8 = run("fp8")
         c8.close()
         extra.update({"fp8_value": units / sec8, "fp8_ms_per_step": sec8 * 1e3,
@@ -261,7 +267,7 @@ def main():
                    "n_bins": B, "n_spikes": rec.n_spikes, "precision": args.precision,
                    "chunk_bins": q["chunk_bins"], "n_pad": q["n_pad"],
                    "trace": "resident" if q["trace_resident"] else "recompute",
-                   "tile_shapes": list(tiles)},
+                   "tile_shapes": list(tiles), "delays_bins": list(delays)},
         "roofline": roofline,
         "setup_ms": setup * 1e3,
         "ll": r["ll"],

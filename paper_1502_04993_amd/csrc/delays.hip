@@ -17,6 +17,8 @@
 //    which turns kernel G's G_ii = sum_t lambda_i x_i[t - d] into the
 //    integral against x_i[t - d_s].  k_self_spike adds
 //    sum_{spikes of i at t} Delta_i[t] to dSigma_ii once per tau.
+#include <type_traits>
+
 #include "common.h"
 
 namespace {
@@ -38,6 +40,16 @@ __device__ inline double trace_at(const DelayTrace& x, int64_t j, int64_t t) {
     }
   }
   return x.tab->pw[m] * z;
+}
+
+// spikes of neuron j in bin t of the recorded raster (t < 0: none)
+__device__ inline double spikes_at(const DelayTrace& x, int64_t j, int64_t t) {
+  if (t < 0) return 0.0;
+  const int64_t s = t >> 6;
+  const int b = (int)(t & 63);
+  int n = 0;
+  for (int p = 0; p < x.planes; ++p) n += (int)((x.masks[((int64_t)p * x.NS + s) * x.Np + j] >> b) & 1ull);
+  return (double)n;
 }
 
 // dst bit (t) = src bit (t - d): word s of dst takes words s - q and s - q - 1
@@ -78,17 +90,32 @@ __global__ __launch_bounds__(256) void k_self_delay(SelfDelayArgs a) {
   const int64_t tt0 = a.t0 + tl0;
   const double jd = a.Jr[i * a.x.Np + i];
   const int per = a.tb >> 6;
+  const double dec = a.x.tab->pw[1];  // a = e^{-dt/tau}
   double s_lam = 0.0, s_gd = 0.0;
+  // the lane's bins are consecutive: the two traces at its first bin, then
+  // one step of the recursion x[u + 1] = a x[u] + s[u] per bin
+  const int64_t tf = tt0 + lane * per;
+  double xs = trace_at(a.x, i, tf - a.ds), xd = trace_at(a.x, i, tf - a.d);
   for (int e = 0; e < per; ++e) {
     const int tl = lane * per + e;
     const int64_t t = tt0 + tl;
+    const double delta = xs - xd;
+    xs = dec * xs + spikes_at(a.x, i, t - a.ds);
+    xd = dec * xd + spikes_at(a.x, i, t - a.d);
     if (t >= a.B) continue;
-    const double delta = trace_at(a.x, i, t - a.ds) - trace_at(a.x, i, t - a.d);
-    const double c = exp(jd * delta);
+    // the factor in FP64, except for BF16 weights, whose rounding (2^-9) is far
+    // above the FP32 exponential's error (the FP32 mode holds L to 1e-10)
+    const double c = std::is_same<WT, __bf16>::value ? (double)expf((float)(jd * delta)) : exp(jd * delta);
     const int64_t k = i * a.L + tl0 + tl;
-    const double pw = a.scaled ? a.x.tab->pw[tl & 63] : 1.0;
-    const double lam = w_load<WT>(a.W, k) / pw * c;
-    w_store<WT>(a.W, k, lam * pw);
+    double lam;
+    if (a.scaled) {  // the rebuild kernels store W a^m
+      const double pw = a.x.tab->pw[tl & 63];
+      lam = w_load<WT>(a.W, k) / pw * c;
+      w_store<WT>(a.W, k, lam * pw);
+    } else {
+      lam = w_load<WT>(a.W, k) * c;
+      w_store<WT>(a.W, k, lam);
+    }
     s_lam += lam;
     s_gd += lam * delta;
   }

@@ -44,10 +44,10 @@ struct ProfRec {
 const char* const kKindNames[] = {"ingest",       "carries",     "spike_term", "kernel_U",
                                   "kernel_V",     "kernel_G",    "reduce_G",   "assemble",
                                   "prepare",      "ascent",      "batch_U",    "batch_G",
-                                  "trace_build"};
+                                  "trace_build",  "self_delay"};
 enum {
   K_INGEST, K_CARRY, K_SPIKE, K_U, K_V, K_G, K_RED, K_ASM, K_PREP, K_ASC, K_BU, K_BG, K_XBUILD,
-  K_NKIND
+  K_SELF, K_NKIND
 };
 
 }  // namespace
@@ -705,7 +705,7 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       sd.ds = c->dly_s;
       sd.rowpart = c->rowpart;
       sd.gpart = c->gpart;
-      ProfScope ps(c, K_U);
+      ProfScope ps(c, K_SELF);
       HIPCHK(c, launch_self_delay(sd, c->st));
     }
     if (want_tau) {
