@@ -152,3 +152,37 @@ def test_checkpoint_rejections():
     b.close()
     for x in (c, o, s2):
         x.close()
+
+
+def test_event_grid_fit_resumes_bit_for_bit():
+    # the continuous-time model: the checkpoint keeps the time mode and the
+    # event grid's slots; a context of the same events resumes the ascent
+    G = _G()
+    rec = synth.balanced(N=30, B=20_000, in_frac=0.3, seed=175)
+    times, neu = synth.event_times(rec, seed=3)
+
+    def ctx():
+        c = G.Context.from_events(30, times, neu, 0.0, rec.T, precision="fp64")
+        c.set_kernel(rec.tau)
+        return c
+    full = ctx()
+    rf = full.fit(max_iter=16, from_zero=True)
+    Jf = full.get_params()[0]
+    full.close()
+    part = ctx()
+    part.fit(max_iter=6, from_zero=True)
+    st = part.get_state()
+    part.close()
+    fresh = ctx()
+    fresh.set_state(st)
+    r = fresh.fit(max_iter=10, resume=True)
+    Jr = fresh.get_params()[0]
+    fresh.close()
+    assert r["iters"] == 10 and np.array_equal(Jr, Jf) and r["ll"] == rf["ll"]
+    # a regular-grid context of the same size refuses the checkpoint
+    grid = G.Context(30, 20_000, rec.dt, precision="fp64")
+    grid.set_spikes(rec.bins, rec.neurons)
+    with pytest.raises(G.GlmrError) as e:
+        grid.set_state(st)
+    assert e.value.status == G.L.GLMR_EINVAL
+    grid.close()
