@@ -53,6 +53,7 @@ struct EvSlots {
   const double* ainv;      // [NS*64] e^{(t_{k+1} - t_k0)/tau}
   const double* left;      // [NS*64] e^{-(t_{k+1} - t_k0)/tau}
   const double* delta;     // [NS*64] (t_{k+1} - t_k)/tau
+  const double* edec;      // [NS*64] e^{-(t_{k+1} - t_k)/tau}  (decay over slot k)
   const double* asub;      // [NS]    e^{-(t_{k0+64} - t_k0)/tau}
 };
 
@@ -106,7 +107,7 @@ struct EvTableArgs {
   const double* tslot;
   double tau;
   int64_t NS;
-  double *pw, *ainv, *left, *delta, *asub;
+  double *pw, *ainv, *left, *delta, *edec, *asub;
   float* gl;                    // [NS*64][16]: the FP32 evaluation's per-slot table (null: none)
   unsigned long long* maxspan;  // max over subtiles of the span / tau (double bits), zero on entry
 };

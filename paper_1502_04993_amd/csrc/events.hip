@@ -19,6 +19,7 @@
 //   ainv[k] = e^{(t_{k+1} - t_k0)/tau}     (the spike recorded at k, as seen from k0)
 //   left[k] = e^{-(t_{k+1} - t_k0)/tau}    (left limit at the event of slot k + 1)
 //   delta[k] = (t_{k+1} - t_k)/tau         (the interval of slot k)
+//   edec[k] = e^{-delta[k]}                 (the decay over slot k)
 //   asub[s] = e^{-(t_{k0+64} - t_k0)/tau}  (decay over a subtile)
 // Slots past the last one have zero length (t = T1) and contribute nothing.
 #include <cmath>
@@ -166,6 +167,7 @@ __global__ void k_ev_tables(EvTableArgs a) {
     a.ainv[k] = exp((tk1 - tb) * r);
     a.left[k] = exp(-(tk1 - tb) * r);
     a.delta[k] = (tk1 - tk) * r;
+    a.edec[k] = exp(-(tk1 - tk) * r);
     if (a.gl) {
       float o[16];
       glmr_ev::table_f((tk1 - tk) * r, o);

@@ -100,8 +100,8 @@ __global__ __launch_bounds__(256) void k_build_x(ResXArgs g) {
 #pragma unroll
   for (int e = 0; e < 16; e += 2) {
     const int64_t t = s * 64 + m0 + e;
-    const double a0 = ev ? exp(-g.ev.delta[t]) : a;      // decay over bin (slot) t
-    const double a1 = ev ? exp(-g.ev.delta[t + 1]) : a;
+    const double a0 = ev ? g.ev.edec[t] : a;  // decay over bin (slot) t
+    const double a1 = ev ? g.ev.edec[t + 1] : a;
     const float x0 = (float)x;
     x = a0 * x + (double)cnt[e];
     const float x1 = (float)x;

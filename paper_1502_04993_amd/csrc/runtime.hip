@@ -81,7 +81,7 @@ struct glmr_ctx {
   bool evm = false;
   double T0 = 0, T1 = 0, max_gap = 0;
   double* tslot = nullptr;  // [NS*64 + 1]
-  double* evtab = nullptr;  // [4 * NS*64 + NS]: pw, ainv, left, delta, asub
+  double* evtab = nullptr;  // [5 * NS*64 + NS]: pw, ainv, left, delta, edec, asub
   float* evgl = nullptr;    // BF16: [NS*64][16] per-slot table of kernel U's interval integrals
   double max_span = 0;      // largest 64-slot span / tau of the current tables
 
@@ -306,7 +306,8 @@ EvSlots ev_slots(const glmr_ctx* c) {
   e.ainv = c->evtab + n;
   e.left = c->evtab + 2 * n;
   e.delta = c->evtab + 3 * n;
-  e.asub = c->evtab + 4 * n;
+  e.edec = c->evtab + 4 * n;
+  e.asub = c->evtab + 5 * n;
   return e;
 }
 
@@ -315,7 +316,7 @@ EvSlots ev_slots(const glmr_ctx* c) {
 constexpr double kMaxSpan = 600.0;
 glmr_status build_ev_tables(glmr_ctx* c) {
   const int64_t n = c->NS * 64;
-  if (!c->evtab) TRY(dalloc(c, c->evtab, (size_t)(4 * n + c->NS)));
+  if (!c->evtab) TRY(dalloc(c, c->evtab, (size_t)(5 * n + c->NS)));
   unsigned long long* ms = nullptr;
   TRY(dalloc(c, ms, 1));
   HIPCHK(c, hipMemsetAsync(ms, 0, sizeof(unsigned long long), c->st));
@@ -327,7 +328,8 @@ glmr_status build_ev_tables(glmr_ctx* c) {
   ta.ainv = c->evtab + n;
   ta.left = c->evtab + 2 * n;
   ta.delta = c->evtab + 3 * n;
-  ta.asub = c->evtab + 4 * n;
+  ta.edec = c->evtab + 4 * n;
+  ta.asub = c->evtab + 5 * n;
   if (c->prec == PREC_BF16) {
     if (!c->evgl) TRY(dalloc(c, c->evgl, (size_t)(16 * n)));
     ta.gl = c->evgl;
