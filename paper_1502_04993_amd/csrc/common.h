@@ -164,6 +164,7 @@ struct SelfDelayArgs {
   void* W;                   // [Np][L] weights of the chunk (kernel U's output)
   int wtype;                 // 0 double, 1 float, 2 bf16
   int scaled;                // 1: W holds lambda a^m (rebuilt-trace kernels), 0: lambda
+  int tiled;                 // 1: W is tile-major [L / 256][Np][256] (resident trace), 0: [Np][L]
   const double* Jr;          // [Np][Np] J as the contraction used it
   int64_t B, t0, L, Lc;      // bins, chunk start, W pitch, bins of the chunk
   int tb;                    // bins per row-sum tile of kernel U (128 or 256)
@@ -204,7 +205,8 @@ struct Gemm1Args {
   const float* xscale;     // FP8: per-chunk X scale (power of two); J row scale
   const float* jscale;
   int mode;                // 0: U -> W, 1: V = Y J^T -> sum W V
-  int w_plain;             // mode 1: W holds exp(V) (resident trace) instead of exp(V) a^m
+  int w_plain;             // mode 1: W holds exp(V) (resident trace, tile-major [L / 256][Np][256])
+                           // instead of exp(V) a^m ([Np][L])
   EvSlots ev;              // event grid (mode 0 only): W = H(D, delta) pw, row sums of F(D, delta)
   const float* evgl;       // event grid, BF16: [slots][16] per-slot table of the FP32 integrals
 };

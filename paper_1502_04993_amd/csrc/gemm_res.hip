@@ -258,13 +258,16 @@ struct Nt {
 
 // acc[a][b] += A[m0 + wave rows][kb:ke] B[n0 + wave cols][kb:ke]^T in format Op.
 // A and B point at the tile's first row; lda/ldb and the k range [kb, ke) are
-// in bytes, the range a multiple of 128.  Acc element r of lane l of block
+// in bytes, the range a multiple of 128.  atile > 0: A is stored tile-major,
+// rows of lda bytes grouped in k blocks of lda bytes that lie atile bytes
+// apart (byte k of row r at A + (k / lda) atile + r lda + k % lda).  Acc element r of lane l of block
 // (a, b) is row 32a + 8(r/4) + 4(l/32) + r%4, column 32b + l%32 of the wave tile.
 template <int BM, int BN, int WGM, int WGN, typename Op>
 __device__ __forceinline__ void nt_loop(const unsigned char* __restrict__ A, int64_t lda,
                                         const unsigned char* __restrict__ Bt, int64_t ldb, int64_t kb,
                                         int64_t ke, unsigned char* smem,
-                                        f32x16 (&acc)[Nt<BM, BN, WGM, WGN>::MB][Nt<BM, BN, WGM, WGN>::NB]) {
+                                        f32x16 (&acc)[Nt<BM, BN, WGM, WGN>::MB][Nt<BM, BN, WGM, WGN>::NB],
+                                        int64_t atile = 0) {
   using T = Nt<BM, BN, WGM, WGN>;
   constexpr int SB = BK * 2;  // bytes per row and step
   const int tid = threadIdx.x, lane = tid & 63;
@@ -279,7 +282,8 @@ __device__ __forceinline__ void nt_loop(const unsigned char* __restrict__ A, int
 #pragma unroll
     for (int q = 0; q < T::APT; ++q) {
       const int piece = tid + q * T::NT, r = piece >> 3, c = piece & 7;
-      ar[q] = *(const i32x4*)(A + r * lda + k0 + c * 16);
+      const int64_t ka = atile ? (k0 / lda) * atile + k0 % lda : k0;
+      ar[q] = *(const i32x4*)(A + r * lda + ka + c * 16);
     }
 #pragma unroll
     for (int q = 0; q < T::BPT; ++q) {
@@ -485,12 +489,16 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
     if (hi == 0) red[wm * BI + il] = v;
   }
   __syncthreads();
-  unsigned char* __restrict__ W = (unsigned char*)g.W;
+  // W is tile-major over the chunk: [L / 256][Np][256] (a 256-bin tile of all
+  // rows is one block), so this tile's rows leave as one contiguous run and
+  // kernel G reads 512 rows of a k step from one block
+  static_assert(BT == 256, "W's tiles are 256 bins");
+  unsigned char* __restrict__ W = (unsigned char*)g.W + ((tl0 >> 8) * g.Np + i0) * (BT * ES);
   constexpr int CPRW = BT * ES / 16;  // 16-byte pieces per staged row
 #pragma unroll 4
   for (int p = tid; p < BI * CPRW; p += T::NT) {
     const int r = p / CPRW, c = p % CPRW;
-    *(i32x4*)(W + ((i0 + r) * g.L + tl0) * ES + c * 16) = *(const i32x4*)(wl + r * WP + c * 16);
+    *(i32x4*)(W + r * (BT * ES) + c * 16) = *(const i32x4*)(wl + r * WP + c * 16);
   }
   for (int il = tid; il < BI; il += T::NT) {
     double v = 0.0;
@@ -558,9 +566,10 @@ __device__ __forceinline__ void res_g_tile(const ResGArgs& g, int64_t logical, u
 
   f32x16 acc[T::MB][T::NB];
   zero_acc(acc);
-  nt_loop<BM, BN, WGM, WGN, Op>((const unsigned char*)g.W + i0 * g.L * ES, g.L * ES,
+  // A = W, tile-major (rows of 256 bins, tile blocks Np rows apart)
+  nt_loop<BM, BN, WGM, WGN, Op>((const unsigned char*)g.W + i0 * GLMR_TT * ES, GLMR_TT * ES,
                                 (const unsigned char*)g.Xjt + (j0 * g.Bp + g.t0) * ES, g.Bp * ES, tb * ES,
-                                te * ES, smem, acc);
+                                te * ES, smem, acc, g.Np * GLMR_TT * ES);
 
   // FP8: the weights were stored as exp(V) / 64 and the trace times its chunk scale
   const float gs = F8 ? 64.f / g.xscale[0] : 1.f;

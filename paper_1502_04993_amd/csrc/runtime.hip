@@ -697,6 +697,7 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       sd.W = c->W;
       sd.wtype = c->prec == PREC_F64 ? 0 : (c->prec == PREC_F32 ? 1 : 2);
       sd.scaled = c->resident ? 0 : 1;
+      sd.tiled = c->resident ? 1 : 0;
       sd.Jr = c->Jr;
       sd.B = c->B;
       sd.t0 = t0;
