@@ -289,8 +289,10 @@ glmr_status glmr_fit(glmr_ctx* ctx, const glmr_fit_opts* opts, glmr_fit_report* 
 glmr_status glmr_get_state(glmr_ctx* ctx, void* buf, size_t* len);
 
 /* Restore a checkpoint into a context of the same recording: same N,
- * n_bins, dt and time mode, and the same spikes (their count and the
- * per-neuron counts are checked; set them first, GLMR_ESTATE otherwise).
+ * n_bins, dt and time mode, and the same spikes (their count, the
+ * per-neuron counts and a 64-bit digest of the ingested raster, which on the
+ * event grid covers the slot times too, are checked; set them first,
+ * GLMR_ESTATE otherwise).
  * Applies the precision, delays and tau of the checkpoint, its parameters,
  * and its ascent (glmr_fit with opts.resume = 1 then continues it).  In a
  * context created with the same configuration the resumed fit ends bit for

@@ -512,6 +512,140 @@ def newton_rows(bins, neurons, N: int, B: int, dt: float, tau: float, rows: Sequ
     return out
 
 
+def _trace_chunks_loop(S, a: float, chunk: int):
+    """The trace chunk by chunk by the recursion itself (trace_rows), carried
+    across chunk boundaries; (b0, X_chunk)."""
+    N = S.shape[1]
+    B = S.shape[0]
+    x0 = np.zeros(N)
+    for b0 in range(0, B, chunk):
+        b1 = min(B, b0 + chunk)
+        Sc = S[b0:b1].toarray().astype(np.float64)
+        X = trace_rows(Sc, a, x0)
+        x0 = a * X[-1] + Sc[-1]
+        yield b0, X
+
+
+def newton_rows_sub(bins, neurons, N: int, B: int, dt: float, tau: float, rows: Sequence[int],
+                    hess_stride: int = 8, refresh: int = 4, max_iter: int = 200,
+                    step_tol: float = 1e-10, chunk: int = DEFAULT_CHUNK, log=None):
+    """Maximiser of L_i for many rows of a long recording, with the Newton
+    matrix taken on a subsample of the time axis.
+
+    The target is the same as newton_rows': the unique point where the exact
+    gradient of the concave row problem vanishes (Sec. 2.2 separability,
+    App. A concavity).  L_i and its gradient (Eq. (7), (12)) are summed over
+    every bin at every iterate.  Only the matrix that scales the step differs:
+    the Hessian of Eq. (18) accumulated over every hess_stride-th time chunk
+    and scaled by B / (bins in those chunks), recomputed at the first
+    `refresh` iterates and then kept.  A fixed point of
+    theta <- theta - H_sub^-1 g is a zero of the exact g whatever H_sub is (as
+    long as it is negative definite), so the approximation slows the last
+    iterations from quadratic to linear convergence and leaves the result
+    unchanged.  Steps are backtracked (t = 1, 1/2, ...) to the Armijo
+    condition on the exact L_i, except once the decrement g^T (-H_sub)^-1 g
+    is below 1e-12 |L_i|: there L_i is quadratic in the error and its change
+    is below its own rounding, and the full step (a contraction of the error
+    in the local quadratic model) is taken on the gradient's evidence alone.
+    Linear convergence makes a small change of L_i (Sec. 2.6.3's test) a weak
+    sign of a small error, so a row stops when its accepted step moves no
+    entry by more than step_tol.  All rows are evaluated in one pass per
+    iterate (X Theta^T and X^T R as matrix products over the rows).
+    Returns dict(row -> dict(mu, J, ll, iters, decrement, max_abs_grad, se));
+    se = sqrt(diag(-H_sub^-1)) at the last refresh, an estimate of the
+    standard errors (a scale for distances, not a reference value)."""
+    rows = [int(i) for i in rows]
+    R_n = len(rows)
+    S = spike_matrix(bins, neurons, N, B)
+    a = decay(dt, tau)
+    q = spike_counts(neurons, N)
+    Sr = S.tocsc()[:, rows].toarray().astype(np.float64)  # [B, R] spike counts of the rows
+    chunk_starts = list(range(0, B, chunk))
+    sampled = [k for k in range(len(chunk_starts)) if k % hess_stride == 0]
+    n_sampled = sum(min(B, chunk_starts[k] + chunk) - chunk_starts[k] for k in sampled)
+    scale = B / n_sampled
+
+    def rows_pass(Th, hess_rows):
+        """L [R], gradient [R, N+1] and the subsampled Hessians [R, N+1, N+1]
+        of the rows in hess_rows at the parameters Th [R, N+1]."""
+        want_H = bool(hess_rows)
+        parts = [[] for _ in range(R_n)]
+        g = np.zeros((R_n, N + 1))
+        H = np.zeros((R_n, N + 1, N + 1)) if want_H else None
+        for k, (b0, X) in enumerate(_trace_chunks_loop(S, a, chunk)):
+            b1 = b0 + X.shape[0]
+            s = Sr[b0:b1]
+            U = X @ Th[:, 1:].T + Th[None, :, 0]  # [K, R]
+            lam = np.exp(U)
+            for r in range(R_n):
+                parts[r].append(math.fsum(s[:, r] * U[:, r]) - dt * math.fsum(lam[:, r]))
+            Rres = s - dt * lam
+            g[:, 0] += Rres.sum(axis=0)
+            g[:, 1:] += (X.T @ Rres).T
+            if want_H and k in sampled:
+                for r in hess_rows:
+                    w = dt * lam[:, r]
+                    Xw = X.T @ w
+                    H[r, 0, 0] -= w.sum()
+                    H[r, 0, 1:] -= Xw
+                    H[r, 1:, 0] -= Xw
+                    Xs = X * np.sqrt(w)[:, None]
+                    H[r, 1:, 1:] -= Xs.T @ Xs  # sum_t w_t x_t x_t^T
+        if want_H:
+            H *= scale
+        return np.array([math.fsum(p) for p in parts]), g, H
+
+    Th = np.zeros((R_n, N + 1))
+    Th[:, 0] = [math.log(q[i] / (B * dt)) for i in rows]
+    L, g, H = rows_pass(Th, list(range(R_n)))
+    active = list(range(R_n))
+    out = {}
+    for k in range(1, max_iter + 1):
+        if not active:
+            break
+        step = {r: np.linalg.solve(H[r], -g[r]) for r in active}
+        dec = {r: float(g[r] @ step[r]) for r in active}
+        t = {r: 1.0 for r in active}
+        L_old = L.copy()
+        pending = list(active)
+        want_H = k < refresh
+        while pending:
+            Tt = Th.copy()
+            for r in pending:
+                Tt[r] = Th[r] + t[r] * step[r]
+            Lt, gt, Ht = rows_pass(Tt, pending if want_H else [])
+            still = []
+            for r in pending:
+                floor = dec[r] <= 1e-12 * max(abs(L[r]), 1.0)
+                if np.isfinite(Lt[r]) and (floor or Lt[r] >= L[r] + 1e-4 * t[r] * dec[r]):
+                    Th[r], L[r], g[r] = Tt[r], Lt[r], gt[r]
+                    if want_H:
+                        H[r] = Ht[r]
+                else:
+                    t[r] *= 0.5
+                    if t[r] >= 1e-12:
+                        still.append(r)
+                    else:
+                        t[r] = 0.0
+            pending = still
+        for r in list(active):
+            eta = abs(L[r] - L_old[r]) / max(abs(L[r]), 1e-300)
+            moved = t[r] * float(np.abs(step[r]).max())
+            if log is not None:
+                log(f"row {rows[r]} iter {k}: L {L[r]!r} eta {eta:.3e} decrement {dec[r]:.3e} "
+                    f"step {t[r]} moved {moved:.3e}")
+            if moved <= step_tol:
+                out[rows[r]] = dict(mu=float(Th[r, 0]), J=Th[r, 1:].copy(), ll=float(L[r]), iters=k,
+                                    decrement=dec[r], max_abs_grad=float(np.abs(g[r]).max()),
+                                    se=np.sqrt(np.diag(np.linalg.inv(-H[r]))))
+                active.remove(r)
+    for r in active:  # iteration cap
+        out[rows[r]] = dict(mu=float(Th[r, 0]), J=Th[r, 1:].copy(), ll=float(L[r]), iters=max_iter,
+                            decrement=float("nan"), max_abs_grad=float(np.abs(g[r]).max()),
+                            se=np.sqrt(np.diag(np.linalg.inv(-H[r]))))
+    return out
+
+
 def lbfgs_fit(bins, neurons, N: int, B: int, dt: float, tau: float,
               J0: Optional[np.ndarray] = None, mu0: Optional[np.ndarray] = None,
               ftol: float = 1e-15, gtol: float = 1e-10, maxiter: int = 5000,
@@ -749,6 +883,108 @@ def continuous_eval(spike_times: Sequence[np.ndarray], T0: float, T1: float, tau
             G += np.outer(c * tau * H, v)
             v = v * xi
     return dict(ll_rows=spike - integ, ll=float(math.fsum(spike - integ)), gJ=dsig - G, gmu=q - integ)
+
+
+def _ei_diff_vec(D: np.ndarray, xi: np.ndarray) -> np.ndarray:
+    """_ei_diff elementwise over arrays D and xi (0 < xi <= 1): the same
+    three branches (D = 0; the series for |D| < 1e-2; the library Ei)."""
+    D = np.asarray(D, dtype=np.float64)
+    xi = np.broadcast_to(np.asarray(xi, dtype=np.float64), D.shape)
+    out = np.empty_like(D)
+    zero = D == 0.0
+    out[zero] = -np.log(xi[zero])
+    small = (np.abs(D) < 1e-2) & ~zero
+    Ds, xs = D[small], xi[small]
+    acc = -np.log(xs)
+    term = np.ones_like(Ds)
+    for n in range(1, 30):
+        term = term * Ds / n  # D^n / n!
+        acc = acc + term * (1.0 - xs ** n) / n
+    out[small] = acc
+    big = ~(zero | small)
+    out[big] = scipy.special.expi(D[big]) - scipy.special.expi(D[big] * xi[big])
+    return out
+
+
+def continuous_eval_rows(times: np.ndarray, neurons: np.ndarray, N: int, T0: float, T1: float,
+                         tau: float, J: np.ndarray, mu: np.ndarray, rows: Sequence[int],
+                         chunk: int = DEFAULT_CHUNK) -> Dict[str, np.ndarray]:
+    """continuous_eval for the postsynaptic rows `rows` only, over event lists
+    too long for its per-event loop over all rows (Eq. (7)-(8), (10), (12),
+    (14); L is separable over rows, Sec. 2.2).
+
+    times, neurons: the network's events sorted by (time, neuron).  The same
+    steps as continuous_eval, in the same order: the interval after event m
+    (m = 0 is T0) starts with the trace v_m, which follows the recursion
+    v_m = xi_{m-1} v_{m-1} + e_{j_m} (Eq. (8): decay over the interval before,
+    then the jump of the event's neuron); at event m of a row's own neuron the
+    spike term takes the left limit mu_i + J_i . (xi_{m-1} v_{m-1}); over the
+    interval, D = J_i . v_m gives tau e^{mu_i} [Ei(D) - Ei(D xi)] (Eq. (10))
+    and tau e^{mu_i} v_m (e^D - e^{D xi}) / D (Eq. (14)).  The trace vectors
+    of a chunk of `chunk` intervals are formed by that recursion, one row per
+    interval; the products with the rows' weights are matrix products.
+    Returns dict(ll_rows, gJ [R, N], gmu, q) for the rows in the given order."""
+    times = np.asarray(times, dtype=np.float64)
+    neurons = np.asarray(neurons, dtype=np.int64)
+    rows = np.asarray(rows, dtype=np.int64)
+    R_n = rows.shape[0]
+    pos = np.full(N, -1, dtype=np.int64)
+    pos[rows] = np.arange(R_n)
+    JR = np.asarray(J, dtype=np.float64)[rows]  # [R, N]
+    muR = np.asarray(mu, dtype=np.float64)[rows]
+    c = np.exp(muR)
+    q_ev = times.shape[0]
+    bounds = np.concatenate([[T0], times, [T1]])  # interval m is [bounds[m], bounds[m + 1])
+    n_int = q_ev + 1
+    spike_parts: List[np.ndarray] = []
+    integ_parts: List[np.ndarray] = []
+    G = np.zeros((R_n, N))
+    dsig = np.zeros((R_n, N))
+    q = np.zeros(R_n)
+    v_prev = np.zeros(N)  # v_{m0 - 1} of the chunk's first interval m0
+    xi_prev = 1.0         # and the decay over its interval
+    for m0 in range(0, n_int, chunk):
+        m1 = min(n_int, m0 + chunk)
+        K = m1 - m0
+        delta = (bounds[m0 + 1:m1 + 1] - bounds[m0:m1]) / tau
+        xi = np.exp(-delta)
+        V = np.empty((K, N))
+        Vleft = np.empty((K, N))  # trace just before the chunk's events (left limits)
+        for k in range(K):
+            m = m0 + k
+            if m == 0:
+                Vleft[k] = 0.0
+                V[k] = 0.0
+                continue
+            np.multiply(v_prev if k == 0 else V[k - 1], xi_prev if k == 0 else xi[k - 1], out=Vleft[k])
+            V[k] = Vleft[k]
+            V[k, neurons[m - 1]] += 1.0
+        v_prev, xi_prev = V[-1].copy(), float(xi[-1])
+        # spike terms of the rows' own events in this chunk
+        ev = np.arange(max(m0, 1), m1)  # intervals that start at an event
+        ev_neu = neurons[ev - 1]
+        mine = pos[ev_neu] >= 0
+        ev, ev_neu = ev[mine], ev_neu[mine]
+        if ev.shape[0]:
+            r_of = pos[ev_neu]
+            Vl = Vleft[ev - m0]
+            U_left = muR[r_of] + np.einsum("kn,kn->k", Vl, JR[r_of])
+            spike_parts.append(np.bincount(r_of, weights=U_left, minlength=R_n))
+            np.add.at(dsig, r_of, Vl)
+            q += np.bincount(r_of, minlength=R_n)
+        # integrals over the chunk's intervals of positive length
+        live = delta > 0
+        D = V[live] @ JR.T  # [K', R]
+        xl = xi[live][:, None]
+        integ_parts.append(tau * c * _ei_diff_vec(D, np.broadcast_to(xl, D.shape)).sum(axis=0))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            H = np.where(np.abs(D) < 1e-8, (1.0 - xl) + D * (1.0 - xl * xl) / 2.0,
+                         (np.exp(D) - np.exp(D * xl)) / np.where(D == 0.0, 1.0, D))
+        G += (tau * c[None, :] * H).T @ V[live]
+    spike = np.array([math.fsum(p[r] for p in spike_parts) for r in range(R_n)])
+    integ = np.array([math.fsum(p[r] for p in integ_parts) for r in range(R_n)])
+    ll_rows = spike - integ
+    return dict(ll_rows=ll_rows, ll=float(math.fsum(ll_rows)), gJ=dsig - G, gmu=q - integ, q=q)
 
 
 def grid_ll_from_times(spike_times: Sequence[np.ndarray], T: float, dt: float, tau: float,

@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import Context, glmr_eval
+from . import Context, glmr_eval, glmr_get_params
 
 
 def _as_param(t: torch.Tensor) -> torch.Tensor:
@@ -21,10 +21,13 @@ def _as_param(t: torch.Tensor) -> torch.Tensor:
 
 
 def _sync(ctx: Context, J: torch.Tensor, mu: torch.Tensor, tau: torch.Tensor):
+    """Bring the context to (J, mu, tau).  The library's own tau is compared,
+    so a kernel set elsewhere (Context.set_kernel, set_state, the
+    cross-validation scans) is never mistaken for the requested one; the
+    per-tau caches are rebuilt only when the two differ."""
     tv = float(tau.detach().cpu())
-    if getattr(ctx, "_tau_cached", None) != tv:
+    if glmr_get_params(ctx.handle) != tv:
         ctx.set_kernel(tv)
-        ctx._tau_cached = tv
     ctx.set_params(_as_param(J), _as_param(mu))
 
 
@@ -76,7 +79,6 @@ def profile_tau(ctx: Context, tau0: float, steps: int = 8, fit_kwargs=None, tau_
 
     def at(tau):
         ctx.set_kernel(tau)
-        ctx._tau_cached = tau
         ctx.fit(**fit_kwargs)
         ll, gt = glmr_eval(ctx.handle, want_tau=True)
         hist.append((tau, ll, gt))
@@ -99,5 +101,4 @@ def profile_tau(ctx: Context, tau0: float, steps: int = 8, fit_kwargs=None, tau_
         u0, d0, u1 = u1, d1, u2
     best = max(hist, key=lambda h: h[1])
     ctx.set_kernel(best[0])
-    ctx._tau_cached = best[0]
     return best[0], hist

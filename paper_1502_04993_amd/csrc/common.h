@@ -80,6 +80,7 @@ hipError_t launch_ingest_scatter(const IngestBufs& b, hipStream_t st);
 hipError_t launch_ingest_sort(const IngestBufs& b, hipStream_t st);
 hipError_t launch_ingest_masks(const IngestBufs& b, uint64_t* masks, int planes, int64_t Np,
                                hipStream_t st);
+hipError_t launch_digest_u64(const uint64_t* p, int64_t n, unsigned long long* out, hipStream_t st);
 
 // Event grid layout (events.hip) ---------------------------------------------
 struct EvLayoutArgs {

@@ -8,6 +8,8 @@
 //     than p times in bin 64 s + b.
 // Validation: every pair must satisfy 0 <= bin < B and 0 <= neuron < N; the
 // number of violations and the first violating index are reported.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -192,6 +194,35 @@ hipError_t launch_ingest_masks(const IngestBufs& b, uint64_t* masks, int planes,
                                hipStream_t st) {
   hipLaunchKernelGGL(k_masks, dim3(grid_for(b.NS * b.NIB, 256)), dim3(256), 0, st, b, masks, planes,
                      Np);
+  return hipGetLastError();
+}
+
+// Digest of a raster for checkpoint matching: the wrapping 64-bit sum over k
+// of mix(w_k ^ mix(k + 1)), mix the splitmix64 finaliser.  A sum is
+// independent of the order the threads add in, so the digest is
+// deterministic; any changed word, or the same words at other positions,
+// changes it except with probability ~2^-64.
+namespace {
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_digest(const uint64_t* __restrict__ p, int64_t n,
+                                                unsigned long long* out) {
+  uint64_t acc = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    acc += mix64(p[k] ^ mix64((uint64_t)k + 1));
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, (unsigned long long)acc);
+}
+}  // namespace
+
+// out must hold 0 on entry.
+hipError_t launch_digest_u64(const uint64_t* p, int64_t n, unsigned long long* out, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096);
+  hipLaunchKernelGGL(k_digest, dim3((unsigned)blocks), dim3(256), 0, st, p, n, out);
   return hipGetLastError();
 }
 

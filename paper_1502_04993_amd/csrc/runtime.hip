@@ -76,6 +76,7 @@ struct glmr_ctx {
   int64_t* q = nullptr;
   std::vector<int64_t> q_host;
   bool all_spiking = false;
+  uint64_t raster_digest = 0;  // digest of the recorded masks (and, on the event grid, the slot times)
 
   // event grid (continuous time): slot start times and per-slot tables
   bool evm = false;
@@ -1325,10 +1326,10 @@ struct StateHead {
   double dt, tau;
   int64_t d, d_self;
   int32_t precision, m;  // m = 0: parameters only, no ascent
-  uint64_t spikes_fp;    // FNV-1a over the spike count and the per-neuron counts q_i
+  uint64_t spikes_fp;    // FNV-1a over the spike count, the per-neuron counts q_i and the raster digest
   double alpha, eps, jmax, mu_lo, mu_hi;
 };
-constexpr char kStateMagic[8] = {'G', 'L', 'M', 'R', 'S', 'T', '0', '1'};
+constexpr char kStateMagic[8] = {'G', 'L', 'M', 'R', 'S', 'T', '0', '2'};
 static_assert(offsetof(StateHead, precision) == 56, "the Python binding reads the precision at byte 56");
 
 uint64_t spikes_fingerprint(const glmr_ctx* c) {
@@ -1341,6 +1342,7 @@ uint64_t spikes_fingerprint(const glmr_ctx* c) {
   };
   mix((uint64_t)c->nspk);
   for (int i = 0; i < c->N; ++i) mix((uint64_t)c->q_host[i]);
+  mix(c->raster_digest);
   return h;
 }
 
@@ -1437,7 +1439,7 @@ glmr_status glmr_set_state(glmr_ctx* c, const void* buf, size_t len) {
   if (h.n_neurons != c->N || h.n_bins != c->B || h.time_mode != tm || h.dt != c->dt)
     return fail(c, GLMR_EINVAL, "the checkpoint is of another recording shape (N, n_bins, dt or time mode)");
   if (h.spikes_fp != spikes_fingerprint(c))
-    return fail(c, GLMR_EINVAL, "the checkpoint is of other spikes (spike counts differ)");
+    return fail(c, GLMR_EINVAL, "the checkpoint is of other spikes (spike counts or raster differ)");
   if (h.m < 0 || h.m > 64 || len != state_bytes(c, h.m)) return fail(c, GLMR_EINVAL, "state length or history");
   if (!(h.tau > 0) || !std::isfinite(h.tau)) return fail(c, GLMR_EINVAL, "bad tau in the checkpoint");
   TRY(glmr_set_precision(c, h.precision));
@@ -1892,9 +1894,16 @@ glmr_status ingest_pairs(glmr_ctx* c, const int64_t* bin, const int32_t* neuron,
   TRY(dalloc(c, c->masks, nm));
   HIPCHK(c, hipMemsetAsync(c->masks, 0, nm * sizeof(uint64_t), c->st));
   HIPCHK(c, launch_ingest_masks(b, c->masks, c->planes, c->Np, c->st));
+  // digest of the recorded raster (before any delay shifts it), for checkpoints
+  HIPCHK(c, hipMemsetAsync(bad, 0, 2 * sizeof(unsigned long long), c->st));
+  HIPCHK(c, launch_digest_u64(c->masks, (int64_t)nm, bad, c->st));
+  if (c->evm) HIPCHK(c, launch_digest_u64((const uint64_t*)c->tslot, c->NS * 64 + 1, bad + 1, c->st));
+  unsigned long long dig[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(dig, bad, sizeof dig, hipMemcpyDeviceToHost, c->st));
   c->q_host.assign(c->Np, 0);
   HIPCHK(c, hipMemcpyAsync(c->q_host.data(), c->q, c->Np * sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  c->raster_digest = (uint64_t)dig[0] ^ ((uint64_t)dig[1] * 0x9E3779B97F4A7C15ull);
   dfree(c, bad);
   dfree(c, cnt);
   dfree(c, cursor);

@@ -61,7 +61,7 @@ def test_null_context_calls():
     assert lib.glmr_fit(None, None, None) == _lib.GLMR_EINVAL
     n = ctypes.c_size_t(0)
     assert lib.glmr_get_state(None, None, ctypes.byref(n)) == _lib.GLMR_EINVAL
-    assert lib.glmr_set_state(None, b"GLMRST01", 8) == _lib.GLMR_EINVAL
+    assert lib.glmr_set_state(None, b"GLMRST02", 8) == _lib.GLMR_EINVAL
     o = _lib.glmr_fit_opts()
     lib.glmr_fit_defaults(ctypes.byref(o))
     assert o.resume == 0  # a fit starts afresh unless asked to resume

@@ -17,12 +17,19 @@ import pytest
 
 import synth
 from oracle import glm_oracle as O
+from parity_check import check
 from test_gpu_parity import round_fp8_rows
 
 pytestmark = pytest.mark.gpu
 
 ROWS = [0, 257, 799, 800, 999]  # first and last excitatory, first and last inhibitory, one inside
-TOL = {"fp32": (1e-9, 1e-4), "bf16": (1e-3, 1e-3), "fp8": (2e-3, 3e-2)}
+# Per-row L_i (the FP32 target 1e-10: at 3.6e6 bins a row averages as many
+# terms as the whole likelihood of the small parity cases), and the gradient
+# rows as a 2-norm and element-wise (tests/parity_check.py); the same bounds as
+# the parity tests.
+TOL = {"fp32": dict(row=1e-10, grad=1e-6, gmax=1e-6),
+       "bf16": dict(row=1e-3, grad=1e-3, gmax=1e-3),
+       "fp8": dict(row=5e-3, grad=3e-2, gmax=3e-2)}
 
 
 def _bf16(J):
@@ -57,19 +64,8 @@ def test_full_size_sampled_rows(tmp_path):
         q = ctx.query()
         ctx.close()
         assert q["trace_resident"] == (prec != "fp32")
-        rl = np.abs(r["ll_rows"][ROWS] - ref["ll_rows"]) / np.abs(ref["ll_rows"])
-        gt = np.concatenate([r["gmu"][ROWS], r["gJ"][ROWS].ravel()])
-        gtr = np.concatenate([ref["gmu"], ref["gJ"].ravel()])
-        rgt = np.linalg.norm(gt - gtr) / np.linalg.norm(gtr)
-        z = refs["zero"]
-        g = np.concatenate([r0["gmu"][ROWS], r0["gJ"][ROWS].ravel()])
-        gr = np.concatenate([z["gmu"], z["gJ"].ravel()])
-        rg = np.linalg.norm(g - gr) / np.linalg.norm(gr)
-        rl0 = np.abs(r0["ll_rows"][ROWS] - z["ll_rows"]) / np.abs(z["ll_rows"])
-        print(f"[full {prec}] max rel L_i {rl.max():.3e} (theta = 0: {rl0.max():.3e}), rel grad rows "
-              f"{rgt:.3e} (theta = 0: {rg:.3e})", flush=True)
-        assert rl.max() <= TOL[prec][0] and rl0.max() <= TOL[prec][0]
-        assert rgt <= TOL[prec][1] and rg <= TOL[prec][1]
+        check(f"full {prec} at the simulated theta", r, ref, TOL[prec], rows=ROWS)
+        check(f"full {prec} at theta = 0", r0, refs["zero"], TOL[prec], rows=ROWS)
 
 
 def _fingerprint(rec):
@@ -135,3 +131,57 @@ def test_full_size_fit_reaches_oracle_row_optima():
     # brings it to a small fraction of it (0.0007)
     assert rb["converged"] and zb < 1.0
     assert zp < 0.05 and zmu < 0.05
+
+
+def _golden(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
+
+
+def _rows_ref(point):
+    return dict(ll_rows=np.array([float(v) for v in point["ll_rows"]]),
+                gmu=np.array([float(v) for v in point["gmu"]]),
+                gJ=np.array([[float(v) for v in row] for row in point["gJ"]]))
+
+
+EV_TOL = {"fp64": dict(row=1e-11, grad=1e-10, gmax=1e-10),
+          "fp32": dict(row=1e-10, grad=1e-6, gmax=1e-6),
+          "bf16": dict(row=1e-3, grad=1e-3, gmax=1e-3)}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp64", "fp32"])
+def test_event_grid_full_size_rows(prec, tmp_path):
+    """Continuous time at the headline size (23.8 M events, 24.3 M slots,
+    N = 1000) in the bench's launch configuration (default chunking; BF16:
+    resident trace, autotuned tiles), every index far past 2^31, against the
+    oracle's continuous-time rows stored by tests/golden/make_events_full_rows.py
+    (Eq. (7)-(8), (10), (12), (14)), at the BF16-rounded simulated weights and
+    at theta = 0."""
+    import paper_1502_04993_amd as G
+    gold = _golden("events_config2_rows.json")
+    rows = gold["rows"]
+    rec = synth.cached("config2", seed=0, B=3_600_000)
+    N = rec.n_neurons
+    times, neu = synth.event_times(rec, seed=0)
+    meta = gold["recording"]
+    assert times.shape[0] == meta["n_events"] and int(np.sum(neu.astype(np.int64))) == meta["neuron_sum"]
+    assert float(np.sum(times)) == float(meta["time_sum"])
+    print(f"[events full {prec}] {times.shape[0]} events ready", flush=True)
+    ctx = G.Context.from_events(N, times, neu, 0.0, rec.T, precision=prec)
+    ctx.set_kernel(rec.tau)
+    J = _bf16(rec.J)
+    ctx.set_params(J, rec.mu)
+    if prec == "bf16":
+        ctx.autotune(str(tmp_path / "tune.txt"))
+    r = ctx.eval(grad=True)
+    ctx.set_params(np.zeros((N, N)), np.zeros(N))
+    r0 = ctx.eval(grad=True)
+    q = ctx.query()
+    ctx.close()
+    print(f"[events full {prec}] slots={q['b_pad']} chunk={q['chunk_bins']} resident={q['trace_resident']}",
+          flush=True)
+    assert q["trace_resident"] == (prec == "bf16")
+    check(f"events full {prec} at the simulated theta", r, _rows_ref(gold["points"]["bf16"]), EV_TOL[prec],
+          rows=rows)
+    check(f"events full {prec} at theta = 0", r0, _rows_ref(gold["points"]["zero"]), EV_TOL[prec], rows=rows)

@@ -1,26 +1,33 @@
 """Parity of the HIP likelihood path against the FP64 oracle (needs an MI355X).
 
-Tolerances (relative to the oracle at the same parameters; the parameters are
-chosen representable in the compute precision, since each mode evaluates the
-likelihood of the parameters rounded to it):
-  FP64: L 1e-12, gradient 1e-10
-  FP32: L 1e-10 at the N = 1000 workloads (the stated target), gradient 1e-4.
-        U = sum_j J_ij x_j is accumulated in FP64 from FP32 operands; the
-        remaining error of L comes from rounding x to FP32 (stochastically, so
-        it is random in sign) and its relative size falls as 1/sqrt(B N); on
-        the tiny cases here (B N ~ 1e5-1e6) the bound is 1e-10 sqrt(2e6/(B N)).
-        The gradient contraction accumulates in FP32 per time split (FP64
-        across splits); absorption of tiny products there leaves ~2e-5.
-  BF16: L 1e-3, gradient 1e-3 (at theta = 0 and near the truth).
+Every comparison asserts four errors (tests/parity_check.py): the total L,
+the largest per-row error of L_i, the 2-norm of the gradient error over
+(dL/dmu, dL/dJ), and its largest element relative to the largest gradient
+element.  Bounds (relative to the oracle at the same parameters; the
+parameters are chosen representable in the compute precision, since each mode
+evaluates the likelihood of the parameters rounded to it):
+  FP64: L 1e-12, L_i 1e-11, gradient 1e-10 (2-norm and element-wise).
+  FP32: L 1e-10 at the N = 1000 workloads (the stated target).  U = sum_j
+        J_ij x_j is accumulated in FP64 from FP32 operands; the remaining
+        error of L comes from rounding x to FP32 (stochastically, so it is
+        random in sign) and its relative size falls as 1/sqrt(B N); on the
+        tiny cases here (B N ~ 1e5-1e6) the bound is 1e-10 sqrt(2e6/(B N)).
+        A row averages B terms instead of B N, so L_i's bound is sqrt(N)
+        times that.  The gradient contraction takes the same FP32-rounded
+        operands widened to FP64 and accumulates in FP64, so the gradient
+        error is the trace rounding alone (measured <= 6e-9): bound 1e-6,
+        2-norm and element-wise.
+  BF16: L 1e-3, L_i 1e-3, gradient 1e-3 (2-norm, the stated target) and
+        element-wise (at theta = 0 and near the truth).
 "bf16" runs the resident trace (built once per tau, kept in HBM); "bf16-rc"
 rebuilds the trace inside the contractions.
-  FP8 (no target is set for it): L 2e-3, gradient 3e-2, at J rounded to the
-        FP8 representation (per-row power-of-two scale, e4m3).  The trace is
-        e4m3 (3 mantissa bits) and the weights e5m2 (2 bits), both rounded
-        stochastically, so each element carries ~5-10 % unbiased noise that
-        averages over the bins; what is left in L is second order (the
-        convexity of exp), measured at ~3e-4 for N = 1000.
-Gradient error = ||g - g_oracle||_2 / ||g_oracle||_2 over (dL/dmu, dL/dJ).
+  FP8 (no target is set for it): L 2e-3, L_i 5e-3, gradient 3e-2 (2-norm and
+        element-wise), at J rounded to the FP8 representation (per-row
+        power-of-two scale, e4m3).  The trace is e4m3 (3 mantissa bits) and
+        the weights e5m2 (2 bits), both rounded stochastically, so each
+        element carries ~5-10 % unbiased noise that averages over the bins;
+        what is left in L is second order (the convexity of exp), measured at
+        ~3e-4 for N = 1000.
 """
 import sys
 
@@ -29,19 +36,33 @@ import pytest
 
 import synth
 from oracle import glm_oracle as O
+from parity_check import check
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-10, 1e-4), "bf16": (1e-3, 1e-3), "bf16-rc": (1e-3, 1e-3),
-       "fp8": (2e-3, 3e-2)}
+TOL = {"fp64": dict(ll=1e-12, row=1e-11, grad=1e-10, gmax=1e-10),
+       "fp32": dict(ll=1e-10, row=1e-10, grad=1e-6, gmax=1e-6),
+       "bf16": dict(ll=1e-3, row=1e-3, grad=1e-3, gmax=1e-3),
+       "bf16-rc": dict(ll=1e-3, row=1e-3, grad=1e-3, gmax=1e-3),
+       "fp8": dict(ll=2e-3, row=5e-3, grad=3e-2, gmax=3e-2)}
 ALL = ["fp64", "fp32", "bf16", "bf16-rc", "fp8"]
 
 
 def ll_tol(prec, rec):
-    tl = TOL[prec][0]
+    tl = TOL[prec]["ll"]
     if prec == "fp32":
         tl *= max(1.0, (2e6 / (rec.n_bins * rec.n_neurons)) ** 0.5)
     return tl
+
+
+def tol_for(prec, rec):
+    """The four bounds of a mode for a recording (FP32's L bounds scale with
+    the number of terms, see the module docstring)."""
+    t = dict(TOL[prec])
+    if prec == "fp32":
+        t["ll"] = ll_tol(prec, rec)
+        t["row"] = t["ll"] * rec.n_neurons ** 0.5
+    return t
 
 
 def _G():
@@ -113,13 +134,9 @@ def run_gpu(rec, J, mu, prec, tau=None, want_tau=False, **kw):
     return out
 
 
-def report(tag, got, ref):
-    rl = abs(got["ll"] - ref["ll"]) / abs(ref["ll"])
-    rg = _rel(_gvec(got), _gvec(ref))
-    rr = float(np.max(np.abs(got["ll_rows"] - ref["ll_rows"]) / np.maximum(np.abs(ref["ll_rows"]), 1e-300)))
-    print(f"[{tag}] rel_ll={rl:.3e} rel_grad={rg:.3e} max_rel_row={rr:.3e}", flush=True)
-    sys.stdout.flush()
-    return rl, rg, rr
+def report(tag, got, ref, tol):
+    """Assert the four element-wise errors of got against the oracle's ref."""
+    return check(tag, got, ref, tol)
 
 
 _REC = {}
@@ -143,8 +160,7 @@ def test_parity_small_ragged(prec):
     J, mu = theta_for(rec, prec)
     ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, J, mu)
     got = run_gpu(rec, J, mu, prec)
-    rl, rg, rr = report(f"small {prec}", got, ref)
-    assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
+    report(f"small {prec}", got, ref, tol_for(prec, rec))
 
 
 @pytest.mark.parametrize("prec", ALL)
@@ -155,8 +171,7 @@ def test_parity_at_zero_coupling(prec):
     mu = np.zeros(N)
     ref = O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, rec.tau, J, mu)
     got = run_gpu(rec, J, mu, prec)
-    rl, rg, rr = report(f"zero {prec}", got, ref)
-    assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
+    report(f"zero {prec}", got, ref, tol_for(prec, rec))
 
 
 @pytest.mark.parametrize("prec", ALL)
@@ -166,8 +181,7 @@ def test_multichunk_multisplit(prec):
     ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, J, mu)
     got = run_gpu(rec, J, mu, prec, chunk_bins=4096)
     assert got["query"]["chunk_bins"] == 4096
-    rl, rg, rr = report(f"chunks {prec}", got, ref)
-    assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
+    report(f"chunks {prec}", got, ref, tol_for(prec, rec))
 
 
 @pytest.mark.parametrize("prec", ALL)
@@ -179,8 +193,7 @@ def test_last_chunk_with_partial_split(prec):
     ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, J, mu)
     got = run_gpu(rec, J, mu, prec, chunk_bins=36864)
     assert got["query"]["chunk_bins"] == 36864
-    rl, rg, rr = report(f"last chunk {prec}", got, ref)
-    assert rl <= ll_tol(prec, rec) and rg <= TOL[prec][1]
+    report(f"last chunk {prec}", got, ref, tol_for(prec, rec))
 
 
 def test_multiple_spikes_per_bin():
@@ -199,8 +212,7 @@ def test_multiple_spikes_per_bin():
     ref = O.loglik(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, J, mu)
     got = run_gpu(rec, J, mu, "fp64")
     assert got["query"]["planes"] == 4
-    rl, rg, rr = report("multi fp64", got, ref)
-    assert rl <= 1e-12 and rg <= 1e-10
+    report("multi fp64", got, ref, TOL["fp64"])
 
 
 def test_edges_first_last_bin_and_silent_neuron():
@@ -223,8 +235,7 @@ def test_edges_first_last_bin_and_silent_neuron():
         ctx.fit(max_iter=2)  # MLE of the silent neuron does not exist
     ctx.close()
     ref = O.loglik(bins, neu, N, B, 0.001, 0.005, J, mu)
-    rl, rg, rr = report("edges fp64", got, ref)
-    assert rl <= 1e-12 and rg <= 1e-10
+    report("edges fp64", got, ref, TOL["fp64"])
 
 
 def test_rejects_out_of_range_spikes():
@@ -271,6 +282,24 @@ def test_tau_gradient(prec, tol):
     assert r <= tol
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16-rc"])
+def test_tau_gradient_many_tiles_and_chunks(prec):
+    # N = 300 pads to 512 (several neuron tiles, i0 > 0) and chunk_bins = 4096
+    # splits the 30016 padded bins into seven full chunks and a short last one:
+    # the tile-major weights that the resident trace's dL/dtau contraction
+    # reads are addressed at every tile and chunk offset
+    rec = synth.balanced(N=300, B=30_000, tau=0.008, seed=12)
+    J, mu = theta_for(rec, prec, seed=5)
+    tau = 0.011
+    ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, tau, J, mu, want_tau=True)
+    got = run_gpu(rec, J, mu, prec, tau=tau, want_tau=True, chunk_bins=4096)
+    assert got["query"]["chunk_bins"] == 4096 and got["query"]["n_pad"] == 512
+    r = abs(got["gtau"] - ref["gtau"]) / abs(ref["gtau"])
+    print(f"[tau tiles {prec}] gtau={got['gtau']:.8e} ref={ref['gtau']:.8e} rel={r:.2e}", flush=True)
+    report(f"tau tiles {prec}", got, ref, tol_for(prec, rec))
+    assert r <= 1e-2
+
+
 @pytest.mark.parametrize("prec", ["bf16", "bf16-rc", "fp8"])
 def test_determinism_bitwise(prec):
     rec = small_rec()
@@ -301,8 +330,7 @@ def test_config1_fp64():
     for tag, J, mu in (("zero", np.zeros((N, N)), np.zeros(N)), ("truth", rec.J, rec.mu)):
         ref = O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, rec.tau, J, mu)
         got = run_gpu(rec, J, mu, "fp64")
-        rl, rg, rr = report(f"config1 {tag}", got, ref)
-        assert rl <= 1e-12 and rg <= 1e-10
+        report(f"config1 {tag}", got, ref, TOL["fp64"])
 
 
 _BIG = {}
@@ -327,5 +355,4 @@ def test_n1000_parity(prec, where):
         J, mu = _round(rec.J, prec), rec.mu.copy()
     ref = O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, rec.tau, J, mu)
     got = run_gpu(rec, J, mu, prec)
-    rl, rg, rr = report(f"n1000 {where} {prec}", got, ref)
-    assert rl <= TOL[prec][0] and rg <= TOL[prec][1]
+    report(f"n1000 {where} {prec}", got, ref, tol_for(prec, rec))

@@ -139,6 +139,16 @@ def test_checkpoint_rejections():
     with pytest.raises(G.GlmrError) as e:
         o.set_state(st)
     assert e.value.status == G.L.GLMR_EINVAL
+    # the same spikes at other times (the bins permuted): equal total and
+    # per-neuron counts, another raster
+    perm = np.random.default_rng(5).permutation(rec.n_bins)
+    moved = _G().Context(rec.n_neurons, rec.n_bins, rec.dt, precision="fp64")
+    moved.set_spikes(perm[rec.bins].astype(np.int64), rec.neurons)
+    moved.set_kernel(rec.tau)
+    with pytest.raises(G.GlmrError) as e:
+        moved.set_state(st)
+    assert e.value.status == G.L.GLMR_EINVAL and "raster" in str(e.value)
+    moved.close()
     small = synth.balanced(N=20, B=10_000, in_frac=0.3, seed=173)
     s2 = _ctx(small, "fp64", rec.tau)
     with pytest.raises(G.GlmrError) as e:

@@ -513,3 +513,65 @@ def test_newton_rows_chunked_matches_dense_newton_and_kkt():
         g = np.abs(np.concatenate([[r["gmu"][k]], r["gJ"][k]])).max()
         g0 = np.abs(np.concatenate([[r0["gmu"][k]], r0["gJ"][k]])).max()
         assert g <= 1e-9 * g0
+
+
+def test_newton_rows_sub_reaches_dense_newton_optimum_and_kkt():
+    """The subsampled-Newton-matrix row fit (the many-row full-size reference)
+    reaches the dense per-row Newton's optimum: its steps use a Hessian of
+    Eq. (18) taken on every second chunk only, but it iterates on the exact
+    gradient, whose zero is the one maximiser of the concave row problem
+    (App. A).  Chunks of 3000 bins leave a ragged last chunk; the rows are
+    given out of order."""
+    import synth
+    rec = synth.config1(0)
+    N, B = rec.n_neurons, rec.n_bins
+    rows = [45, 0, 7, 23]
+    res = O.newton_rows_sub(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, rows, hess_stride=2,
+                            refresh=2, chunk=3000)
+    Jn, mun, _ = O.newton_fit(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, rows=rows)
+    J = np.zeros((N, N))
+    mu = np.zeros(N)
+    for i in rows:
+        assert np.abs(res[i]["J"] - Jn[i]).max() < 1e-8 and abs(res[i]["mu"] - mun[i]) < 1e-9
+        J[i], mu[i] = res[i]["J"], res[i]["mu"]
+    r = O.loglik(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, J, mu, rows=rows)
+    q = O.spike_counts(rec.neurons, N)
+    r0 = O.loglik(rec.bins, rec.neurons, N, B, rec.dt, rec.tau, np.zeros((N, N)), np.log(q / (B * rec.dt)),
+                  rows=rows)
+    for k, i in enumerate(rows):
+        assert res[i]["ll"] == pytest.approx(float(r["ll_rows"][k]), rel=1e-13)
+        g = np.abs(np.concatenate([[r["gmu"][k]], r["gJ"][k]])).max()
+        g0 = np.abs(np.concatenate([[r0["gmu"][k]], r0["gJ"][k]])).max()
+        assert g <= 1e-9 * g0
+        assert res[i]["max_abs_grad"] == pytest.approx(g, rel=1e-3, abs=1e-12 * g0)
+        # the standard-error estimate is positive and finite
+        assert np.all(np.isfinite(res[i]["se"])) and np.all(res[i]["se"] > 0)
+
+
+@pytest.mark.parametrize("chunk", [7, 50, 65536])
+def test_continuous_eval_rows_is_the_all_rows_evaluator(chunk):
+    """The rows-restricted continuous evaluator (for event lists too long for
+    the all-rows loop) gives continuous_eval's rows: L_i, dL/dJ_i. and dL/dmu_i
+    of Eq. (7), (10), (12), (14), with chunk boundaries anywhere, an event at
+    T0, equal times of different neurons, and rows out of order."""
+    rng = np.random.default_rng(17)
+    N, T0, T1, tau = 6, 0.0, 2.0, 0.015
+    ts = [np.sort(rng.random(int(rng.integers(8, 20))) * (T1 - T0) + T0) for _ in range(N)]
+    ts[0] = np.sort(np.concatenate([[T0], ts[0]]))
+    ts[3] = np.sort(np.concatenate([ts[3], [ts[1][2]]]))  # a tie with neuron 1
+    J = rng.normal(0.0, 0.8, (N, N))
+    J[2] = 0.0  # D = 0 throughout for this row
+    J[4, :] *= 1e-4  # |D| in the series branch
+    mu = np.log(rng.uniform(3.0, 9.0, N))
+    ref = O.continuous_eval(ts, T0, T1, tau, J, mu)
+    times = np.concatenate(ts)
+    neu = np.concatenate([np.full(len(t), j) for j, t in enumerate(ts)]).astype(np.int32)
+    order = np.lexsort((neu, times))
+    rows = [5, 0, 2, 4, 3, 1]
+    r = O.continuous_eval_rows(times[order], neu[order], N, T0, T1, tau, J, mu, rows, chunk=chunk)
+    assert np.allclose(r["ll_rows"], ref["ll_rows"][rows], rtol=1e-12, atol=1e-12)
+    assert np.allclose(r["gJ"], ref["gJ"][rows], rtol=1e-11, atol=1e-11)
+    assert np.allclose(r["gmu"], ref["gmu"][rows], rtol=1e-12, atol=1e-12)
+    assert np.array_equal(r["q"], np.array([len(ts[i]) for i in rows], dtype=float))
+    sub = O.continuous_eval_rows(times[order], neu[order], N, T0, T1, tau, J, mu, [3], chunk=chunk)
+    assert np.allclose(sub["ll_rows"], ref["ll_rows"][[3]], rtol=1e-12, atol=1e-12)
