@@ -82,8 +82,15 @@ typedef enum {
                     contraction on the FP32 MFMA; exp and lambda sums in FP64 */
   GLMR_BF16 = 2, /* trace, J and lambda in BF16 (trace rounded stochastically),
                     MFMA with FP32 accumulation */
-  GLMR_FP8 = 3   /* trace, J and lambda in OCP e4m3 with power-of-two scales,
+  GLMR_FP8 = 3,  /* trace, J and lambda in OCP e4m3 with power-of-two scales,
                     FP32 accumulation */
+  GLMR_BF16_J2 = 4 /* GLMR_BF16 with J as the sum of two BF16 terms (its 16
+                    leading significant bits): kernel U takes k over [J_hi | J_lo]
+                    against the trace twice, so the likelihood is that of J to
+                    ~1e-5 relative instead of BF16's 4e-3 steps, at one more pass
+                    of the trace through the MFMA in kernel U.  Resident trace
+                    only; no dL/dtau (GLMR_EINVAL).  Switching between GLMR_BF16
+                    and GLMR_BF16_J2 keeps the trace. */
 } glmr_precision;
 
 typedef enum { GLMR_HOST = 0, GLMR_DEVICE = 1 } glmr_where;
@@ -226,7 +233,8 @@ glmr_status glmr_eval(glmr_ctx* ctx, double* ll, double* ll_rows, double* grad_J
 typedef struct {
   int32_t max_iter;       /* iteration cap (default 500) */
   double ftol;            /* per-row stop when |L_i^k - L_i^(k-1)| / |L_i^k| <= ftol
-                             (Sec. 2.6.3); 0 = precision default */
+                             (Sec. 2.6.3); 0 = precision default (FP64 1e-14, FP32 1e-11,
+                             BF16 1e-6, BF16 with a two-term J 1e-10, FP8 1e-4) */
   int32_t lbfgs_m;        /* history length, 1..64 (default 40; the state takes 2 m N (N+1)
                              doubles) */
   int32_t max_backtracks; /* Armijo halvings per iteration (default 30) */

@@ -347,7 +347,6 @@ class Context:
 
     def set_kernel(self, tau: float):
         return glmr_set_kernel(self._c, tau)
-
     def set_delays(self, d_bins: int, d_self_bins: int):
         """Transmission delays in bins: d on every connection j -> i (j != i),
         d_self on the self-connection (Sec. 2.4, Eq. (15))."""

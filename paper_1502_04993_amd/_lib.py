@@ -21,12 +21,13 @@ GLMR_ENOSPIKES = -4
 GLMR_ENONFINITE = -5
 GLMR_ESTATE = -6
 
-GLMR_FP64, GLMR_FP32, GLMR_BF16, GLMR_FP8 = 0, 1, 2, 3
+GLMR_FP64, GLMR_FP32, GLMR_BF16, GLMR_FP8, GLMR_BF16_J2 = 0, 1, 2, 3, 4
 GLMR_HOST, GLMR_DEVICE = 0, 1
 GLMR_TRACE_AUTO, GLMR_TRACE_RESIDENT, GLMR_TRACE_RECOMPUTE = 0, 1, 2
 TRACE_MODES = {"auto": GLMR_TRACE_AUTO, "resident": GLMR_TRACE_RESIDENT, "recompute": GLMR_TRACE_RECOMPUTE}
 
-PRECISIONS = {"fp64": GLMR_FP64, "fp32": GLMR_FP32, "bf16": GLMR_BF16, "fp8": GLMR_FP8}
+PRECISIONS = {"fp64": GLMR_FP64, "fp32": GLMR_FP32, "bf16": GLMR_BF16, "fp8": GLMR_FP8,
+              "bf16j2": GLMR_BF16_J2}
 GLMR_TIME_GRID, GLMR_TIME_EVENTS = 0, 1
 TIME_MODES = {"grid": GLMR_TIME_GRID, "events": GLMR_TIME_EVENTS}
 

@@ -80,7 +80,8 @@ hipError_t launch_ingest_scatter(const IngestBufs& b, hipStream_t st);
 hipError_t launch_ingest_sort(const IngestBufs& b, hipStream_t st);
 hipError_t launch_ingest_masks(const IngestBufs& b, uint64_t* masks, int planes, int64_t Np,
                                hipStream_t st);
-hipError_t launch_digest_u64(const uint64_t* p, int64_t n, unsigned long long* out, hipStream_t st);
+hipError_t launch_digest_u64(const uint64_t* p, int64_t n_outer, int64_t inner, int64_t ld, int64_t cols,
+                             unsigned long long* out, hipStream_t st);
 
 // Event grid layout (events.hip) ---------------------------------------------
 struct EvLayoutArgs {
@@ -249,7 +250,8 @@ hipError_t launch_build_x(const ResXArgs& a, hipStream_t st);
 hipError_t launch_build_x8(const ResXArgs& a, hipStream_t st);
 
 struct ResUArgs {
-  const void* Jc;          // [Np][Np] bf16
+  const void* Jc;          // [Np][Np] bf16 ([Np][2 Np]: J_hi | J_lo when j2)
+  int j2;                  // J as two BF16 terms: k runs over 2 Np, the trace repeated
   const void* Xtj;         // [Bp][Np] bf16
   int64_t Np, B;
   int64_t t0;              // first bin of this chunk
@@ -325,7 +327,7 @@ hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st);
 hipError_t launch_sum_rows(const double* v, int n, double* out, hipStream_t st);
 
 // Parameter preparation
-hipError_t launch_prepare_params(int prec, int N, int64_t Np, const double* J64, const double* mu,
+hipError_t launch_prepare_params(int prec, int j2, int N, int64_t Np, const double* J64, const double* mu,
                                  void* Jc, double* Jr, double* rowscale, float* jscale,
                                  hipStream_t st);
 hipError_t launch_copy_out(const double* src, int64_t src_ld, double* dst, int rows, int cols,

@@ -260,14 +260,17 @@ struct Nt {
 // A and B point at the tile's first row; lda/ldb and the k range [kb, ke) are
 // in bytes, the range a multiple of 128.  atile > 0: A is stored tile-major,
 // rows of lda bytes grouped in k blocks of lda bytes that lie atile bytes
-// apart (byte k of row r at A + (k / lda) atile + r lda + k % lda).  Acc element r of lane l of block
-// (a, b) is row 32a + 8(r/4) + 4(l/32) + r%4, column 32b + l%32 of the wave tile.
+// apart (byte k of row r at A + (k / lda) atile + r lda + k % lda).  awrap > 0:
+// A's k repeats with that period (byte k of row r at A + r lda + k % awrap, for
+// k < 2 awrap): B then holds two k blocks against the same A.  Acc element r
+// of lane l of block (a, b) is row 32a + 8(r/4) + 4(l/32) + r%4, column
+// 32b + l%32 of the wave tile.
 template <int BM, int BN, int WGM, int WGN, typename Op>
 __device__ __forceinline__ void nt_loop(const unsigned char* __restrict__ A, int64_t lda,
                                         const unsigned char* __restrict__ Bt, int64_t ldb, int64_t kb,
                                         int64_t ke, unsigned char* smem,
                                         f32x16 (&acc)[Nt<BM, BN, WGM, WGN>::MB][Nt<BM, BN, WGM, WGN>::NB],
-                                        int64_t atile = 0) {
+                                        int64_t atile = 0, int64_t awrap = 0) {
   using T = Nt<BM, BN, WGM, WGN>;
   constexpr int SB = BK * 2;  // bytes per row and step
   const int tid = threadIdx.x, lane = tid & 63;
@@ -282,7 +285,7 @@ __device__ __forceinline__ void nt_loop(const unsigned char* __restrict__ A, int
 #pragma unroll
     for (int q = 0; q < T::APT; ++q) {
       const int piece = tid + q * T::NT, r = piece >> 3, c = piece & 7;
-      const int64_t ka = atile ? (k0 / lda) * atile + k0 % lda : k0;
+      const int64_t ka = atile ? (k0 / lda) * atile + k0 % lda : (awrap && k0 >= awrap ? k0 - awrap : k0);
       ar[q] = *(const i32x4*)(A + r * lda + ka + c * 16);
     }
 #pragma unroll
@@ -370,9 +373,11 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
 
   f32x16 acc[T::MB][T::NB];
   zero_acc(acc);
+  // J in two BF16 terms: rows [J_hi | J_lo] of 2 Np, k over both against the same trace
+  const int64_t jrow = g.Np * ES, ldj = (!F8 && g.j2) ? 2 * jrow : jrow;
   nt_loop<BT, BI, WGM, WGN, Op>((const unsigned char*)g.Xtj + tt0 * g.Np * ES, g.Np * ES,
-                                (const unsigned char*)g.Jc + i0 * g.Np * ES, g.Np * ES, 0, g.Np * ES,
-                                smem, acc);
+                                (const unsigned char*)g.Jc + i0 * ldj, ldj, 0, ldj, smem, acc, 0,
+                                ldj != jrow ? jrow : 0);
 
   // W = exp(V) (0 past the last bin); sums over the wave's bins per neuron in
   // FP32 over at most 16 MB values, FP64 beyond.  The loop ended on a barrier,

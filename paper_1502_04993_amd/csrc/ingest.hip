@@ -197,11 +197,13 @@ hipError_t launch_ingest_masks(const IngestBufs& b, uint64_t* masks, int planes,
   return hipGetLastError();
 }
 
-// Digest of a raster for checkpoint matching: the wrapping 64-bit sum over k
-// of mix(w_k ^ mix(k + 1)), mix the splitmix64 finaliser.  A sum is
-// independent of the order the threads add in, so the digest is
-// deterministic; any changed word, or the same words at other positions,
-// changes it except with probability ~2^-64.
+// Digest of a raster for checkpoint matching, independent of the padding:
+// the wrapping 64-bit sum over the nonzero words w of mix(w ^ mix(id + 1)),
+// mix the splitmix64 finaliser and id the word's logical position (plane,
+// subtile, neuron j < N; or the index of a plain array).  A sum does not
+// depend on the order the threads add in, so the digest is deterministic;
+// a changed word, or the same words at other positions, changes it except
+// with probability ~2^-64.
 namespace {
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -209,20 +211,30 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(256) void k_digest(const uint64_t* __restrict__ p, int64_t n,
-                                                unsigned long long* out) {
+// words p[(q * inner + s) * ld + j] for planes q < n_outer / inner, s < inner, j < cols;
+// logical id (q, s, j)
+__global__ __launch_bounds__(256) void k_digest(const uint64_t* __restrict__ p, int64_t n_outer, int64_t inner,
+                                                int64_t ld, int64_t cols, unsigned long long* out) {
   uint64_t acc = 0;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-    acc += mix64(p[k] ^ mix64((uint64_t)k + 1));
+  const int64_t n = n_outer * cols;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = k / cols, j = k % cols;
+    const uint64_t w = p[a * ld + j];
+    const uint64_t id = ((uint64_t)(a / inner) << 56) + ((uint64_t)(a % inner) << 20) + (uint64_t)j;
+    if (w) acc += mix64(w ^ mix64(id + 1));
+  }
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if ((threadIdx.x & 63) == 0) atomicAdd(out, (unsigned long long)acc);
 }
 }  // namespace
 
-// out must hold 0 on entry.
-hipError_t launch_digest_u64(const uint64_t* p, int64_t n, unsigned long long* out, hipStream_t st) {
+// Adds to *out the digest of n_outer rows of `cols` words (row pitch ld),
+// row a being subtile a % inner of plane a / inner.
+hipError_t launch_digest_u64(const uint64_t* p, int64_t n_outer, int64_t inner, int64_t ld, int64_t cols,
+                             unsigned long long* out, hipStream_t st) {
+  const int64_t n = n_outer * cols;
   const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096);
-  hipLaunchKernelGGL(k_digest, dim3((unsigned)blocks), dim3(256), 0, st, p, n, out);
+  hipLaunchKernelGGL(k_digest, dim3((unsigned)blocks), dim3(256), 0, st, p, n_outer, inner, ld, cols, out);
   return hipGetLastError();
 }
 

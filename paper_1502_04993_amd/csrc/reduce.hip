@@ -145,6 +145,24 @@ __global__ void k_prepare_f32u(int N, int64_t Np, const double* J64, const doubl
   }
 }
 
+// BF16 with J in two terms: row i of Jc is [bf16(J_i.) | bf16(J_i. - bf16(J_i.))]
+// (pitch 2 Np); Jr holds their exact sum, the value the likelihood is of.
+__global__ void k_prepare_j2(int N, int64_t Np, const double* J64, const double* mu, __bf16* Jc, double* Jr,
+                             double* rowscale) {
+  const int64_t n = Np * Np;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = k / Np, j = k % Np;
+    const double v = (i < N && j < N) ? J64[k] : 0.0;
+    const __bf16 hi = to_prec<__bf16>(v);
+    const __bf16 lo = to_prec<__bf16>(v - (double)hi);
+    Jc[i * 2 * Np + j] = hi;
+    Jc[i * 2 * Np + Np + j] = lo;
+    Jr[k] = (double)hi + (double)lo;
+    if (j == 0) rowscale[i] = (i < N) ? exp(mu[i]) : 0.0;
+  }
+}
+
 // FP8: row i of J times the power-of-two scale 2^floor(log2(448 / max_j |J_ij|)),
 // rounded to the nearest OCP e4m3 value; Jr holds the value actually used.
 // One 256-thread block per row.
@@ -529,7 +547,7 @@ hipError_t launch_sum_rows(const double* v, int n, double* out, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_prepare_params(int prec, int N, int64_t Np, const double* J64, const double* mu,
+hipError_t launch_prepare_params(int prec, int j2, int N, int64_t Np, const double* J64, const double* mu,
                                  void* Jc, double* Jr, double* rowscale, float* jscale,
                                  hipStream_t st) {
   const int g = grid_for(Np * Np, 256);
@@ -543,8 +561,12 @@ hipError_t launch_prepare_params(int prec, int N, int64_t Np, const double* J64,
                          rowscale);
       break;
     case PREC_BF16:
-      hipLaunchKernelGGL(k_prepare<__bf16>, dim3(g), dim3(256), 0, st, N, Np, J64, mu, (__bf16*)Jc, Jr,
-                         rowscale);
+      if (j2)
+        hipLaunchKernelGGL(k_prepare_j2, dim3(g), dim3(256), 0, st, N, Np, J64, mu, (__bf16*)Jc, Jr,
+                           rowscale);
+      else
+        hipLaunchKernelGGL(k_prepare<__bf16>, dim3(g), dim3(256), 0, st, N, Np, J64, mu, (__bf16*)Jc, Jr,
+                           rowscale);
       break;
     case PREC_FP8:
       if (!jscale) return hipErrorInvalidValue;

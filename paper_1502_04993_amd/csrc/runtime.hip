@@ -111,10 +111,12 @@ struct glmr_ctx {
   size_t x_bytes = 0;                    // bytes of each layout as allocated
   unsigned* xmax = nullptr;              // FP8: per-chunk trace maxima
   float* xscale = nullptr;               // FP8: per-chunk trace scales
+  int64_t x_nchunks = 0;                 // FP8: entries of xmax / xscale
   float* jscale = nullptr;               // FP8: per-row scales of J
 
   // parameters (padded FP64 masters and the compute-precision copy)
   bool have_params = false;
+  bool j2 = false;  // GLMR_BF16_J2: J staged as two BF16 terms (prec is PREC_BF16)
   double* J64 = nullptr;
   double* mu = nullptr;
   void* Jc = nullptr;
@@ -208,6 +210,41 @@ void dfree(glmr_ctx* c, T*& p) {
     if (s_ != GLMR_OK) return s_;    \
   } while (0)
 
+// Temporaries of a set-up pass come either from hipMalloc (ar == nullptr) or
+// from a bump arena over the static scratch array (the no-allocation entry
+// point); buffers that persist in the context must then exist already.
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
+template <typename T>
+glmr_status temp_alloc(glmr_ctx* c, Arena* ar, T*& p, size_t n) {
+  if (!ar) return dalloc(c, p, n);
+  const size_t at = (ar->used + 255) & ~(size_t)255;
+  const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  if (at + bytes > ar->cap)
+    return fail(c, GLMR_EINVAL, "the set-up needs more than the %zu bytes of static scratch", ar->cap);
+  p = (T*)(ar->base + at);
+  ar->used = at + bytes;
+  return GLMR_OK;
+}
+
+template <typename T>
+void temp_free(glmr_ctx* c, Arena* ar, T*& p) {
+  if (ar) p = nullptr;
+  else dfree(c, p);
+}
+
+template <typename T>
+glmr_status persist(glmr_ctx* c, Arena* ar, T*& p, size_t n) {
+  if (p) return GLMR_OK;
+  if (ar)
+    return fail(c, GLMR_ESTATE, "the per-tau buffers do not exist yet: call glmr_set_kernel once on this "
+                                "context before glmr_set_kernel_noalloc");
+  return dalloc(c, p, n);
+}
+
 hipEvent_t ev_get(glmr_ctx* c) {
   if (!c->pool.empty()) {
     hipEvent_t e = c->pool.back();
@@ -257,6 +294,10 @@ int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 size_t in_bytes(int prec) { return prec == PREC_F64 ? 8 : prec == PREC_F32 ? 4 : prec == PREC_BF16 ? 2 : 1; }
 // bytes of the staged weight copy Jc (FP32 mode stages FP32 values as FP64)
 size_t jc_bytes(int prec) { return prec == PREC_F32 ? 8 : in_bytes(prec); }
+// bytes of the context's Jc (two BF16 terms per weight in GLMR_BF16_J2)
+size_t jc_size(const glmr_ctx* c) { return (size_t)c->Np * c->Np * jc_bytes(c->prec) * (c->j2 ? 2 : 1); }
+// the public precision code of a context
+int32_t public_precision(const glmr_ctx* c) { return c->j2 ? GLMR_BF16_J2 : c->prec; }
 
 // ---------------------------------------------------------------- kernel caches
 // Whether the BF16 trace is kept in HBM (see glmr_trace_mode).
@@ -315,12 +356,13 @@ EvSlots ev_slots(const glmr_ctx* c) {
 // Per-slot tables of the event grid for the current tau.  A run of 64 slots
 // longer than kMaxSpan tau would overflow e^{(t - t_k0)/tau}.
 constexpr double kMaxSpan = 600.0;
-glmr_status build_ev_tables(glmr_ctx* c) {
+glmr_status build_ev_tables(glmr_ctx* c, Arena* ar) {
   const int64_t n = c->NS * 64;
-  if (!c->evtab) TRY(dalloc(c, c->evtab, (size_t)(5 * n + c->NS)));
+  TRY(persist(c, ar, c->evtab, (size_t)(5 * n + c->NS)));
   unsigned long long* ms = nullptr;
-  TRY(dalloc(c, ms, 1));
-  HIPCHK(c, hipMemsetAsync(ms, 0, sizeof(unsigned long long), c->st));
+  TRY(temp_alloc(c, ar, ms, 1));
+  if (ar) HIPCHK(c, launch_fill_i32((int32_t*)ms, 2, 0, c->st));  // the static scratch keeps old contents
+  else HIPCHK(c, hipMemsetAsync(ms, 0, sizeof(unsigned long long), c->st));
   EvTableArgs ta{};
   ta.tslot = c->tslot;
   ta.tau = c->tau;
@@ -332,9 +374,9 @@ glmr_status build_ev_tables(glmr_ctx* c) {
   ta.edec = c->evtab + 4 * n;
   ta.asub = c->evtab + 5 * n;
   if (c->prec == PREC_BF16) {
-    if (!c->evgl) TRY(dalloc(c, c->evgl, (size_t)(16 * n)));
+    TRY(persist(c, ar, c->evgl, (size_t)(16 * n)));
     ta.gl = c->evgl;
-  } else {
+  } else if (!ar) {
     dfree(c, c->evgl);
   }
   ta.maxspan = ms;
@@ -342,7 +384,7 @@ glmr_status build_ev_tables(glmr_ctx* c) {
   unsigned long long h = 0;
   HIPCHK(c, hipMemcpyAsync(&h, ms, sizeof h, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  dfree(c, ms);
+  temp_free(c, ar, ms);
   double span = 0;
   std::memcpy(&span, &h, sizeof span);
   c->max_span = span;
@@ -354,7 +396,7 @@ glmr_status build_ev_tables(glmr_ctx* c) {
 
 bool want_resident(glmr_ctx* c) {
   if (c->evm && c->prec != PREC_BF16) return false;  // the event grid's resident trace is BF16
-  if (c->prec == PREC_FP8) return true;  // FP8 contractions exist only on the resident trace
+  if (c->prec == PREC_FP8 || c->j2) return true;  // FP8 and two-term J contractions exist only on it
   if (c->prec != PREC_BF16 || c->cfg.trace == GLMR_TRACE_RECOMPUTE) return false;
   if (c->cfg.trace == GLMR_TRACE_RESIDENT) return true;
   size_t fr = 0, tot = 0;
@@ -367,21 +409,25 @@ bool want_resident(glmr_ctx* c) {
 }
 
 // Build (or drop) the resident trace for the current tau; needs C64 and tab.
-glmr_status build_resident_trace(glmr_ctx* c) {
-  c->resident = want_resident(c);
+// With an arena (no allocation) the earlier decision and buffers are kept.
+glmr_status build_resident_trace(glmr_ctx* c, Arena* ar) {
+  if (!ar) c->resident = want_resident(c);
   if (!c->resident) {
-    dfree(c, c->Xtj);
-    dfree(c, c->Xjt);
+    if (!ar) {
+      dfree(c, c->Xtj);
+      dfree(c, c->Xjt);
+    }
     return GLMR_OK;
   }
   const bool f8 = c->prec == PREC_FP8;
   const size_t n = (size_t)c->Bp * c->Np * (f8 ? 1 : 2);
   if (c->x_bytes != n) {
+    if (ar) return fail(c, GLMR_ESTATE, "the resident trace was built for another precision: call glmr_set_kernel");
     dfree(c, c->Xtj);
     dfree(c, c->Xjt);
   }
-  if (!c->Xtj) TRY(dalloc(c, c->Xtj, n));
-  if (!c->Xjt) TRY(dalloc(c, c->Xjt, n));
+  TRY(persist(c, ar, c->Xtj, n));
+  TRY(persist(c, ar, c->Xjt, n));
   c->x_bytes = n;
   ResXArgs xa{};
   xa.C64 = c->C64;
@@ -396,9 +442,16 @@ glmr_status build_resident_trace(glmr_ctx* c) {
   xa.ev = ev_slots(c);
   if (f8) {
     const int64_t nchunks = (c->Bp + c->L - 1) / c->L;
-    TRY(dalloc(c, c->xmax, (size_t)nchunks));
-    TRY(dalloc(c, c->xscale, (size_t)nchunks));
-    HIPCHK(c, hipMemsetAsync(c->xmax, 0, (size_t)nchunks * sizeof(unsigned), c->st));
+    if (ar) {
+      if (!c->xmax || !c->xscale || c->x_nchunks != nchunks)
+        return fail(c, GLMR_ESTATE, "the FP8 trace scales do not exist for this chunking: call glmr_set_kernel");
+      HIPCHK(c, launch_fill_i32((int32_t*)c->xmax, (int)nchunks, 0, c->st));
+    } else {
+      TRY(dalloc(c, c->xmax, (size_t)nchunks));
+      TRY(dalloc(c, c->xscale, (size_t)nchunks));
+      c->x_nchunks = nchunks;
+      HIPCHK(c, hipMemsetAsync(c->xmax, 0, (size_t)nchunks * sizeof(unsigned), c->st));
+    }
     xa.L = c->L;
     xa.xmax = c->xmax;
     xa.xscale = c->xscale;
@@ -411,12 +464,15 @@ glmr_status build_resident_trace(glmr_ctx* c) {
   return GLMR_OK;
 }
 
-glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
+// The per-tau caches: carries, resident trace, spike term.  ar != nullptr:
+// the temporaries come from the static scratch and nothing is allocated (the
+// spike term then takes as many time splits as the scratch holds).
+glmr_status build_kernel_caches(glmr_ctx* c, bool want_y, Arena* ar = nullptr) {
   const double dt = c->dt, tau = c->tau;
   c->have_kernel = false;
   if (c->evm) {
     want_y = false;
-    TRY(build_ev_tables(c));
+    TRY(build_ev_tables(c, ar));
   }
   Tables h{};
   for (int m = 0; m < 64; ++m) {
@@ -426,20 +482,20 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
     h.ainv32[m] = (float)h.ainv[m];
   }
   for (int k = 0; k <= 64; ++k) h.apow[k] = std::exp(-64.0 * (double)k * dt / tau);
-  if (!c->tab) TRY(dalloc(c, c->tab, 1));
+  TRY(persist(c, ar, c->tab, 1));
   HIPCHK(c, hipMemcpyAsync(c->tab, &h, sizeof(Tables), hipMemcpyHostToDevice, c->st));
 
   const size_t nc = (size_t)c->NS * c->Np;
-  if (!c->C64) TRY(dalloc(c, c->C64, nc));
-  if (want_y && !c->CY64) TRY(dalloc(c, c->CY64, nc));
+  TRY(persist(c, ar, c->C64, nc));
+  if (want_y) TRY(persist(c, ar, c->CY64, nc));
   const bool need32 = c->prec == PREC_BF16 || c->prec == PREC_FP8;
-  if (need32 && !c->C32) TRY(dalloc(c, c->C32, nc));
-  if (need32 && want_y && !c->CY32) TRY(dalloc(c, c->CY32, nc));
+  if (need32) TRY(persist(c, ar, c->C32, nc));
+  if (need32 && want_y) TRY(persist(c, ar, c->CY32, nc));
   const int64_t G = 64;
   const int64_t nseg = (c->NS + G - 1) / G;
   double *seg = nullptr, *segin = nullptr;
-  TRY(dalloc(c, seg, (size_t)nseg * c->Np * 2));
-  TRY(dalloc(c, segin, (size_t)nseg * c->Np * 2));
+  TRY(temp_alloc(c, ar, seg, (size_t)nseg * c->Np * 2));
+  TRY(temp_alloc(c, ar, segin, (size_t)nseg * c->Np * 2));
   CarryArgs ca{};
   ca.masks = c->masks;
   ca.planes = c->planes;
@@ -463,7 +519,7 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
   }
   if (self_delayed(c)) {
     // the recorded raster's own trace, for the self-connection's delay
-    if (!c->C0) TRY(dalloc(c, c->C0, nc));
+    TRY(persist(c, ar, c->C0, nc));
     CarryArgs c0 = ca;
     c0.masks = c->masks0;
     c0.want_y = 0;
@@ -474,18 +530,22 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
     ProfScope ps(c, K_CARRY);
     HIPCHK(c, launch_carries(c0, c->st));
   }
-  TRY(build_resident_trace(c));
+  TRY(build_resident_trace(c, ar));
 
   // spike term dSigma (and dSigmaY)
   const int64_t nij = c->Np * c->Np;
-  if (!c->dsig) TRY(dalloc(c, c->dsig, (size_t)nij));
-  if (want_y && !c->dsigY) TRY(dalloc(c, c->dsigY, (size_t)nij));
+  TRY(persist(c, ar, c->dsig, (size_t)nij));
+  if (want_y) TRY(persist(c, ar, c->dsigY, (size_t)nij));
   int64_t pairs = c->NIB * c->NIB;
   int splits = (int)std::max<int64_t>(1, std::min<int64_t>((8192 + pairs - 1) / pairs, c->NS));
-  // bound the partial buffer to ~512 MB
-  while (splits > 1 && (size_t)splits * nij * 8 * (want_y ? 2 : 1) > (512ull << 20)) splits /= 2;
+  // bound the partial buffer to ~512 MB (with the static scratch, to what it has left)
+  const size_t part_cap = ar ? (ar->cap > ar->used + 256 ? ar->cap - ar->used - 256 : 0) : (512ull << 20);
+  while (splits > 1 && (size_t)splits * nij * 8 * (want_y ? 2 : 1) > part_cap) splits /= 2;
   double* part = nullptr;
-  TRY(dalloc(c, part, (size_t)splits * nij * (want_y ? 2 : 1)));
+  // the self-delay correction reuses it for 64 time splits of Np sums
+  const size_t part_n = std::max<size_t>((size_t)splits * nij * (want_y ? 2 : 1),
+                                         self_delayed(c) ? 64 * (size_t)c->Np : 0);
+  TRY(temp_alloc(c, ar, part, part_n));
   SpikeTermArgs sa{};
   sa.masks = c->masks;
   sa.planes = c->planes;
@@ -522,9 +582,9 @@ glmr_status build_kernel_caches(glmr_ctx* c, bool want_y) {
     HIPCHK(c, launch_self_spike(ss, c->st));
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
-  dfree(c, part);
-  dfree(c, seg);
-  dfree(c, segin);
+  temp_free(c, ar, part);
+  temp_free(c, ar, seg);
+  temp_free(c, ar, segin);
   c->have_kernel = true;
   c->have_y = want_y;
   return GLMR_OK;
@@ -609,6 +669,7 @@ ResUArgs make_u_args(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
   const ResShape su = res_shape(k);
   ResUArgs ua{};
   ua.Jc = c->Jc;
+  ua.j2 = c->j2 ? 1 : 0;
   ua.Xtj = c->Xtj;
   ua.Np = c->Np;
   ua.B = c->B;
@@ -688,6 +749,8 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
     if (c->resident) {
       ProfScope ps(c, K_U);
       HIPCHK(c, launch_u_chunk(c, c->res_shape_u, t0, Lc));
+    } else if (c->j2) {
+      return fail(c, GLMR_EINVAL, "the two-term J runs on the resident trace only");
     } else {
       ProfScope ps(c, K_U);
       HIPCHK(c, launch_gemm1(c->prec, c->tile, g1, c->st));
@@ -788,7 +851,7 @@ glmr_status eval_finish(glmr_ctx* c, bool want_grad, bool want_tau) {
 glmr_status prepare_params(glmr_ctx* c) {
   ProfScope ps(c, K_PREP);
   if (c->prec == PREC_FP8 && !c->jscale) TRY(dalloc(c, c->jscale, (size_t)c->Np));
-  HIPCHK(c, launch_prepare_params(c->prec, c->N, c->Np, c->J64, c->mu, c->Jc, c->Jr, c->rowscale,
+  HIPCHK(c, launch_prepare_params(c->prec, c->j2 ? 1 : 0, c->N, c->Np, c->J64, c->mu, c->Jc, c->Jr, c->rowscale,
                                   c->prec == PREC_FP8 ? c->jscale : nullptr, c->st));
   return GLMR_OK;
 }
@@ -944,8 +1007,12 @@ struct GraphRun {
   }
 };
 
-double default_ftol(int prec) {
-  switch (prec) {
+// the stopping threshold of a mode: below its rounding noise in L, eta cannot
+// fall.  The two-term J removes BF16's J steps; L's own noise (FP32 exp and
+// potentials summed in FP64) is ~1e-10 relative.
+double default_ftol(const glmr_ctx* c) {
+  if (c->j2) return 1e-10;
+  switch (c->prec) {
     case PREC_F64: return 1e-14;
     case PREC_F32: return 1e-11;
     case PREC_BF16: return 1e-6;
@@ -1037,7 +1104,7 @@ glmr_status fit_one(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_report* rep
   HIPCHK(c, hipSetDevice(c->cfg.device));
   auto t_start = std::chrono::steady_clock::now();
   AscentArgs& a = c->asc;
-  const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c->prec);
+  const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c);
   int evals = 0, iters = 0;
   if (o.resume) {
     // every step ends with the next directions in place: carry on from there.
@@ -1399,7 +1466,7 @@ glmr_status glmr_get_state(glmr_ctx* c, void* buf, size_t* len) {
   h.tau = c->tau;
   h.d = c->dly;
   h.d_self = c->dly_s;
-  h.precision = c->prec;
+  h.precision = public_precision(c);
   h.m = m;
   h.spikes_fp = spikes_fingerprint(c);
   h.alpha = c->asc.alpha;
@@ -1472,7 +1539,8 @@ glmr_status glmr_batch_create(glmr_ctx* const* ctxs, int32_t n, glmr_batch** out
   if (!ctxs || n < 1) return GLMR_EINVAL;
   for (int r = 0; r < n; ++r) {
     if (!ctxs[r]) return GLMR_EINVAL;
-    if (ctxs[r]->cfg.device != ctxs[0]->cfg.device || ctxs[r]->prec != ctxs[0]->prec) return GLMR_EINVAL;
+    if (ctxs[r]->cfg.device != ctxs[0]->cfg.device || public_precision(ctxs[r]) != public_precision(ctxs[0]))
+      return GLMR_EINVAL;
     for (int q = 0; q < r; ++q)
       if (ctxs[q] == ctxs[r]) return GLMR_EINVAL;  // each recording once
   }
@@ -1510,7 +1578,7 @@ glmr_status batch_prepare(glmr_batch* b) {
   for (glmr_ctx* c : b->ctxs) {
     // the grouped launches take one precision for all (a context may have
     // been switched since the batch was made)
-    if (c->prec != b->ctxs[0]->prec)
+    if (public_precision(c) != public_precision(b->ctxs[0]))
       return fail(c, GLMR_ESTATE, "the batch's recordings no longer share one precision");
     TRY(check_ready(c));
     grouped = grouped && c->resident && !self_delayed(c) && !c->evm;
@@ -1684,7 +1752,7 @@ glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* o_in, glmr_fit_re
   OnBatchStream on(b);
   for (glmr_ctx* c : b->ctxs) TRY(fit_begin(c, o));
   TRY(batch_prepare(b));
-  const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c0->prec);
+  const double ftol = o.ftol > 0 ? o.ftol : default_ftol(c0);
   TRY(batch_eval_theta(b, false));
   for (glmr_ctx* c : b->ctxs) HIPCHK(c, launch_lbfgs_direction(c->asc, 1, b->st));
   // one ascent step of every recording, captured once and replayed
@@ -1774,11 +1842,11 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
   *out = nullptr;
   if (!cfg) return GLMR_EINVAL;
   if (cfg->n_neurons < 1 || cfg->n_neurons > 65536 || cfg->n_bins < 1 || !(cfg->dt > 0) ||
-      !std::isfinite(cfg->dt) || cfg->chunk_bins < 0 || cfg->precision < 0 || cfg->precision > 3 ||
+      !std::isfinite(cfg->dt) || cfg->chunk_bins < 0 || cfg->precision < 0 || cfg->precision > 4 ||
       !(cfg->tile_n == 0 || cfg->tile_n == 128 || cfg->tile_n == 256) || cfg->trace < 0 || cfg->trace > 2)
     return GLMR_EINVAL;
-  if (cfg->precision == GLMR_FP8 && cfg->trace == GLMR_TRACE_RECOMPUTE)
-    return GLMR_EINVAL;  // FP8 contractions exist only on the resident trace
+  if ((cfg->precision == GLMR_FP8 || cfg->precision == GLMR_BF16_J2) && cfg->trace == GLMR_TRACE_RECOMPUTE)
+    return GLMR_EINVAL;  // FP8 and two-term J contractions exist only on the resident trace
   if (cfg->time_mode != GLMR_TIME_GRID && cfg->time_mode != GLMR_TIME_EVENTS) return GLMR_EINVAL;
   if (cfg->time_mode == GLMR_TIME_EVENTS && cfg->precision == GLMR_FP8)
     return GLMR_EINVAL;  // the event grid's contractions run in FP64, FP32 or BF16
@@ -1795,7 +1863,8 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
   c->B = cfg->n_bins;
   c->dt = cfg->dt;
   c->evm = cfg->time_mode == GLMR_TIME_EVENTS;
-  c->prec = cfg->precision;
+  c->j2 = cfg->precision == GLMR_BF16_J2;
+  c->prec = c->j2 ? GLMR_BF16 : cfg->precision;
   int tile = cfg->tile_n;
   if (tile == 0) tile = ((c->prec == GLMR_BF16 || c->prec == GLMR_FP8) && c->N <= 384) ? 128 : 256;
   c->Np = rup(c->N, tile);
@@ -1896,8 +1965,8 @@ glmr_status ingest_pairs(glmr_ctx* c, const int64_t* bin, const int32_t* neuron,
   HIPCHK(c, launch_ingest_masks(b, c->masks, c->planes, c->Np, c->st));
   // digest of the recorded raster (before any delay shifts it), for checkpoints
   HIPCHK(c, hipMemsetAsync(bad, 0, 2 * sizeof(unsigned long long), c->st));
-  HIPCHK(c, launch_digest_u64(c->masks, (int64_t)nm, bad, c->st));
-  if (c->evm) HIPCHK(c, launch_digest_u64((const uint64_t*)c->tslot, c->NS * 64 + 1, bad + 1, c->st));
+  HIPCHK(c, launch_digest_u64(c->masks, (int64_t)c->planes * c->NS, c->NS, c->Np, c->N, bad, c->st));
+  if (c->evm) HIPCHK(c, launch_digest_u64((const uint64_t*)c->tslot, 1, 1, 0, c->B + 1, bad + 1, c->st));
   unsigned long long dig[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(dig, bad, sizeof dig, hipMemcpyDeviceToHost, c->st));
   c->q_host.assign(c->Np, 0);
@@ -2103,7 +2172,7 @@ glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int3
     TRY(dalloc(c, c->mu, (size_t)Np));
     HIPCHK(c, hipMemsetAsync(c->mu, 0, Np * sizeof(double), c->st));
     void* p = nullptr;
-    TRY(dalloc(c, (unsigned char*&)p, (size_t)Np * Np * jc_bytes(c->prec)));
+    TRY(dalloc(c, (unsigned char*&)p, jc_size(c)));
     c->Jc = p;
     TRY(dalloc(c, c->Jr, (size_t)Np * Np));
     TRY(dalloc(c, c->rowscale, (size_t)Np));
@@ -2120,18 +2189,38 @@ glmr_status glmr_set_params(glmr_ctx* c, const double* J, const double* mu, int3
 glmr_status glmr_set_precision(glmr_ctx* c, int32_t precision) {
   if (!c) return GLMR_EINVAL;
   c->err.clear();
-  if (precision < 0 || precision > 3) return fail(c, GLMR_EINVAL, "precision must be FP64, FP32, BF16 or FP8");
-  if (precision == GLMR_FP8 && c->cfg.trace == GLMR_TRACE_RECOMPUTE)
-    return fail(c, GLMR_EINVAL, "FP8 needs the resident trace");
+  if (precision < 0 || precision > 4)
+    return fail(c, GLMR_EINVAL, "precision must be FP64, FP32, BF16, FP8 or BF16 with a two-term J");
+  if ((precision == GLMR_FP8 || precision == GLMR_BF16_J2) && c->cfg.trace == GLMR_TRACE_RECOMPUTE)
+    return fail(c, GLMR_EINVAL, "FP8 and the two-term J need the resident trace");
   TRY(reject_event_grid_precision(c, precision));
   if (precision == GLMR_FP8 && c->dly != c->dly_s)
     return fail(c, GLMR_EINVAL, "a self-delay other than d needs FP64, FP32 or BF16");
-  if (precision == c->prec) return GLMR_OK;
+  const bool j2 = precision == GLMR_BF16_J2;
+  const int prec = j2 ? GLMR_BF16 : precision;
+  if (prec == c->prec && j2 == c->j2) return GLMR_OK;
   HIPCHK(c, hipSetDevice(c->cfg.device));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->asc_live = false;
-  c->prec = precision;
   c->cfg.precision = precision;
+  if (prec == c->prec) {
+    // BF16 <-> BF16 with a two-term J: the same trace and workspace, only the
+    // staged weights change (the two-term J needs the trace resident)
+    c->j2 = j2;
+    if (c->Jc) {
+      unsigned char* jc = (unsigned char*)c->Jc;
+      dfree(c, jc);
+      void* p = nullptr;
+      TRY(dalloc(c, (unsigned char*&)p, jc_size(c)));
+      c->Jc = p;
+    }
+    if (j2 && c->have_kernel && !c->resident) TRY(build_kernel_caches(c, c->have_y));
+    if (c->have_params) TRY(prepare_params(c));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return GLMR_OK;
+  }
+  c->j2 = j2;
+  c->prec = prec;
   setup_precision(c);
   // buffers whose size or element type depend on the precision
   unsigned char* w = (unsigned char*)c->W;
@@ -2147,7 +2236,7 @@ glmr_status glmr_set_precision(glmr_ctx* c, int32_t precision) {
     unsigned char* jc = (unsigned char*)c->Jc;
     dfree(c, jc);
     void* p = nullptr;
-    TRY(dalloc(c, (unsigned char*&)p, (size_t)c->Np * c->Np * jc_bytes(c->prec)));
+    TRY(dalloc(c, (unsigned char*&)p, jc_size(c)));
     c->Jc = p;
   }
   if (c->have_kernel) TRY(build_kernel_caches(c, c->have_y));
@@ -2180,6 +2269,8 @@ glmr_status glmr_eval(glmr_ctx* c, double* ll, double* ll_rows, double* grad_J, 
   HIPCHK(c, hipSetDevice(c->cfg.device));
   const bool want_grad = grad_J || grad_mu;
   const bool want_tau = grad_tau != nullptr;
+  if (want_tau && c->j2)
+    return fail(c, GLMR_EINVAL, "dL/dtau is not available with the two-term J (use GLMR_BF16)");
   if (want_tau && c->prec == PREC_FP8)
     return fail(c, GLMR_EINVAL, "dL/dtau is evaluated in FP64, FP32 or BF16, not FP8");
   if (want_tau && c->evm) return fail(c, GLMR_EINVAL, "dL/dtau is not available on the event grid");

@@ -12,8 +12,9 @@ evaluates the likelihood of the parameters rounded to it):
         error of L comes from rounding x to FP32 (stochastically, so it is
         random in sign) and its relative size falls as 1/sqrt(B N); on the
         tiny cases here (B N ~ 1e5-1e6) the bound is 1e-10 sqrt(2e6/(B N)).
-        A row averages B terms instead of B N, so L_i's bound is sqrt(N)
-        times that.  The gradient contraction takes the same FP32-rounded
+        A row averages B terms instead of B N, so a row's error is about
+        sqrt(N) times that, and the largest of N such random errors about
+        four times its spread: L_i's bound is 4 sqrt(N) times L's.  The gradient contraction takes the same FP32-rounded
         operands widened to FP64 and accumulates in FP64, so the gradient
         error is the trace rounding alone (measured <= 6e-9): bound 1e-6,
         2-norm and element-wise.
@@ -61,7 +62,7 @@ def tol_for(prec, rec):
     t = dict(TOL[prec])
     if prec == "fp32":
         t["ll"] = ll_tol(prec, rec)
-        t["row"] = t["ll"] * rec.n_neurons ** 0.5
+        t["row"] = 4.0 * t["ll"] * rec.n_neurons ** 0.5
     return t
 
 
@@ -270,7 +271,9 @@ def test_empty_raster():
     assert np.allclose(got["gJ"], 0.0)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("bf16", 1e-2), ("bf16-rc", 1e-2)])
+# dL/dtau is a component of the gradient: BF16 takes the gradient's bound
+# (measured 1.3e-5 and 1.9e-5)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("bf16", 1e-3), ("bf16-rc", 1e-3)])
 def test_tau_gradient(prec, tol):
     rec = synth.balanced(N=40, B=6000, tau=0.008, seed=8)
     J, mu = theta_for(rec, prec, seed=2)
@@ -284,7 +287,7 @@ def test_tau_gradient(prec, tol):
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16-rc"])
 def test_tau_gradient_many_tiles_and_chunks(prec):
-    # N = 300 pads to 512 (several neuron tiles, i0 > 0) and chunk_bins = 4096
+    # N = 300 pads to 384 (three 128-neuron tiles, i0 > 0) and chunk_bins = 4096
     # splits the 30016 padded bins into seven full chunks and a short last one:
     # the tile-major weights that the resident trace's dL/dtau contraction
     # reads are addressed at every tile and chunk offset
@@ -293,11 +296,11 @@ def test_tau_gradient_many_tiles_and_chunks(prec):
     tau = 0.011
     ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, tau, J, mu, want_tau=True)
     got = run_gpu(rec, J, mu, prec, tau=tau, want_tau=True, chunk_bins=4096)
-    assert got["query"]["chunk_bins"] == 4096 and got["query"]["n_pad"] == 512
+    assert got["query"]["chunk_bins"] == 4096 and got["query"]["n_pad"] == 384
     r = abs(got["gtau"] - ref["gtau"]) / abs(ref["gtau"])
     print(f"[tau tiles {prec}] gtau={got['gtau']:.8e} ref={ref['gtau']:.8e} rel={r:.2e}", flush=True)
     report(f"tau tiles {prec}", got, ref, tol_for(prec, rec))
-    assert r <= 1e-2
+    assert r <= 1e-3
 
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16-rc", "fp8"])
@@ -356,3 +359,58 @@ def test_n1000_parity(prec, where):
     ref = O.loglik(rec.bins, rec.neurons, N, rec.n_bins, rec.dt, rec.tau, J, mu)
     got = run_gpu(rec, J, mu, prec)
     report(f"n1000 {where} {prec}", got, ref, tol_for(prec, rec))
+
+
+def _bf16_rne(x):
+    """Round to BF16 through FP32, both to nearest even (as the library stages J)."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def two_term_j(J):
+    """J as GLMR_BF16_J2 represents it: bf16(J) + bf16(J - bf16(J))."""
+    hi = _bf16_rne(J)
+    return hi + _bf16_rne(J - hi)
+
+
+@pytest.mark.parametrize("case", ["small", "chunks", "n1000"])
+def test_bf16_two_term_j(case):
+    """BF16 with J as two BF16 terms: the BF16 bounds against the oracle at the
+    two-term value of J, which is within ~1e-5 relative of J itself (so the
+    oracle at the unrounded J gives almost the same errors), while BF16's
+    one-term J is 4e-3 steps away."""
+    G = _G()
+    if case == "small":
+        rec, kw = small_rec(), {}
+    elif case == "chunks":
+        rec, kw = synth.balanced(N=70, B=20_000, seed=5), dict(chunk_bins=4096)
+    else:
+        rec, kw = big_rec(), {}
+    rng = np.random.default_rng(9)
+    J = rec.J + rng.normal(0, 0.05, rec.J.shape)  # not representable in BF16
+    J2 = two_term_j(J)
+    assert np.abs(J2 - J).max() <= 2.0 ** -16 * np.abs(J).max()
+    ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, J2, rec.mu)
+    ctx = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision="bf16j2", **kw)
+    ctx.set_spikes(rec.bins, rec.neurons)
+    ctx.set_kernel(rec.tau)
+    ctx.set_params(J, rec.mu)
+    got = ctx.eval(grad=True)
+    assert ctx.query()["trace_resident"]
+    with pytest.raises(G.GlmrError):
+        ctx.eval(want_tau=True)
+    # switching to one-term BF16 and back keeps the trace; the one-term
+    # likelihood is that of bf16(J)
+    ctx.set_precision("bf16")
+    one = ctx.eval(grad=True)
+    ctx.set_precision("bf16j2")
+    again = ctx.eval(grad=True)
+    ctx.close()
+    report(f"two-term J {case}", got, ref, TOL["bf16"])
+    assert again["ll"] == got["ll"] and np.array_equal(again["gJ"], got["gJ"])
+    ref1 = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, _bf16_rne(J), rec.mu,
+                    want_grad=False)
+    report(f"one-term J after the switch {case}", dict(ll=one["ll"], ll_rows=one["ll_rows"]), ref1,
+           TOL["bf16"])
