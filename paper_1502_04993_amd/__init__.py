@@ -376,8 +376,9 @@ class Context:
     def fit(self, max_iter=500, ftol=0.0, lbfgs_m=40, max_backtracks=30, warm_start_mu=False,
             from_zero=False, polish=None, polish_iter=200, l1_alpha=0.0, l1_eps=0.0, j_max=0.0,
             rate_min=0.0, rate_max=0.0, resume=False):
-        """Per-row L-BFGS ascent.  polish="fp32" finishes a BF16 ascent with FP32
-        evaluations from the BF16 optimum (then switches back).  l1_alpha /
+        """Per-row L-BFGS ascent.  polish="bf16j2" (BF16 with a two-term J, the
+        trace kept) or "fp32" continues a BF16 ascent from the BF16 optimum to
+        the exact one (then switches back).  l1_alpha /
         l1_eps: the smooth epsilon-l1 penalty; j_max, rate_min, rate_max: bounds.
         resume=True continues the ascent the context holds (an earlier fit's, or
         one restored by set_state)."""
