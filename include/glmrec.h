@@ -189,6 +189,27 @@ void glmr_ei_interval_f32(float D, double delta, float* F, float* H);
  * only be computed once). */
 glmr_status glmr_set_kernel(glmr_ctx* ctx, double tau);
 
+/* glmr_set_kernel for callers that cannot allocate device memory (code that
+ * runs under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same per-tau set-up and the same results up to the
+ * rounding order of the spike term's FP64 sums (it may take fewer time
+ * splits), with no hipMalloc, hipFree or allocating library call: the
+ * carries' segment sums, the spike term's partials and the event grid's span
+ * maximum live in a static device array of 256 MiB (the library holds one on
+ * each GPU it runs on, until the process ends); the buffers that persist in
+ * the context (carries, resident trace, spike term, tables) are reused.
+ * Call glmr_set_kernel once on the context first (at set-up, where
+ * allocation is allowed): GLMR_ESTATE if those buffers do not exist, or were
+ * made for another precision or chunking.  GLMR_EINVAL for tau as in
+ * glmr_set_kernel, and when the recording's set-up needs more than the
+ * static array (2 x ceil(n_bins / 4096) x n_pad x 16 bytes plus n_pad^2 x 8
+ * bytes, twice that for the dL/dtau caches); nothing is changed then.  Every
+ * call on a GPU uses that GPU's one array: calls on one GPU that overlap in
+ * time (from several threads) race and must not be made; each call
+ * synchronises the context's stream before it returns, so calls made one
+ * after the other are safe. */
+glmr_status glmr_set_kernel_noalloc(glmr_ctx* ctx, double tau);
+
 /* Transmission delays of Sec. 2.4, Eq. (15), on the regular grid, in bins:
  * every connection j -> i with j != i delays by d, the self-connection
  * i -> i by d_self, 0 <= d, d_self < n_bins.  Row i then sees

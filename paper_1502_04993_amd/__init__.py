@@ -21,7 +21,7 @@ from ._lib import (GLMR_BF16, GLMR_DEVICE, GLMR_FP8, GLMR_FP32, GLMR_FP64, GLMR_
 __all__ = ["Context", "Batch", "GlmrError", "glmr_create", "glmr_destroy", "glmr_set_spikes",
            "glmr_event_slots", "glmr_set_spike_times", "glmr_ei_interval", "glmr_ei_interval_f32", "glmr_set_delays",
            "glmr_get_state", "glmr_set_state",
-           "glmr_set_kernel", "glmr_set_precision", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
+           "glmr_set_kernel", "glmr_set_kernel_noalloc", "glmr_set_precision", "glmr_set_params", "glmr_get_params", "glmr_eval", "glmr_fit",
            "glmr_fit_defaults", "glmr_status_string", "glmr_last_error", "glmr_query",
            "glmr_batch_create", "glmr_batch_destroy", "glmr_batch_eval", "glmr_batch_get_grad",
            "glmr_batch_fit", "glmr_prof_enable", "glmr_prof_get", "glmr_prof_reset"]
@@ -129,6 +129,10 @@ def glmr_set_delays(ctx, d_bins, d_self_bins):
 
 def glmr_set_kernel(ctx, tau):
     return _check(L.load().glmr_set_kernel(ctx, float(tau)), ctx)
+
+
+def glmr_set_kernel_noalloc(ctx, tau):
+    return _check(L.load().glmr_set_kernel_noalloc(ctx, float(tau)), ctx)
 
 
 def glmr_set_precision(ctx, precision):
@@ -347,6 +351,12 @@ class Context:
 
     def set_kernel(self, tau: float):
         return glmr_set_kernel(self._c, tau)
+
+    def set_kernel_noalloc(self, tau: float):
+        """set_kernel without device allocation (the library's static scratch);
+        needs one set_kernel on this context first."""
+        return glmr_set_kernel_noalloc(self._c, tau)
+
     def set_delays(self, d_bins: int, d_self_bins: int):
         """Transmission delays in bins: d on every connection j -> i (j != i),
         d_self on the self-connection (Sec. 2.4, Eq. (15))."""

@@ -68,6 +68,7 @@ SIGNATURES = {
     "glmr_ei_interval_f32": (None, [ctypes.c_float, ctypes.c_double, ctypes.POINTER(ctypes.c_float),
                                     ctypes.POINTER(ctypes.c_float)]),
     "glmr_set_kernel": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "glmr_set_kernel_noalloc": (ctypes.c_int, [_vp, ctypes.c_double]),
     "glmr_get_state": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),
     "glmr_set_state": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "glmr_set_delays": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64]),

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -156,6 +157,15 @@ struct glmr_ctx {
   int64_t prof_n[K_NKIND] = {};
 };
 
+// Static scratch of the no-allocation entry point (glmr_set_kernel_noalloc):
+// kScratchBytes on every device the library runs a kernel on, held until the
+// process ends.  In host code `scratch` names a host-side stand-in; its device
+// address comes from hipGetSymbolAddress, once per device (scratch_init), and
+// only that address is passed to kernels.  Every call on a device shares that
+// device's array and finds the previous call's contents in it.
+constexpr size_t kScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 glmr_status fail(glmr_ctx* c, glmr_status s, const char* fmt, ...) {
@@ -234,6 +244,27 @@ template <typename T>
 void temp_free(glmr_ctx* c, Arena* ar, T*& p) {
   if (ar) p = nullptr;
   else dfree(c, p);
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Resolve the device address of `scratch` on the current device (once).
+hipError_t scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_scratch_ptr[dev] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_err[dev] = e;
+    g_scratch_done[dev] = true;
+  }
+  return g_scratch_err[dev];
 }
 
 template <typename T>
@@ -1857,6 +1888,9 @@ glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
   }
   if (cfg->device < 0 || cfg->device >= ndev) return GLMR_EINVAL;
   if (hipSetDevice(cfg->device) != hipSuccess) return GLMR_EDEVICE;
+  // the static scratch's address on this device (used by glmr_set_kernel_noalloc;
+  // a failure here is reported by that call)
+  (void)scratch_init(cfg->device);
   glmr_ctx* c = new glmr_ctx();
   c->cfg = *cfg;
   c->N = cfg->n_neurons;
@@ -2136,6 +2170,39 @@ glmr_status glmr_set_kernel(glmr_ctx* c, double tau) {
   if (!c->have_spikes) return GLMR_OK;  // caches are built when the spikes arrive
   // once dL/dtau has been asked for, keep the tau-derivative caches current
   return build_kernel_caches(c, c->keep_y);
+}
+
+glmr_status glmr_set_kernel_noalloc(glmr_ctx* c, double tau) {
+  if (!c) return GLMR_EINVAL;
+  c->err.clear();
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(c, GLMR_EINVAL, "tau must be positive");
+  if (!c->evm && tau < c->dt) return fail(c, GLMR_EINVAL, "tau must be >= dt");
+  if (!c->have_spikes) return fail(c, GLMR_ESTATE, "set the spikes first");
+  if (!c->C64 || !c->dsig || !c->tab)
+    return fail(c, GLMR_ESTATE, "the per-tau buffers do not exist yet: call glmr_set_kernel once on this "
+                                "context before glmr_set_kernel_noalloc");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const hipError_t se = scratch_init(c->cfg.device);
+  if (se != hipSuccess)
+    return fail(c, GLMR_EDEVICE, "hipGetSymbolAddress of the static scratch: %s", hipGetErrorString(se));
+  // the fixed temporaries (carry segments, span maximum) and one time split
+  // of the spike term must fit
+  const int64_t nseg = (c->NS + 63) / 64;
+  const bool wy = c->keep_y && !c->evm;
+  const size_t need = 2 * ((size_t)nseg * c->Np * 2 * sizeof(double) + 256) + 512 +
+                      std::max<size_t>((size_t)c->Np * c->Np * sizeof(double) * (wy ? 2 : 1),
+                                       self_delayed(c) ? 64 * (size_t)c->Np * sizeof(double) : 0);
+  if (need > kScratchBytes)
+    return fail(c, GLMR_EINVAL, "this recording's per-tau set-up needs %zu bytes of scratch; the static "
+                                "scratch holds %zu (use glmr_set_kernel)", need, kScratchBytes);
+  c->asc_live = false;
+  c->tau = tau;
+  c->a = std::exp(-c->dt / tau);
+  c->have_kernel = false;
+  Arena ar;
+  ar.base = (unsigned char*)g_scratch_ptr[c->cfg.device];
+  ar.cap = kScratchBytes;
+  return build_kernel_caches(c, c->keep_y, &ar);
 }
 
 glmr_status glmr_set_delays(glmr_ctx* c, int64_t d, int64_t d_self) {
