@@ -392,15 +392,19 @@ void glmr_prof_reset(glmr_ctx* ctx);
 
 /* Layout facts of a context (for tests and the bench): padded neuron count,
  * padded bin count, chunk bins, spike planes, neuron tile, and whether the
- * trace is resident (1) or rebuilt inside the contractions (0).  Any pointer
- * may be NULL. */
+ * trace is resident in row-major layouts (1), resident with the trace and the
+ * weights stored as MFMA fragments (2: BF16 on the uniform grid, unless the
+ * environment sets GLMR_XFRAG=0 when the precision is set), or rebuilt inside
+ * the contractions (0).  Any pointer may be NULL. */
 glmr_status glmr_query(const glmr_ctx* ctx, int64_t* n_pad, int64_t* b_pad, int64_t* chunk_bins,
                        int32_t* planes, int32_t* tile_n, int32_t* trace_resident);
 
 /* Autotuner: times every tile shape the library offers for the two
- * contractions (kernel U: BI neurons x 256 bins; kernel G: BI x BI; several
- * wave grids) on this context's own data and parameters (first time chunk,
- * three launches each) and keeps the fastest pair for later evaluations.
+ * contractions that suits the context's trace layout (row-major: kernel U
+ * BI neurons x 256 bins, kernel G BI x BI, several wave grids; fragments: one
+ * kernel U of 128 neurons x 256 bins, kernel G of 128, 256 or 512 rows x 128)
+ * on this context's own data and parameters (first time chunk, three
+ * launches each) and keeps the fastest pair for later evaluations.
  * Applies to the resident BF16 trace; in other modes it changes nothing and
  * reports -1.  cache_path (nullable) is a text file of earlier results keyed
  * by GPU architecture, padded neuron count, chunk length and precision: a hit

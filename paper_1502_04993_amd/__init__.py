@@ -214,7 +214,7 @@ def glmr_query(ctx):
     _check(L.load().glmr_query(ctx, ctypes.byref(n_pad), ctypes.byref(b_pad), ctypes.byref(chunk),
                                ctypes.byref(planes), ctypes.byref(tile), ctypes.byref(resident)), ctx)
     return dict(n_pad=n_pad.value, b_pad=b_pad.value, chunk_bins=chunk.value, planes=planes.value,
-                tile_n=tile.value, trace_resident=bool(resident.value))
+                tile_n=tile.value, trace_resident=bool(resident.value), trace_frag=resident.value == 2)
 
 
 def glmr_autotune(ctx, cache_path=None):

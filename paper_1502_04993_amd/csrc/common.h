@@ -28,6 +28,20 @@
 
 #define GLMR_SUB 64   // bins per subtile (mask word)
 #define GLMR_TT 256   // bins per time tile of the likelihood kernel
+
+// Element (i, t) of a chunk's weights W (neuron i < Np, chunk-local bin t < L):
+//   layout 0  row-major [Np][L];
+//   layout 1  tile-major [L / 256][Np][256] (a 256-bin tile of all rows is one block);
+//   layout 2  MFMA fragments: the 32 x 16 block of neurons 32 ib .. and bins
+//             16 kb .. is the 1 KB starting at byte 1024 (ib (L / 16) + kb), in
+//             lane order (lane l holds neuron 32 ib + l % 32, bins 16 kb + 8 (l / 32) .. + 8).
+// The resident trace's Xtj uses layout 2 of [Bp][Np] in the same way (rows t,
+// columns j) when it is stored as fragments.
+__host__ __device__ inline int64_t w_elem(int layout, int64_t i, int64_t t, int64_t Np, int64_t L) {
+  if (layout == 1) return ((t >> 8) * Np + i) * 256 + (t & 255);
+  if (layout == 2) return ((((i >> 5) * (L >> 4) + (t >> 4)) * 64 + (i & 31) + 32 * ((t >> 3) & 1)) << 3) + (t & 7);
+  return i * L + t;
+}
 #define GLMR_IB 64    // neurons per spike-segment block
 
 typedef __attribute__((ext_vector_type(2))) double f64x2;
@@ -166,7 +180,7 @@ struct SelfDelayArgs {
   void* W;                   // [Np][L] weights of the chunk (kernel U's output)
   int wtype;                 // 0 double, 1 float, 2 bf16
   int scaled;                // 1: W holds lambda a^m (rebuilt-trace kernels), 0: lambda
-  int tiled;                 // 1: W is tile-major [L / 256][Np][256] (resident trace), 0: [Np][L]
+  int tiled;                 // W's layout (w_elem): 0 [Np][L], 1 tile-major, 2 fragments (resident trace)
   const double* Jr;          // [Np][Np] J as the contraction used it
   int64_t B, t0, L, Lc;      // bins, chunk start, W pitch, bins of the chunk
   int tb;                    // bins per row-sum tile of kernel U (128 or 256)
@@ -207,8 +221,8 @@ struct Gemm1Args {
   const float* xscale;     // FP8: per-chunk X scale (power of two); J row scale
   const float* jscale;
   int mode;                // 0: U -> W, 1: V = Y J^T -> sum W V
-  int w_plain;             // mode 1: W holds exp(V) (resident trace, tile-major [L / 256][Np][256])
-                           // instead of exp(V) a^m ([Np][L])
+  int w_plain;             // mode 1: W holds exp(V) in the resident trace's layout (w_elem's
+                           // layout 1 or 2) instead of exp(V) a^m ([Np][L]); 0 for the latter
   EvSlots ev;              // event grid (mode 0 only): W = H(D, delta) pw, row sums of F(D, delta)
   const float* evgl;       // event grid, BF16: [slots][16] per-slot table of the FP32 integrals
 };
@@ -239,8 +253,9 @@ struct ResXArgs {
   int planes;
   const Tables* tab;
   int64_t Np, NS, Bp;
-  void* Xtj;               // [Bp][Np] bf16 (FP8: e4m3 bytes)
+  void* Xtj;               // [Bp][Np] bf16 (FP8: e4m3 bytes); MFMA fragments when xfrag
   void* Xjt;               // [Np][Bp] bf16 (FP8: e4m3 bytes)
+  int xfrag;               // BF16: Xtj stored as 32 x 16 fragments (w_elem's layout 2 of [Bp][Np])
   int64_t L;               // FP8: bins per scaling chunk (the evaluation's time chunk)
   unsigned* xmax;          // FP8: [ceil(Bp / L)] chunk maxima (float bits), zero on entry
   float* xscale;           // FP8: [ceil(Bp / L)] power-of-two chunk scales
@@ -275,9 +290,12 @@ struct ResGArgs {
   const float* xscale;     // FP8: this chunk's trace scale (one value)
 };
 struct ResShape {
-  int bm;                  // neuron tile (kernel U: bm x 256 bins; kernel G: bm x bm)
-  int wgm, wgn;            // wave grid
+  int ui;                  // kernel U: neurons per tile (x 256 bins)
+  int gi, gj;              // kernel G: tile rows (i) x columns (j)
+  int wgm, wgn;            // wave grid of the row-major kernels
   int fp8_ok;              // usable for FP8 operands
+  int frag;                // the fragment-major kernels (trace and W as MFMA fragments, 4 waves)
+  int u_own;               // kernel U differs from that of every earlier shape with the same frag
 };
 const ResShape* res_shapes(int* n);
 // Work queue of a grouped (many-recording) launch: args[r] describes recording

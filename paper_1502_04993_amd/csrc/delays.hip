@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_self_delay(SelfDelayArgs a) {
     // above the FP32 exponential's error (the FP32 mode holds L to 1e-10)
     const double c = std::is_same<WT, __bf16>::value ? (double)expf((float)(jd * delta)) : exp(jd * delta);
     const int64_t tc = tl0 + tl;  // chunk-local bin
-    const int64_t k = a.tiled ? ((tc >> 8) * a.x.Np + i) * 256 + (tc & 255) : i * a.L + tc;
+    const int64_t k = w_elem(a.tiled, i, tc, a.x.Np, a.L);
     double lam;
     if (a.scaled) {  // the rebuild kernels store W a^m
       const double pw = a.x.tab->pw[tl & 63];

@@ -475,9 +475,9 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
 #pragma unroll
       for (int r = 0; r < P::NACC; ++r) {
         const int il = wm * WM + a * P::MB + P::row(r, lane);
-        // the resident kernel U stores W tile-major ([L / 256][Np][256])
+        // the resident kernel U stores W tile-major or as MFMA fragments
         const int64_t tc = tl0 + tl;
-        w_t* wp = g.w_plain ? W + ((tc >> 8) * g.Np + i0 + il) * 256 + (tc & 255) : W + (i0 + il) * g.L + tc;
+        w_t* wp = W + w_elem(g.w_plain, i0 + il, tc, g.Np, g.L);
         if (g.mode == 0) {
           auto lam = P::lam(pw * acc[a][b][r]);
           if (!valid) lam = 0;

@@ -111,15 +111,36 @@ __global__ __launch_bounds__(256) void k_build_x(ResXArgs g) {
     p = __builtin_amdgcn_cvt_sr_bf16_f32(p, x1, (uint32_t)(t + 1) * SR_T + rj, true);
     w[e / 2] = __builtin_bit_cast(uint32_t, p);
   }
-  // Xjt[j][64 s + m0 .. + 16]
-  i32x4* xr = (i32x4*)((__bf16*)g.Xjt + j * g.Bp + s * 64 + m0);
-  xr[0] = i32x4{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-  xr[1] = i32x4{(int)w[4], (int)w[5], (int)w[6], (int)w[7]};
+  if (g.xfrag) {
+    // Xjt as fragments of [Np][Bp]: bins 64 s + m0 .. + 16 of column j are
+    // lanes j % 32 (first 8 bins) and j % 32 + 32 of the fragment (j / 32,
+    // (64 s + m0) / 16); a wave's 64 columns fill two fragments
+    i32x4* xr = (i32x4*)g.Xjt + ((j >> 5) * (g.Bp / 16) + (s * 64 + m0) / 16) * 64 + (j & 31);
+    xr[0] = i32x4{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+    xr[32] = i32x4{(int)w[4], (int)w[5], (int)w[6], (int)w[7]};
+  } else {
+    // Xjt[j][64 s + m0 .. + 16]
+    i32x4* xr = (i32x4*)((__bf16*)g.Xjt + j * g.Bp + s * 64 + m0);
+    xr[0] = i32x4{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+    xr[1] = i32x4{(int)w[4], (int)w[5], (int)w[6], (int)w[7]};
+  }
   // Xtj through LDS
 #pragma unroll
   for (int e = 0; e < 16; ++e)
     *(uint16_t*)(tile + (m0 + e) * ROWB + jj * 2) = (uint16_t)(w[e / 2] >> (16 * (e & 1)));
   __syncthreads();
+  if (g.xfrag) {
+    // the 2 x 4 fragments of the 64 x 64 block, each 1 KB in lane order
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int piece = tid + q * 256, f = piece >> 6, ln = piece & 63;
+      const int tbl = f >> 2, kbl = f & 3;  // 32-bin and 16-column block within the block
+      const i32x4 v = *(const i32x4*)(tile + (tbl * 32 + (ln & 31)) * ROWB + (kbl * 16 + 8 * (ln >> 5)) * 2);
+      const int64_t frag = (s * 2 + tbl) * (g.Np / 16) + jb * 4 + kbl;
+      *(i32x4*)((unsigned char*)g.Xtj + (frag * 64 + ln) * 16) = v;
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int piece = tid + q * 256, row = piece >> 3, c16 = piece & 7;
@@ -612,6 +633,248 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_g_group(ResGGroup q) {
   }
 }
 
+// ------------------------------------------------------------------ fragment-major kernels
+// BF16 on the uniform grid, with Xtj and W stored as MFMA fragments (w_elem's
+// layout 2): one operand of each contraction is read by every wave straight
+// from memory into registers, one coalesced 16-byte load per lane and
+// fragment, and only the other operand is staged through LDS and shared by
+// the workgroup's 4 waves.  Kernel U writes W in the fragment order kernel G
+// reads, exchanging half-fragments between the two half-waves
+// (v_permlane32_swap) so that each lane stores 8 consecutive bins.
+constexpr int FB = 128;                    // neurons per tile of the LDS-staged operand
+constexpr int FLDS = 2 * FB * ROWB;        // its double buffer (bytes)
+
+__device__ __forceinline__ f32x16 mma_bf16(const i32x4& a, const i32x4& b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+// acc[a][b] += sum over the k steps [0, nk) of Afrag(a, step) Bs(b, step)^T:
+// A fragments come from ga(step, regs) into registers a step ahead; B (128 rows
+// by 64 k per step) from gb(step, regs) through LDS.  BFRAG: B's 16 KB of a
+// step are its 4 x 4 fragments in order (row block, k block), else 128 rows of
+// 128 bytes.  Acc element r of lane l of block (a, b) is row 32 a + 8 (r / 4)
+// + 4 (l / 32) + r % 4 of the wave's rows, column 32 b + l % 32 of the 128
+// columns.
+template <int MB, bool BFRAG, typename GA, typename GB>
+__device__ __forceinline__ void frag_loop(int nk, GA ga, GB gb, unsigned char* smem, f32x16 (&acc)[MB][4]) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int l32 = lane & 31, hi = lane >> 5;
+  i32x4 an[MB][4], bn[4];
+  auto sb = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int p = tid + 256 * q, r = p >> 3, c = p & 7;
+      *(i32x4*)(smem + buf * (FB * ROWB) + (BFRAG ? p * 16 : r * ROWB + c * 16)) = bn[q];
+    }
+  };
+  if (nk <= 0) return;
+  ga(0, an);
+  gb(0, bn);
+  sb(0);
+  __syncthreads();
+  for (int ks = 0; ks < nk; ++ks) {
+    const int cur = ks & 1;
+    const bool more = ks + 1 < nk;
+    i32x4 ac[MB][4];
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) ac[a][kc] = an[a][kc];
+    if (more) {
+      gb(ks + 1, bn);
+      ga(ks + 1, an);
+    }
+    const unsigned char* Bs = smem + cur * (FB * ROWB) + (BFRAG ? lane * 16 : l32 * ROWB + hi * 16);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      i32x4 bv[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        bv[b] = *(const i32x4*)(Bs + (BFRAG ? (b * 4 + kc) * 1024 : b * 32 * ROWB + kc * 32));
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mma_bf16(ac[a][kc], bv[b], acc[a][b]);
+    }
+    if (more) sb(cur ^ 1);
+    __syncthreads();
+  }
+}
+
+// Kernel U: tile 256 bins x 128 neurons, 4 waves of 64 bins x 128 neurons.
+// A = the trace's fragments (rows t), B = J's rows i0 .. i0 + 127 (k = j, the
+// two-term J's 2 Np columns against the trace repeated).  Epilogue as in
+// res_u_tile: W = exp(V) (0 past the last bin) and per-neuron FP64 sums over
+// the tile's bins (FP32 within a lane's 32 bins).
+__device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, int64_t ttile, unsigned char* smem) {
+  constexpr int MB = 2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int64_t i0 = itile * FB, tl0 = ttile * GLMR_TT, tt0 = g.t0 + tl0;
+  const int64_t kbn = g.Np / 16;                         // 16-column blocks of a trace row block
+  const i32x4* __restrict__ Xg = (const i32x4*)g.Xtj + ((tt0 + 64 * wave) / 32) * kbn * 64 + lane;
+  const int64_t ldj = (g.j2 ? 2 : 1) * g.Np * 2;         // bytes per row of J
+  const unsigned char* __restrict__ Jg = (const unsigned char*)g.Jc + i0 * ldj;
+  auto ga = [&](int ks, i32x4 (&an)[MB][4]) {
+    int64_t kb = (int64_t)ks * 4;
+    if (kb >= kbn) kb -= kbn;  // the two-term J's second half meets the same trace
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) an[a][kc] = Xg[(a * kbn + kb + kc) * 64];
+  };
+  auto gb = [&](int ks, i32x4 (&bn)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int p = tid + 256 * q, r = p >> 3, c = p & 7;
+      bn[q] = *(const i32x4*)(Jg + r * ldj + (int64_t)ks * 128 + c * 16);
+    }
+  };
+  f32x16 acc[MB][4];
+  zero_acc(acc);
+  frag_loop<MB, false>((int)(ldj / 128), ga, gb, smem, acc);
+
+  // the loop ended on a barrier: its LDS holds the per-wave sums next
+  double* red = (double*)smem;  // [4][FB]
+  unsigned char* __restrict__ W = (unsigned char*)g.W;
+  const int64_t wkb = g.L / 16;  // 16-bin blocks of a W row block
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    float cs = 0.f;
+    const int64_t ib = (i0 >> 5) + b;
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+      uint32_t pk[8];  // bins 8 q + 4 hi + {0, 1} and {2, 3} for q = 0 .. 3
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t t = tt0 + 64 * wave + 32 * a + 8 * q + 4 * hi;
+        float lam[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          lam[e] = __expf(acc[a][b][4 * q + e]);
+          if (t + e >= g.B) lam[e] = 0.f;
+          cs += lam[e];
+        }
+        bf16x2 p0 = {(__bf16)lam[0], (__bf16)lam[1]}, p1 = {(__bf16)lam[2], (__bf16)lam[3]};
+        pk[2 * q] = __builtin_bit_cast(uint32_t, p0);
+        pk[2 * q + 1] = __builtin_bit_cast(uint32_t, p1);
+      }
+      // 16-bin block qp holds q = 2 qp (its bins 0 .. 7) and q = 2 qp + 1
+      // (bins 8 .. 15), and a fragment lane needs 8 consecutive bins: the
+      // lower half-wave gets the upper half's values of q = 2 qp (bins 4 .. 7),
+      // the upper half the lower half's of q = 2 qp + 1 (bins 8 .. 11)
+#pragma unroll
+      for (int qp = 0; qp < 2; ++qp) {
+        const int q0 = 2 * qp, q1 = 2 * qp + 1;
+        const auto s0 = __builtin_amdgcn_permlane32_swap(pk[2 * q0], pk[2 * q1], false, false);
+        const auto s1 = __builtin_amdgcn_permlane32_swap(pk[2 * q0 + 1], pk[2 * q1 + 1], false, false);
+        const i32x4 v = i32x4{(int)s0[0], (int)s1[0], (int)s0[1], (int)s1[1]};
+        const int64_t kb = (tl0 + 64 * wave + 32 * a) / 16 + qp;
+        *(i32x4*)(W + ((ib * wkb + kb) * 64 + lane) * 16) = v;
+      }
+    }
+    double v = (double)cs;
+    v += __shfl_xor(v, 32, 64);
+    if (hi == 0) red[wave * FB + b * 32 + l32] = v;
+  }
+  __syncthreads();
+  if (tid < FB) {
+    const double v = red[tid] + red[FB + tid] + red[2 * FB + tid] + red[3 * FB + tid];
+    g.rowpart[(tt0 / GLMR_TT) * g.Np + i0 + tid] = v;
+  }
+}
+
+// two workgroups per CU: each wave within 256 registers, so that one wave's
+// loads overlap the other's MFMAs on every SIMD
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_res_uf(ResUArgs g) {
+  __shared__ __align__(16) unsigned char smem[FLDS];
+  const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
+  res_uf_tile(g, logical % g.n_itiles, logical / g.n_itiles, smem);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_res_uf_group(ResUGroup q) {
+  __shared__ __align__(16) unsigned char smem[FLDS];
+  const int64_t rank = xcd_logical(blockIdx.x, gridDim.x);
+  for (int64_t base = 0; base < q.total; base += gridDim.x) {
+    const int64_t k = base + rank;
+    if (k >= q.total) break;
+    const int r = find_rec(q.prefix, q.n, k);
+    const ResUArgs g = q.args[r];
+    const int64_t local = k - q.prefix[r];
+    res_uf_tile(g, local % g.n_itiles, local / g.n_itiles, smem);
+    __syncthreads();
+  }
+}
+
+// Kernel G: tile (128 MB) x 128 of (i, j) over one split of the chunk's bins,
+// 4 waves of 32 MB rows x 128 columns.  A = W's fragments (rows i), B = the
+// fragments of Xjt's rows j0 .. j0 + 127, copied to LDS as they lie.
+template <int MB>
+__device__ __forceinline__ void res_gf_tile(const ResGArgs& g, int64_t logical, unsigned char* smem) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int64_t jtile = logical % g.n_jtiles;
+  const int64_t itile = (logical / g.n_jtiles) % g.n_itiles;
+  const int64_t split = logical / ((int64_t)g.n_jtiles * g.n_itiles);
+  const int64_t i0 = itile * (4 * 32 * MB), j0 = jtile * FB;
+  const int64_t tb = split * g.ks;
+  const int64_t te = (tb + g.ks < g.Lc) ? tb + g.ks : g.Lc;
+  const int64_t wkb = g.L / 16;
+  const i32x4* __restrict__ Wg = (const i32x4*)g.W + ((i0 >> 5) + MB * wave) * wkb * 64 + (tb / 16) * 64 + lane;
+  const int64_t xkb = g.Bp / 16;  // 16-bin blocks of an Xjt row block
+  const i32x4* __restrict__ Xg = (const i32x4*)g.Xjt + ((j0 >> 5) * xkb + (g.t0 + tb) / 16) * 64;
+  auto ga = [&](int ks, i32x4 (&an)[MB][4]) {
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) an[a][kc] = Wg[(a * wkb + (int64_t)ks * 4 + kc) * 64];
+  };
+  auto gb = [&](int ks, i32x4 (&bn)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // piece p: row block p / 256, k block p / 64 % 4, lane p % 64
+      const int p = tid + 256 * q;
+      bn[q] = Xg[((p >> 8) * xkb + (int64_t)ks * 4 + ((p >> 6) & 3)) * 64 + (p & 63)];
+    }
+  };
+  f32x16 acc[MB][4];
+  zero_acc(acc);
+  frag_loop<MB, true>((int)((te - tb) / 64), ga, gb, smem, acc);
+  float* __restrict__ Gp = (float*)g.Gp + split * g.Np * g.Np;
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t il = i0 + 32 * MB * wave + a * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+        Gp[il * g.Np + j0 + b * 32 + l32] = acc[a][b][r];
+      }
+}
+
+template <int MB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB == 4 ? 1 : 2))) void k_res_gf(ResGArgs g) {
+  __shared__ __align__(16) unsigned char smem[FLDS];
+  res_gf_tile<MB>(g, xcd_logical(blockIdx.x, gridDim.x), smem);
+}
+
+template <int MB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB == 4 ? 1 : 2))) void k_res_gf_group(
+    ResGGroup q) {
+  __shared__ __align__(16) unsigned char smem[FLDS];
+  const int64_t rank = xcd_logical(blockIdx.x, gridDim.x);
+  for (int64_t base = 0; base < q.total; base += gridDim.x) {
+    const int64_t k = base + rank;
+    if (k >= q.total) break;
+    const int r = find_rec(q.prefix, q.n, k);
+    const ResGArgs g = q.args[r];
+    res_gf_tile<MB>(g, k - q.prefix[r], smem);
+    __syncthreads();
+  }
+}
+
 template <typename K>
 hipError_t set_lds(K kern, size_t lds) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -678,6 +941,30 @@ hipError_t run_g(const ResGArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t run_uf(const ResUArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_res_uf, dim3((unsigned)((int64_t)a.n_itiles * a.n_ttiles)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int MB>
+hipError_t run_gf(const ResGArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_res_gf<MB>, dim3((unsigned)((int64_t)a.n_splits * a.n_itiles * a.n_jtiles)), dim3(256), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+hipError_t run_uf_group(const ResUGroup& q, hipStream_t st) {
+  hipLaunchKernelGGL(k_res_uf_group, dim3(persistent_grid(k_res_uf_group, 256, 0, q.total)), dim3(256), 0, st, q);
+  return hipGetLastError();
+}
+
+template <int MB>
+hipError_t run_gf_group(const ResGGroup& q, hipStream_t st) {
+  auto kern = k_res_gf_group<MB>;
+  hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, 256, 0, q.total)), dim3(256), 0, st, q);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_build_x(const ResXArgs& a, hipStream_t st) {
@@ -696,14 +983,19 @@ hipError_t launch_build_x8(const ResXArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Tile shapes (neuron tile BM x 256 bins for U, BM x BM for G) and wave grids
-// offered to the autotuner; `shape` indexes res_shapes().  The 8-wave
-// 256-neuron tiles need more than the 256 registers a wave may hold at two
-// waves per SIMD once the fragments are FP8 (32 bytes a lane), so FP8 skips them.
+// Tile shapes offered to the autotuner; `shape` indexes res_shapes().
+// 0 .. 6: the row-major kernels (neuron tile BM x 256 bins for U, BM x BM for
+// G) with their wave grids.  The 8-wave 256-neuron tiles need more than the
+// 256 registers a wave may hold at two waves per SIMD once the fragments are
+// FP8 (32 bytes a lane), so FP8 skips them.  7 .. 9: the fragment-major
+// kernels (BF16, uniform grid): one kernel U, kernel G with 256, 512 or 128
+// rows per tile.
 const ResShape* res_shapes(int* n) {
   static const ResShape s[] = {
-      {256, 2, 2, 1}, {256, 2, 4, 0}, {256, 4, 2, 0}, {128, 2, 2, 1},
-      {128, 1, 4, 1}, {128, 4, 2, 1}, {128, 2, 4, 1},
+      {256, 256, 256, 2, 2, 1, 0, 1}, {256, 256, 256, 2, 4, 0, 0, 1}, {256, 256, 256, 4, 2, 0, 0, 1},
+      {128, 128, 128, 2, 2, 1, 0, 1}, {128, 128, 128, 1, 4, 1, 0, 1}, {128, 128, 128, 4, 2, 1, 0, 1},
+      {128, 128, 128, 2, 4, 1, 0, 1}, {128, 256, 128, 4, 1, 0, 1, 1}, {128, 512, 128, 4, 1, 0, 1, 0},
+      {128, 128, 128, 4, 1, 0, 1, 0},
   };
   *n = (int)(sizeof(s) / sizeof(s[0]));
   return s;
@@ -719,6 +1011,9 @@ hipError_t res_u(int shape, const ResUArgs& a, hipStream_t st) {
     case 4: return run_u<128, 1, 4, F8, EV>(a, st);
     case 5: return run_u<128, 4, 2, F8, EV>(a, st);
     case 6: return run_u<128, 2, 4, F8, EV>(a, st);
+    case 7:
+    case 8:
+    case 9: return (F8 || EV) ? hipErrorInvalidValue : run_uf(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -733,6 +1028,9 @@ hipError_t res_g(int shape, const ResGArgs& a, hipStream_t st) {
     case 4: return run_g<128, 128, 1, 4, F8>(a, st);
     case 5: return run_g<128, 128, 4, 2, F8>(a, st);
     case 6: return run_g<128, 128, 2, 4, F8>(a, st);
+    case 7: return F8 ? hipErrorInvalidValue : run_gf<2>(a, st);
+    case 8: return F8 ? hipErrorInvalidValue : run_gf<4>(a, st);
+    case 9: return F8 ? hipErrorInvalidValue : run_gf<1>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -747,6 +1045,9 @@ hipError_t res_u_group(int shape, const ResUGroup& q, hipStream_t st) {
     case 4: return run_u_group<128, 1, 4, F8>(q, st);
     case 5: return run_u_group<128, 4, 2, F8>(q, st);
     case 6: return run_u_group<128, 2, 4, F8>(q, st);
+    case 7:
+    case 8:
+    case 9: return F8 ? hipErrorInvalidValue : run_uf_group(q, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -761,6 +1062,9 @@ hipError_t res_g_group(int shape, const ResGGroup& q, hipStream_t st) {
     case 4: return run_g_group<128, 128, 1, 4, F8>(q, st);
     case 5: return run_g_group<128, 128, 4, 2, F8>(q, st);
     case 6: return run_g_group<128, 128, 2, 4, F8>(q, st);
+    case 7: return F8 ? hipErrorInvalidValue : run_gf_group<2>(q, st);
+    case 8: return F8 ? hipErrorInvalidValue : run_gf_group<4>(q, st);
+    case 9: return F8 ? hipErrorInvalidValue : run_gf_group<1>(q, st);
     default: return hipErrorInvalidValue;
   }
 }

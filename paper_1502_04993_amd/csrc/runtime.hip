@@ -109,6 +109,7 @@ struct glmr_ctx {
   unsigned char* Xtj = nullptr;
   unsigned char* Xjt = nullptr;
   int res_shape_u = 1, res_shape_g = 1;  // indices into res_shapes()
+  int xfrag = 0;                         // BF16, uniform grid: Xtj and W as MFMA fragments
   size_t x_bytes = 0;                    // bytes of each layout as allocated
   unsigned* xmax = nullptr;              // FP8: per-chunk trace maxima
   float* xscale = nullptr;               // FP8: per-chunk trace scales
@@ -470,6 +471,7 @@ glmr_status build_resident_trace(glmr_ctx* c, Arena* ar) {
   xa.Bp = c->Bp;
   xa.Xtj = c->Xtj;
   xa.Xjt = c->Xjt;
+  xa.xfrag = c->xfrag;
   xa.ev = ev_slots(c);
   if (f8) {
     const int64_t nchunks = (c->Bp + c->L - 1) / c->L;
@@ -672,11 +674,18 @@ int64_t split_len(const glmr_ctx* c, int64_t Lc) {
   return split_len_tiles(c, Lc, (c->Np / c->bi2) * (c->Np / c->bj2));
 }
 
-// whether tile shape k fits this context's padding and precision
+// whether shape k suits this context's trace layout and precision
+bool shape_fits(const glmr_ctx* c, int k) {
+  int n = 0;
+  const ResShape* sh = res_shapes(&n);
+  return k >= 0 && k < n && sh[k].frag == c->xfrag && (c->prec != PREC_FP8 || sh[k].fp8_ok);
+}
+
+// kernel G's tiles of shape k divide the padded neurons
 bool shape_ok(const glmr_ctx* c, int k) {
   int n = 0;
   const ResShape* sh = res_shapes(&n);
-  return k >= 0 && k < n && c->Np % sh[k].bm == 0 && (c->prec != PREC_FP8 || sh[k].fp8_ok);
+  return shape_fits(c, k) && c->Np % sh[k].gi == 0 && c->Np % sh[k].gj == 0;
 }
 
 // kernel U's shapes: on the event grid only the 128-neuron tiles (the
@@ -685,7 +694,14 @@ bool shape_ok(const glmr_ctx* c, int k) {
 bool shape_ok_u(const glmr_ctx* c, int k) {
   int n = 0;
   const ResShape* sh = res_shapes(&n);
-  return shape_ok(c, k) && !(c->evm && sh[k].bm != 128);
+  return shape_fits(c, k) && c->Np % sh[k].ui == 0 && !(c->evm && sh[k].ui != 128);
+}
+
+// shapes worth timing for kernel U (the fragment-major shapes share one kernel U)
+bool shape_tune_u(const glmr_ctx* c, int k) {
+  int n = 0;
+  const ResShape* sh = res_shapes(&n);
+  return shape_ok_u(c, k) && sh[k].u_own;
 }
 
 ResShape res_shape(int k) {
@@ -706,7 +722,7 @@ ResUArgs make_u_args(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
   ua.B = c->B;
   ua.t0 = t0;
   ua.L = c->L;
-  ua.n_itiles = (int)(c->Np / su.bm);
+  ua.n_itiles = (int)(c->Np / su.ui);
   ua.n_ttiles = (int)(Lc / GLMR_TT);
   ua.W = c->W;
   ua.rowpart = c->rowpart;
@@ -731,8 +747,8 @@ ResGArgs make_g_args(glmr_ctx* c, int k, int64_t t0, int64_t Lc) {
   ga.t0 = t0;
   ga.L = c->L;
   ga.Lc = Lc;
-  ga.n_itiles = (int)(c->Np / sg.bm);
-  ga.n_jtiles = (int)(c->Np / sg.bm);
+  ga.n_itiles = (int)(c->Np / sg.gi);
+  ga.n_jtiles = (int)(c->Np / sg.gj);
   ga.ks = split_len_tiles(c, Lc, (int64_t)ga.n_itiles * ga.n_jtiles);
   ga.n_splits = (int)((Lc + ga.ks - 1) / ga.ks);
   ga.Gp = c->Gp;
@@ -792,7 +808,7 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
       sd.W = c->W;
       sd.wtype = c->prec == PREC_F64 ? 0 : (c->prec == PREC_F32 ? 1 : 2);
       sd.scaled = c->resident ? 0 : 1;
-      sd.tiled = c->resident ? 1 : 0;
+      sd.tiled = c->resident ? (c->xfrag ? 2 : 1) : 0;
       sd.Jr = c->Jr;
       sd.B = c->B;
       sd.t0 = t0;
@@ -808,7 +824,7 @@ glmr_status eval_core(glmr_ctx* c, bool want_grad, bool want_tau) {
     }
     if (want_tau) {
       g1.mode = 1;
-      g1.w_plain = c->resident ? 1 : 0;
+      g1.w_plain = c->resident ? (c->xfrag ? 2 : 1) : 0;
       g1.rowpart = c->rowpartV;
       ProfScope ps(c, K_V);
       HIPCHK(c, launch_gemm1(c->prec, c->tile, g1, c->st));
@@ -895,9 +911,19 @@ void setup_precision(glmr_ctx* c) {
   else if (c->cfg.tile_n == 256) c->tile = 256;
   else c->tile = c->N > 384 ? 256 : 128;
   gemm_tiles(c->prec, c->tile, &c->bi1, &c->bt1, &c->bi2, &c->bj2);
-  // resident-trace shapes: 256-neuron tiles when the padding allows
-  if (c->prec == PREC_FP8) c->res_shape_u = c->res_shape_g = 5;
-  else c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 2 : 3;
+  // resident-trace shapes: on the uniform grid in BF16 the fragment-major
+  // kernels (unless GLMR_XFRAG=0), else the row-major ones with 256-neuron
+  // tiles when the padding allows
+  const char* xf = std::getenv("GLMR_XFRAG");
+  c->xfrag = (c->prec == PREC_BF16 && !c->evm && !(xf && std::strcmp(xf, "0") == 0)) ? 1 : 0;
+  if (c->xfrag) {
+    c->res_shape_u = 7;
+    c->res_shape_g = (c->Np % 256 == 0) ? 7 : 9;
+  } else if (c->prec == PREC_FP8) {
+    c->res_shape_u = c->res_shape_g = 5;
+  } else {
+    c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 2 : 3;
+  }
   if (c->evm) c->res_shape_u = 5;  // the interval integrals: 128-neuron tiles keep kernel U unspilled
   if (const char* e = std::getenv("GLMR_RES_SHAPE")) {
     int u = -1, g = -1;
@@ -1694,6 +1720,11 @@ glmr_status glmr_batch_autotune(glmr_batch* b, const char* cache_path, int32_t* 
       if (shape_class(c) == cls && !(u ? shape_ok_u(c, k) : shape_ok(c, k))) return false;
     return true;
   };
+  auto all_tune_u = [&](int cls, int k) {
+    for (glmr_ctx* c : b->ctxs)
+      if (shape_class(c) == cls && !shape_tune_u(c, k)) return false;
+    return true;
+  };
   bool cached = false;
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
@@ -1731,7 +1762,7 @@ glmr_status glmr_batch_autotune(glmr_batch* b, const char* cache_path, int32_t* 
       int best_u = -1, best_g = -1;
       double bu = 1e300, bg = 1e300;
       for (int k = 0; k < n; ++k) {
-        const bool oku = all_ok(cls, k, true), okg = all_ok(cls, k, false);
+        const bool oku = all_tune_u(cls, k), okg = all_ok(cls, k, false);
         if (!oku && !okg) continue;
         const int su = b->tuned_u[cls], sg = b->tuned_g[cls];
         b->tuned_u[cls] = oku ? k : su;
@@ -2401,7 +2432,7 @@ glmr_status glmr_query(const glmr_ctx* c, int64_t* n_pad, int64_t* b_pad, int64_
   if (chunk_bins) *chunk_bins = c->L;
   if (planes) *planes = c->planes;
   if (tile_n) *tile_n = c->tile;
-  if (trace_resident) *trace_resident = c->resident ? 1 : 0;
+  if (trace_resident) *trace_resident = c->resident ? (c->xfrag ? 2 : 1) : 0;
   return GLMR_OK;
 }
 
@@ -2423,7 +2454,7 @@ extern "C" glmr_status glmr_autotune(glmr_ctx* c, const char* cache_path, int32_
   }
   const std::string key = tune_key(c);
   int n = 0;
-  const ResShape* sh = res_shapes(&n);
+  (void)res_shapes(&n);
   int best_u = -1, best_g = -1;
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
@@ -2449,15 +2480,16 @@ extern "C" glmr_status glmr_autotune(glmr_ctx* c, const char* cache_path, int32_
     const int64_t Lc = std::min<int64_t>(c->L, c->Bp);
     double tu = 1e300, tg = 1e300;
     for (int k = 0; k < n; ++k) {
-      if (!shape_ok(c, k)) continue;
       double ms = 0;
-      if (shape_ok_u(c, k)) {
+      if (shape_tune_u(c, k)) {
         TRY(time_launches(c, [&] { return launch_u_chunk(c, k, 0, Lc); }, 3, &ms));
         if (ms < tu) { tu = ms; best_u = k; }
       }
-      int ns = 0;
-      TRY(time_launches(c, [&] { return launch_g_chunk(c, k, 0, Lc, &ns); }, 3, &ms));
-      if (ms < tg) { tg = ms; best_g = k; }
+      if (shape_ok(c, k)) {
+        int ns = 0;
+        TRY(time_launches(c, [&] { return launch_g_chunk(c, k, 0, Lc, &ns); }, 3, &ms));
+        if (ms < tg) { tg = ms; best_g = k; }
+      }
     }
     if (cache_path) {
       if (FILE* f = std::fopen(cache_path, "a")) {

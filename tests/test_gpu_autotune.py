@@ -4,6 +4,8 @@ Kernel U accumulates every V in the same k order whatever the tile shape;
 the shapes differ only in how the FP32 sums of exp(V) over a wave's bins
 are grouped before the FP64 sums, and kernel G's in how its FP32 partials
 are grouped over time.  So all shapes agree far inside the BF16 tolerance.
+Shapes 0-6 are the row-major kernels (GLMR_XFRAG=0), 7-9 the fragment-major
+ones (the default for BF16 on the uniform grid).
 """
 import os
 
@@ -17,20 +19,25 @@ from oracle import glm_oracle as O
 
 pytestmark = pytest.mark.gpu
 
-N_SHAPES = 7
+N_SHAPES = 10
+FRAG = (7, 8, 9)
 
 
-def _ctx(rec, shape=None):
+def _ctx(rec, shape=None, frag=True):
     import paper_1502_04993_amd as G
-    old = os.environ.pop("GLMR_RES_SHAPE", None)
+    saved = {k: os.environ.pop(k, None) for k in ("GLMR_RES_SHAPE", "GLMR_XFRAG")}
     if shape is not None:
         os.environ["GLMR_RES_SHAPE"] = f"{shape},{shape}"
+        frag = shape in FRAG
+    if not frag:
+        os.environ["GLMR_XFRAG"] = "0"
     try:
         ctx = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision="bf16")
     finally:
-        os.environ.pop("GLMR_RES_SHAPE", None)
-        if old is not None:
-            os.environ["GLMR_RES_SHAPE"] = old
+        for k, v in saved.items():
+            os.environ.pop(k, None)
+            if v is not None:
+                os.environ[k] = v
     ctx.set_spikes(rec.bins, rec.neurons)
     ctx.set_kernel(rec.tau)
     return ctx
@@ -48,7 +55,7 @@ def test_every_shape_agrees_and_matches_oracle():
         ctx = _ctx(rec, k)
         ctx.set_params(Jb, mu)
         r = ctx.eval(grad=True)
-        assert ctx.query()["trace_resident"]
+        assert ctx.query()["trace_resident"] and ctx.query()["trace_frag"] == (k in FRAG)
         ctx.close()
         g = np.concatenate([r["gmu"], r["gJ"].ravel()])
         check(f"shape {k}", r, ref, TOL["bf16"])
@@ -59,18 +66,22 @@ def test_every_shape_agrees_and_matches_oracle():
         assert np.linalg.norm(g - grads[0]) / np.linalg.norm(grads[0]) < 1e-5
 
 
-def test_autotune_picks_valid_shapes_and_caches(tmp_path):
+@pytest.mark.parametrize("frag", [True, False])
+def test_autotune_picks_valid_shapes_and_caches(tmp_path, frag):
     rec = synth.balanced(N=384, B=30_000, seed=22)  # Np = 384: only the 128-neuron tiles fit
     cache = str(tmp_path / "tune.txt")
-    ctx = _ctx(rec)
+    ctx = _ctx(rec, frag=frag)
     ctx.set_params(rec.J, rec.mu)
     u, g = ctx.autotune(cache)
-    assert u in (3, 4, 5, 6) and g in (3, 4, 5, 6)
+    if frag:
+        assert u == 7 and g == 9  # one kernel U; kernel G's 256- and 512-row tiles do not divide 384
+    else:
+        assert u in (3, 4, 5, 6) and g in (3, 4, 5, 6)
     a = ctx.eval(grad=True)
     ctx.close()
     lines = open(cache).read().splitlines()
     assert len(lines) == 1 and lines[0].startswith("glmrec-tune ")
-    ctx = _ctx(rec)
+    ctx = _ctx(rec, frag=frag)
     ctx.set_params(rec.J, rec.mu)
     assert ctx.autotune(cache) == (u, g)  # served from the cache
     b = ctx.eval(grad=True)

@@ -36,30 +36,39 @@ def _recs():
 
 
 def _ctx(rec, prec, shape=None):
+    # prec "bf16-rowmajor": BF16 with the row-major trace and weights (GLMR_XFRAG=0)
     G = _G()
-    old = os.environ.pop("GLMR_RES_SHAPE", None)
+    saved = {k: os.environ.pop(k, None) for k in ("GLMR_RES_SHAPE", "GLMR_XFRAG")}
     if shape is not None:
         os.environ["GLMR_RES_SHAPE"] = shape
+    if prec == "bf16-rowmajor":
+        os.environ["GLMR_XFRAG"] = "0"
+        prec = "bf16"
     try:
         c = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision=prec)
     finally:
-        os.environ.pop("GLMR_RES_SHAPE", None)
-        if old is not None:
-            os.environ["GLMR_RES_SHAPE"] = old
+        for k, v in saved.items():
+            os.environ.pop(k, None)
+            if v is not None:
+                os.environ[k] = v
     c.set_spikes(rec.bins, rec.neurons)
     c.set_kernel(rec.tau)
     return c
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8", "fp64"])
+# one shape every padding allows: 128-row tiles (fragment-major kernel G for BF16)
+ONE_SHAPE = {"bf16": "9,9", "bf16-rowmajor": "5,5", "fp8": "5,5", "fp64": None}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16-rowmajor", "fp8", "fp64"])
 def test_batch_eval_equals_each_context_and_oracle(prec):
     G = _G()
     recs = _recs()
-    shape = "5,5" if prec != "fp64" else None  # one shape every padding allows
-    ctxs = [_ctx(r, prec, shape) for r in recs]
+    ctxs = [_ctx(r, prec, ONE_SHAPE[prec]) for r in recs]
+    assert all(c.query()["trace_frag"] == (prec == "bf16") for c in ctxs)
     thetas = []
     for r, c in zip(recs, ctxs):
-        J = _bf16(r.J) if prec == "bf16" else r.J
+        J = _bf16(r.J) if prec.startswith("bf16") else r.J
         if prec == "fp8":
             from test_gpu_parity import round_fp8_rows
             J = round_fp8_rows(r.J)
@@ -74,7 +83,7 @@ def test_batch_eval_equals_each_context_and_oracle(prec):
         assert np.array_equal(gJ, singles[k]["gJ"]) and np.array_equal(gmu, singles[k]["gmu"])
         ref = O.loglik(r.bins, r.neurons, r.n_neurons, r.n_bins, r.dt, r.tau, thetas[k], r.mu)
         got = dict(ll=lls[k], ll_rows=singles[k]["ll_rows"], gJ=gJ, gmu=gmu)
-        check(f"batch {prec} rec {k} N={r.n_neurons} B={r.n_bins}", got, ref, tol_for(prec, r))
+        check(f"batch {prec} rec {k} N={r.n_neurons} B={r.n_bins}", got, ref, tol_for(prec.split("-")[0], r))
     b.close()
     for c in ctxs:
         c.close()
@@ -85,7 +94,7 @@ def test_batch_fit_equals_individual_fits(prec):
     G = _G()
     recs = [synth.balanced(N=n, B=b, in_frac=0.2, seed=60 + k)
             for k, (n, b) in enumerate([(40, 8_000), (90, 12_000), (150, 10_000)])]
-    shape = "5,5" if prec == "bf16" else None
+    shape = ONE_SHAPE[prec]
     single = []
     for r in recs:
         c = _ctx(r, prec, shape)
@@ -114,7 +123,7 @@ def test_batch_fit_graph_replays_match_eager():
     try:
         for flag in ("1", "0"):
             os.environ["GLMR_NO_GRAPH"] = flag
-            ctxs = [_ctx(r, "bf16", "5,5") for r in recs]
+            ctxs = [_ctx(r, "bf16", ONE_SHAPE["bf16"]) for r in recs]
             b = G.Batch(ctxs)
             b.fit(max_iter=12, from_zero=True)
             out.append([c.get_params()[0] for c in ctxs])
@@ -139,9 +148,10 @@ def test_batch_autotune_keeps_results_within_tolerance(tmp_path):
     b = G.Batch(ctxs)
     cache = str(tmp_path / "tune.txt")
     # two classes: N = 130 and 520 pad to multiples of 256 (every shape), the
-    # others not (128-neuron tiles only); the first class's shapes are reported
+    # others not (128-neuron tiles only); the first class's shapes are reported:
+    # the one fragment-major kernel U and one of the three kernel G tiles
     u, g = b.autotune(cache)
-    assert 0 <= u <= 6 and 0 <= g <= 6
+    assert u == 7 and g in (7, 8, 9)
     assert b.autotune(cache) == (u, g)
     assert len(open(cache).read().splitlines()) == 1
     lls = b.eval()
@@ -201,7 +211,7 @@ def test_batch_config5_members_against_oracle_rows(tmp_path):
     in BF16 with the autotuned shapes: a balanced network of N = 1976 (padded
     to 2048 neurons, whose weights chunk is shortened under the 4 GiB cap),
     and two synfire networks (R18: N >= 625, chain 10 x 50, J_ii = -20) of
-    N = 639 (128-neuron tiles only) and N = 1947.  The batch agrees with each
+    N = 639 (padded to 768) and N = 1947.  The batch agrees with each
     context's own evaluation (its own tile shapes: the same sums grouped
     otherwise) far inside the BF16 bounds, and sampled rows (a chain member,
     a background excitatory and an inhibitory neuron, the last row) match the
@@ -223,8 +233,14 @@ def test_batch_config5_members_against_oracle_rows(tmp_path):
     for k, (r, c, J) in enumerate(zip(recs, ctxs, Js)):
         gJ, gmu = b.grad(k)
         single = c.eval(grad=True)
-        assert abs(lls[k] - single["ll"]) <= 1e-9 * abs(single["ll"])
-        assert np.abs(gJ - single["gJ"]).max() <= 1e-5 * np.abs(single["gJ"]).max()
+        # the autotuned shapes may group the FP32 sums otherwise than the
+        # context's own: kernel U sums 32 to 128 values of exp(V) per lane in
+        # FP32, and a bursty synfire row's integral rests on a few of those
+        # partials, so the grouping moves L by up to ~1e-7 (1.5e-7 measured
+        # over all shapes for N = 639); kernel G's FP32 partials over splits of
+        # other lengths move the gradient by up to ~2e-5 of its largest entry
+        assert abs(lls[k] - single["ll"]) <= 1e-6 * abs(single["ll"])
+        assert np.abs(gJ - single["gJ"]).max() <= 1e-4 * np.abs(single["gJ"]).max()
         N = r.n_neurons
         rows = [0, r.n_exc - 1, r.n_exc, N - 1]
         if r.group_of is not None:
