@@ -644,6 +644,14 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_res_g_group(ResGGroup q) {
 constexpr int FB = 128;                    // neurons per tile of the LDS-staged operand
 constexpr int FLDS = 2 * FB * ROWB;        // its double buffer (bytes)
 
+// Buffer resource over [base, base + bytes) for raw buffer loads: the wave-
+// uniform base sits in scalar registers, a lane's offset in one 32-bit
+// register (constant over the k loop) and the k step's offset in a scalar,
+// so the loop does no 64-bit address arithmetic; reads past `bytes` return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
 __device__ __forceinline__ f32x16 mma_bf16(const i32x4& a, const i32x4& b, const f32x16& c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
                                                  0, 0, 0);
@@ -714,22 +722,26 @@ __device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, in
   const int l32 = lane & 31, hi = lane >> 5;
   const int64_t i0 = itile * FB, tl0 = ttile * GLMR_TT, tt0 = g.t0 + tl0;
   const int64_t kbn = g.Np / 16;                         // 16-column blocks of a trace row block
-  const i32x4* __restrict__ Xg = (const i32x4*)g.Xtj + ((tt0 + 64 * wave) / 32) * kbn * 64 + lane;
   const int64_t ldj = (g.j2 ? 2 : 1) * g.Np * 2;         // bytes per row of J
-  const unsigned char* __restrict__ Jg = (const unsigned char*)g.Jc + i0 * ldj;
+  __amdgpu_buffer_rsrc_t xr[MB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+    xr[a] = buf_rsrc((const unsigned char*)g.Xtj + ((tt0 + 64 * wave) / 32 + a) * kbn * 1024, (int)(kbn * 1024));
+  const __amdgpu_buffer_rsrc_t jr = buf_rsrc((const unsigned char*)g.Jc + i0 * ldj, (int)(FB * ldj));
   auto ga = [&](int ks, i32x4 (&an)[MB][4]) {
-    int64_t kb = (int64_t)ks * 4;
-    if (kb >= kbn) kb -= kbn;  // the two-term J's second half meets the same trace
+    int kb = ks * 4;
+    if (kb >= kbn) kb -= (int)kbn;  // the two-term J's second half meets the same trace
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) an[a][kc] = Xg[(a * kbn + kb + kc) * 64];
+      for (int kc = 0; kc < 4; ++kc)
+        an[a][kc] = __builtin_amdgcn_raw_buffer_load_b128(xr[a], lane * 16 + kc * 1024, kb * 1024, 0);
   };
   auto gb = [&](int ks, i32x4 (&bn)[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int p = tid + 256 * q, r = p >> 3, c = p & 7;
-      bn[q] = *(const i32x4*)(Jg + r * ldj + (int64_t)ks * 128 + c * 16);
+      bn[q] = __builtin_amdgcn_raw_buffer_load_b128(jr, r * (int)ldj + c * 16, ks * 128, 0);
     }
   };
   f32x16 acc[MB][4];
@@ -822,22 +834,25 @@ __device__ __forceinline__ void res_gf_tile(const ResGArgs& g, int64_t logical, 
   const int64_t i0 = itile * (4 * 32 * MB), j0 = jtile * FB;
   const int64_t tb = split * g.ks;
   const int64_t te = (tb + g.ks < g.Lc) ? tb + g.ks : g.Lc;
-  const int64_t wkb = g.L / 16;
-  const i32x4* __restrict__ Wg = (const i32x4*)g.W + ((i0 >> 5) + MB * wave) * wkb * 64 + (tb / 16) * 64 + lane;
-  const int64_t xkb = g.Bp / 16;  // 16-bin blocks of an Xjt row block
-  const i32x4* __restrict__ Xg = (const i32x4*)g.Xjt + ((j0 >> 5) * xkb + (g.t0 + tb) / 16) * 64;
+  const int64_t wkb = g.L / 16, xkb = g.Bp / 16;
+  const int span = (int)((te - tb) / 16) * 1024;  // bytes of one row block over the split
+  __amdgpu_buffer_rsrc_t wr[MB], xr[4];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+    wr[a] = buf_rsrc((const unsigned char*)g.W + (((i0 >> 5) + MB * wave + a) * wkb + tb / 16) * 1024, span);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    xr[q] = buf_rsrc((const unsigned char*)g.Xjt + (((j0 >> 5) + q) * xkb + (g.t0 + tb) / 16) * 1024, span);
+  const int va = lane * 16, vb = wave * 1024 + lane * 16;
   auto ga = [&](int ks, i32x4 (&an)[MB][4]) {
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) an[a][kc] = Wg[(a * wkb + (int64_t)ks * 4 + kc) * 64];
+      for (int kc = 0; kc < 4; ++kc) an[a][kc] = __builtin_amdgcn_raw_buffer_load_b128(wr[a], va + kc * 1024, ks * 4096, 0);
   };
   auto gb = [&](int ks, i32x4 (&bn)[4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {  // piece p: row block p / 256, k block p / 64 % 4, lane p % 64
-      const int p = tid + 256 * q;
-      bn[q] = Xg[((p >> 8) * xkb + (int64_t)ks * 4 + ((p >> 6) & 3)) * 64 + (p & 63)];
-    }
+    for (int q = 0; q < 4; ++q) bn[q] = __builtin_amdgcn_raw_buffer_load_b128(xr[q], vb, ks * 4096, 0);
   };
   f32x16 acc[MB][4];
   zero_acc(acc);
