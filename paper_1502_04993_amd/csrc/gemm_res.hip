@@ -377,6 +377,14 @@ __device__ __forceinline__ void zero_acc(f32x16 (&acc)[MB][NB]) {
 // is staged in LDS so that each neuron's 256 bins leave as one run.
 constexpr uint32_t SR_WT = 0x85EBCA6Bu, SR_WI = 0xC2B2AE35u;  // rounding bits of the FP8 weights
 
+// The quadrature and FP64 tiers of the interval integrals, out of line: few
+// intervals leave the expansion's bound, and inlined at every one of kernel
+// U's unrolled call sites this code would quadruple the kernel and its
+// register demand.
+__device__ __attribute__((noinline)) void ev_rare_tier(const float* o, double delta, float D, float* F, float* H) {
+  glmr_ev::gl_tier_f(o, delta, D, F, H);
+}
+
 constexpr int EVTS = 20;  // floats per slot of kernel U's staged expansion table (80 B: 16 used)
 
 template <int BI, int WGM, int WGN, bool F8, bool EV = false>
@@ -455,7 +463,7 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
             float F, H;
             if (!glmr_ev::taylor_f(c, D, &F, &H)) {
               const int64_t t = tt0 + tq + e;  // t < B: slots past it are within the bound
-              glmr_ev::gl_tier_f(g.evgl + t * 16, g.evdelta[t], D, &F, &H);
+              ev_rare_tier(g.evgl + t * 16, g.evdelta[t], D, &F, &H);
             }
             lam[b][e] = H;
             cs[b] += F;
@@ -714,7 +722,10 @@ __device__ __forceinline__ void frag_loop(int nk, GA ga, GB gb, unsigned char* s
 // A = the trace's fragments (rows t), B = J's rows i0 .. i0 + 127 (k = j, the
 // two-term J's 2 Np columns against the trace repeated).  Epilogue as in
 // res_u_tile: W = exp(V) (0 past the last bin) and per-neuron FP64 sums over
-// the tile's bins (FP32 within a lane's 32 bins).
+// the tile's bins (FP32 within a lane's 32 bins); on the event grid (EV) the
+// interval integrals of Eq. (10), (14) in their place, from the tile's slot
+// coefficients staged in LDS.
+template <bool EV>
 __device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, int64_t ttile, unsigned char* smem) {
   constexpr int MB = 2;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -752,44 +763,119 @@ __device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, in
   double* red = (double*)smem;  // [4][FB]
   unsigned char* __restrict__ W = (unsigned char*)g.W;
   const int64_t wkb = g.L / 16;  // 16-bin blocks of a W row block
+  // W's fragment stores of one 32-bin block a of neuron block b: pk[2 q + {0, 1}]
+  // hold bins 8 q + 4 hi + {0, 1}, {2, 3}.  16-bin block qp holds q = 2 qp (its
+  // bins 0 .. 7) and q = 2 qp + 1 (bins 8 .. 15), and a fragment lane needs 8
+  // consecutive bins: the lower half-wave gets the upper half's values of
+  // q = 2 qp (bins 4 .. 7), the upper half the lower half's of q = 2 qp + 1
+  // (bins 8 .. 11)
+  auto store_w = [&](int a, int b, const uint32_t (&pk)[8]) {
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    float cs = 0.f;
-    const int64_t ib = (i0 >> 5) + b;
+    for (int qp = 0; qp < 2; ++qp) {
+      const int q0 = 2 * qp, q1 = 2 * qp + 1;
+      const auto s0 = __builtin_amdgcn_permlane32_swap(pk[2 * q0], pk[2 * q1], false, false);
+      const auto s1 = __builtin_amdgcn_permlane32_swap(pk[2 * q0 + 1], pk[2 * q1 + 1], false, false);
+      const i32x4 v = i32x4{(int)s0[0], (int)s1[0], (int)s0[1], (int)s1[1]};
+      const int64_t kb = (tl0 + 64 * wave + 32 * a) / 16 + qp;
+      *(i32x4*)(W + ((((i0 >> 5) + b) * wkb + kb) * 64 + lane) * 16) = v;
+    }
+  };
+  if constexpr (EV) {
+    // W = (e^D - e^{D xi}) / D and row sums of Ei(D) - Ei(D xi): the 16
+    // expansion coefficients of each of the tile's slots are formed once into
+    // LDS (after the row-sum partials); a lane reads its slot's with four
+    // broadcast loads and uses them for its 4 neuron blocks.  Intervals
+    // outside the expansion's bound take the quadrature or FP64 tier from
+    // the table in memory.
+    static_assert(4 * FB * sizeof(double) + GLMR_TT * EVTS * sizeof(float) <= FLDS && GLMR_TT == 256,
+                  "one slot per thread, the staged table after the row-sum partials");
+    float* ctab = (float*)(smem + 4 * FB * sizeof(double));  // [GLMR_TT][EVTS]
+    {
+      const int64_t t = tt0 + tid;
+      // past the last slot: zero length and u = 0, so F = H = 0
+      const float2 de = t < g.B ? *(const float2*)(g.evgl + t * 16) : float2{0.f, 0.f};
+      float c[16];
+      glmr_ev::stage_f(de.x, de.y, c);
+      float4* o = (float4*)(ctab + tid * EVTS);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[v] = float4{c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]};
+    }
+    __syncthreads();
+    float cs[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
-      uint32_t pk[8];  // bins 8 q + 4 hi + {0, 1} and {2, 3} for q = 0 .. 3
+      uint32_t pk[4][8];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t t = tt0 + 64 * wave + 32 * a + 8 * q + 4 * hi;
-        float lam[4];
+        const int tq = 64 * wave + 32 * a + 8 * q + 4 * hi;  // first of the lane's 4 consecutive slots
+        float lam[4][4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          lam[e] = __expf(acc[a][b][4 * q + e]);
-          if (t + e >= g.B) lam[e] = 0.f;
-          cs += lam[e];
-        }
-        bf16x2 p0 = {(__bf16)lam[0], (__bf16)lam[1]}, p1 = {(__bf16)lam[2], (__bf16)lam[3]};
-        pk[2 * q] = __builtin_bit_cast(uint32_t, p0);
-        pk[2 * q + 1] = __builtin_bit_cast(uint32_t, p1);
-      }
-      // 16-bin block qp holds q = 2 qp (its bins 0 .. 7) and q = 2 qp + 1
-      // (bins 8 .. 15), and a fragment lane needs 8 consecutive bins: the
-      // lower half-wave gets the upper half's values of q = 2 qp (bins 4 .. 7),
-      // the upper half the lower half's of q = 2 qp + 1 (bins 8 .. 11)
+          float c[16];
+          const float4* src = (const float4*)(ctab + (tq + e) * EVTS);
 #pragma unroll
-      for (int qp = 0; qp < 2; ++qp) {
-        const int q0 = 2 * qp, q1 = 2 * qp + 1;
-        const auto s0 = __builtin_amdgcn_permlane32_swap(pk[2 * q0], pk[2 * q1], false, false);
-        const auto s1 = __builtin_amdgcn_permlane32_swap(pk[2 * q0 + 1], pk[2 * q1 + 1], false, false);
-        const i32x4 v = i32x4{(int)s0[0], (int)s1[0], (int)s0[1], (int)s1[1]};
-        const int64_t kb = (tl0 + 64 * wave + 32 * a) / 16 + qp;
-        *(i32x4*)(W + ((ib * wkb + kb) * 64 + lane) * 16) = v;
+          for (int v = 0; v < 4; ++v) {
+            const float4 w = src[v];
+            c[4 * v] = w.x;
+            c[4 * v + 1] = w.y;
+            c[4 * v + 2] = w.z;
+            c[4 * v + 3] = w.w;
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const float D = acc[a][b][4 * q + e];
+            float F, H;
+            if (!glmr_ev::taylor_f(c, D, &F, &H)) {
+              const int64_t t = tt0 + tq + e;  // t < B: slots past it are within the bound
+              ev_rare_tier(g.evgl + t * 16, g.evdelta[t], D, &F, &H);
+            }
+            lam[b][e] = H;
+            cs[b] += F;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          bf16x2 p0 = {(__bf16)lam[b][0], (__bf16)lam[b][1]}, p1 = {(__bf16)lam[b][2], (__bf16)lam[b][3]};
+          pk[b][2 * q] = __builtin_bit_cast(uint32_t, p0);
+          pk[b][2 * q + 1] = __builtin_bit_cast(uint32_t, p1);
+        }
       }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) store_w(a, b, pk[b]);
     }
-    double v = (double)cs;
-    v += __shfl_xor(v, 32, 64);
-    if (hi == 0) red[wave * FB + b * 32 + l32] = v;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double v = (double)cs[b];
+      v += __shfl_xor(v, 32, 64);
+      if (hi == 0) red[wave * FB + b * 32 + l32] = v;
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      float cs = 0.f;
+#pragma unroll
+      for (int a = 0; a < MB; ++a) {
+        uint32_t pk[8];  // bins 8 q + 4 hi + {0, 1} and {2, 3} for q = 0 .. 3
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t t = tt0 + 64 * wave + 32 * a + 8 * q + 4 * hi;
+          float lam[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            lam[e] = __expf(acc[a][b][4 * q + e]);
+            if (t + e >= g.B) lam[e] = 0.f;
+            cs += lam[e];
+          }
+          bf16x2 p0 = {(__bf16)lam[0], (__bf16)lam[1]}, p1 = {(__bf16)lam[2], (__bf16)lam[3]};
+          pk[2 * q] = __builtin_bit_cast(uint32_t, p0);
+          pk[2 * q + 1] = __builtin_bit_cast(uint32_t, p1);
+        }
+        store_w(a, b, pk);
+      }
+      double v = (double)cs;
+      v += __shfl_xor(v, 32, 64);
+      if (hi == 0) red[wave * FB + b * 32 + l32] = v;
+    }
   }
   __syncthreads();
   if (tid < FB) {
@@ -803,7 +889,15 @@ __device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, in
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_res_uf(ResUArgs g) {
   __shared__ __align__(16) unsigned char smem[FLDS];
   const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
-  res_uf_tile(g, logical % g.n_itiles, logical / g.n_itiles, smem);
+  res_uf_tile<false>(g, logical % g.n_itiles, logical / g.n_itiles, smem);
+}
+
+// the event grid's kernel U, also two workgroups per CU: one wave's interval
+// integrals overlap the other's MFMAs
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_res_uf_ev(ResUArgs g) {
+  __shared__ __align__(16) unsigned char smem[FLDS];
+  const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
+  res_uf_tile<true>(g, logical % g.n_itiles, logical / g.n_itiles, smem);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_res_uf_group(ResUGroup q) {
@@ -815,7 +909,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int r = find_rec(q.prefix, q.n, k);
     const ResUArgs g = q.args[r];
     const int64_t local = k - q.prefix[r];
-    res_uf_tile(g, local % g.n_itiles, local / g.n_itiles, smem);
+    res_uf_tile<false>(g, local % g.n_itiles, local / g.n_itiles, smem);
     __syncthreads();
   }
 }
@@ -956,8 +1050,10 @@ hipError_t run_g(const ResGArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <bool EV>
 hipError_t run_uf(const ResUArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_res_uf, dim3((unsigned)((int64_t)a.n_itiles * a.n_ttiles)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(EV ? k_res_uf_ev : k_res_uf, dim3((unsigned)((int64_t)a.n_itiles * a.n_ttiles)), dim3(256), 0,
+                     st, a);
   return hipGetLastError();
 }
 
@@ -1028,7 +1124,7 @@ hipError_t res_u(int shape, const ResUArgs& a, hipStream_t st) {
     case 6: return run_u<128, 2, 4, F8, EV>(a, st);
     case 7:
     case 8:
-    case 9: return (F8 || EV) ? hipErrorInvalidValue : run_uf(a, st);
+    case 9: return F8 ? hipErrorInvalidValue : run_uf<EV>(a, st);
     default: return hipErrorInvalidValue;
   }
 }

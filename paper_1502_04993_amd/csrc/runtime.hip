@@ -109,7 +109,7 @@ struct glmr_ctx {
   unsigned char* Xtj = nullptr;
   unsigned char* Xjt = nullptr;
   int res_shape_u = 1, res_shape_g = 1;  // indices into res_shapes()
-  int xfrag = 0;                         // BF16, uniform grid: Xtj and W as MFMA fragments
+  int xfrag = 0;                         // BF16: Xtj, Xjt and W as MFMA fragments
   size_t x_bytes = 0;                    // bytes of each layout as allocated
   unsigned* xmax = nullptr;              // FP8: per-chunk trace maxima
   float* xscale = nullptr;               // FP8: per-chunk trace scales
@@ -911,11 +911,11 @@ void setup_precision(glmr_ctx* c) {
   else if (c->cfg.tile_n == 256) c->tile = 256;
   else c->tile = c->N > 384 ? 256 : 128;
   gemm_tiles(c->prec, c->tile, &c->bi1, &c->bt1, &c->bi2, &c->bj2);
-  // resident-trace shapes: on the uniform grid in BF16 the fragment-major
-  // kernels (unless GLMR_XFRAG=0), else the row-major ones with 256-neuron
-  // tiles when the padding allows
+  // resident-trace shapes: in BF16 the fragment-major kernels (unless
+  // GLMR_XFRAG=0), else the row-major ones with 256-neuron tiles when the
+  // padding allows
   const char* xf = std::getenv("GLMR_XFRAG");
-  c->xfrag = (c->prec == PREC_BF16 && !c->evm && !(xf && std::strcmp(xf, "0") == 0)) ? 1 : 0;
+  c->xfrag = (c->prec == PREC_BF16 && !(xf && std::strcmp(xf, "0") == 0)) ? 1 : 0;
   if (c->xfrag) {
     c->res_shape_u = 7;
     c->res_shape_g = (c->Np % 256 == 0) ? 7 : 9;
@@ -923,8 +923,8 @@ void setup_precision(glmr_ctx* c) {
     c->res_shape_u = c->res_shape_g = 5;
   } else {
     c->res_shape_u = c->res_shape_g = (c->Np % 256 == 0) ? 2 : 3;
+    if (c->evm) c->res_shape_u = 5;  // the interval integrals: 128-neuron tiles keep kernel U unspilled
   }
-  if (c->evm) c->res_shape_u = 5;  // the interval integrals: 128-neuron tiles keep kernel U unspilled
   if (const char* e = std::getenv("GLMR_RES_SHAPE")) {
     int u = -1, g = -1;
     if (std::sscanf(e, "%d,%d", &u, &g) == 2 && shape_ok_u(c, u) && shape_ok(c, g)) {

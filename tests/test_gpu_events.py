@@ -204,10 +204,12 @@ def test_event_grid_fit_reaches_oracle_optimum():
 
 
 def test_event_grid_bf16_tile_shapes_and_autotune(tmp_path):
-    # kernel U's event-grid variant runs on the 128-neuron tiles (shapes 3-6);
-    # every one matches the oracle, they agree with each other far inside the
-    # tolerance, and the autotuner keeps the event grid's choice apart from
-    # the regular grid's in a shared cache
+    # kernel U's event-grid variants: the fragment-major kernel (shape 7, the
+    # default) with kernel G's fragment tiles 7, 8, 9, and the row-major
+    # 128-neuron tiles (shapes 3-6, GLMR_XFRAG=0); every one matches the
+    # oracle, they agree with each other far inside the tolerance, and the
+    # autotuner keeps the event grid's choice apart from the regular grid's in
+    # a shared cache
     import os
     G = _G()
     N = 512
@@ -217,18 +219,22 @@ def test_event_grid_bf16_tile_shapes_and_autotune(tmp_path):
     J = _round(rec.J, "bf16")
     ref = O.continuous_eval(_lists(times, neu, N), T0, T1, rec.tau, J, rec.mu)
     lls = []
-    for k in (3, 4, 5, 6):
-        os.environ["GLMR_RES_SHAPE"] = f"{k},2"
+    for u, g, frag in [(7, 7, True), (7, 8, True), (7, 9, True), (3, 2, False), (4, 2, False), (5, 2, False),
+                       (6, 2, False)]:
+        os.environ["GLMR_RES_SHAPE"] = f"{u},{g}"
+        if not frag:
+            os.environ["GLMR_XFRAG"] = "0"
         try:
             c, slots = _ctx(N, times, neu, T0, T1, "bf16")
         finally:
             os.environ.pop("GLMR_RES_SHAPE", None)
+            os.environ.pop("GLMR_XFRAG", None)
         c.set_kernel(rec.tau)
         c.set_params(J, rec.mu)
         r = c.eval(grad=True)
-        assert c.query()["trace_resident"]
+        assert c.query()["trace_resident"] and c.query()["trace_frag"] == frag
         c.close()
-        _compare(r, ref, "bf16", slots, N, f"shape {k}")
+        _compare(r, ref, "bf16", slots, N, f"shape {u},{g}")
         lls.append(r["ll"])
     assert max(abs(v - lls[0]) for v in lls) <= 1e-9 * abs(lls[0])
     cache = str(tmp_path / "tune.txt")
@@ -237,7 +243,7 @@ def test_event_grid_bf16_tile_shapes_and_autotune(tmp_path):
     c.set_params(J, rec.mu)
     u, g = c.autotune(cache)
     c.close()
-    assert u in (3, 4, 5, 6) and 0 <= g <= 6
+    assert u == 7 and g in (7, 8, 9)
     grid = G.Context(N, rec.n_bins, rec.dt, "bf16")
     grid.set_spikes(rec.bins, rec.neurons)
     grid.set_kernel(rec.tau)
