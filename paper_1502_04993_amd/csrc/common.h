@@ -300,17 +300,25 @@ struct ResShape {
 const ResShape* res_shapes(int* n);
 // Work queue of a grouped (many-recording) launch: args[r] describes recording
 // r's chunk; its tiles are k in [prefix[r], prefix[r + 1]) of [0, total).
+// The fragment-major kernels take one workgroup per tile and split every
+// recording's tiles evenly over the 8 XCDs (workgroup b runs on XCD b % 8):
+// xprefix[x][r] (row x of 8, n + 1 entries) counts the tiles XCD x takes
+// from recordings before r, and xgrid workgroups cover the largest share.
 struct ResUGroup {
   const ResUArgs* args;    // device [n]
   const int64_t* prefix;   // device [n + 1]
   int n;
   int64_t total;
+  const int64_t* xprefix;  // device [8][n + 1]
+  int64_t xgrid;
 };
 struct ResGGroup {
   const ResGArgs* args;
   const int64_t* prefix;
   int n;
   int64_t total;
+  const int64_t* xprefix;
+  int64_t xgrid;
 };
 hipError_t launch_res_u_group(int shape, int fp8, const ResUGroup& q, hipStream_t st);
 hipError_t launch_res_g_group(int shape, int fp8, const ResGGroup& q, hipStream_t st);

@@ -656,8 +656,16 @@ constexpr int FLDS = 2 * FB * ROWB;        // its double buffer (bytes)
 // uniform base sits in scalar registers, a lane's offset in one 32-bit
 // register (constant over the k loop) and the k step's offset in a scalar,
 // so the loop does no 64-bit address arithmetic; reads past `bytes` return 0.
+// Base and size are wave-uniform by construction; reading them from the
+// first lane says so to the compiler, which otherwise wraps every load in a
+// loop over distinct values when they come from memory (the grouped kernels'
+// per-recording arguments).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+  const uint64_t b = (uint64_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  void* ub = (void*)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
 __device__ __forceinline__ f32x16 mma_bf16(const i32x4& a, const i32x4& b, const f32x16& c) {
@@ -900,18 +908,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   res_uf_tile<true>(g, logical % g.n_itiles, logical / g.n_itiles, smem);
 }
 
+// The grouped fragment-major kernels: one workgroup per tile, each
+// recording's tiles split evenly over the XCDs in contiguous runs, as a
+// launch of that recording alone would place them (consecutive tiles share
+// an L2; every XCD meets every recording's work in turn, so tiles of uneven
+// cost stay balanced).  Workgroup b is the (b / 8)-th on XCD b % 8; its
+// recording r and tile follow from that XCD's prefix row.  The recording's
+// arguments are read into scalar registers (the values are the same in
+// every lane).  Returns false for the workgroups past the XCD's share.
+template <typename A, typename Q>
+__device__ __forceinline__ bool striped_tile(const Q& q, A& g, int64_t& local) {
+  const int x = (int)(blockIdx.x % 8);
+  const int64_t idx = blockIdx.x / 8;
+  const int64_t* __restrict__ px = q.xprefix + (int64_t)x * (q.n + 1);
+  if (idx >= px[q.n]) return false;
+  const int r = __builtin_amdgcn_readfirstlane(find_rec(px, q.n, idx));
+  const int64_t t = q.prefix[r + 1] - q.prefix[r];
+  local = x * (t / 8) + (x < t % 8 ? x : t % 8) + (idx - px[r]);
+  const uint32_t* src = (const uint32_t*)(q.args + r);
+  uint32_t* dst = (uint32_t*)&g;
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(A) / 4); ++w) dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
+  return true;
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_res_uf_group(ResUGroup q) {
   __shared__ __align__(16) unsigned char smem[FLDS];
-  const int64_t rank = xcd_logical(blockIdx.x, gridDim.x);
-  for (int64_t base = 0; base < q.total; base += gridDim.x) {
-    const int64_t k = base + rank;
-    if (k >= q.total) break;
-    const int r = find_rec(q.prefix, q.n, k);
-    const ResUArgs g = q.args[r];
-    const int64_t local = k - q.prefix[r];
-    res_uf_tile<false>(g, local % g.n_itiles, local / g.n_itiles, smem);
-    __syncthreads();
-  }
+  ResUArgs g;
+  int64_t local;
+  if (!striped_tile(q, g, local)) return;
+  res_uf_tile<false>(g, local % g.n_itiles, local / g.n_itiles, smem);
 }
 
 // Kernel G: tile (128 MB) x 128 of (i, j) over one split of the chunk's bins,
@@ -973,15 +999,10 @@ template <int MB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB == 4 ? 1 : 2))) void k_res_gf_group(
     ResGGroup q) {
   __shared__ __align__(16) unsigned char smem[FLDS];
-  const int64_t rank = xcd_logical(blockIdx.x, gridDim.x);
-  for (int64_t base = 0; base < q.total; base += gridDim.x) {
-    const int64_t k = base + rank;
-    if (k >= q.total) break;
-    const int r = find_rec(q.prefix, q.n, k);
-    const ResGArgs g = q.args[r];
-    res_gf_tile<MB>(g, k - q.prefix[r], smem);
-    __syncthreads();
-  }
+  ResGArgs g;
+  int64_t local;
+  if (!striped_tile(q, g, local)) return;
+  res_gf_tile<MB>(g, local, smem);
 }
 
 template <typename K>
@@ -1064,15 +1085,27 @@ hipError_t run_gf(const ResGArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename Q>
+hipError_t striped_grid(const Q& q, unsigned* grid) {
+  if (!q.xprefix || q.xgrid < 1 || q.xgrid > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;
+  *grid = (unsigned)q.xgrid;
+  return hipSuccess;
+}
+
 hipError_t run_uf_group(const ResUGroup& q, hipStream_t st) {
-  hipLaunchKernelGGL(k_res_uf_group, dim3(persistent_grid(k_res_uf_group, 256, 0, q.total)), dim3(256), 0, st, q);
+  unsigned grid = 0;
+  const hipError_t e = striped_grid(q, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_res_uf_group, dim3(grid), dim3(256), 0, st, q);
   return hipGetLastError();
 }
 
 template <int MB>
 hipError_t run_gf_group(const ResGGroup& q, hipStream_t st) {
-  auto kern = k_res_gf_group<MB>;
-  hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, 256, 0, q.total)), dim3(256), 0, st, q);
+  unsigned grid = 0;
+  const hipError_t e = striped_grid(q, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_res_gf_group<MB>, dim3(grid), dim3(256), 0, st, q);
   return hipGetLastError();
 }
 

@@ -1256,6 +1256,8 @@ struct glmr_batch {
     ResGArgs* dg = nullptr;
     int64_t *pu = nullptr, *pg = nullptr;
     int64_t tu = 0, tg = 0;
+    int64_t *xu = nullptr, *xg = nullptr;  // [8][m + 1] per-XCD tile prefixes (fragment-major kernels)
+    int64_t gu = 0, gg = 0;                // their launch grids
   };
   struct Chunk {         // the recordings that have time chunk ci
     std::vector<Group> groups;
@@ -1369,6 +1371,24 @@ glmr_status build_queues(glmr_batch* b) {
       HIPCHK(c0, hipMemcpy(gr.pg, li.pg.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
       gr.tu = li.pu.back();
       gr.tg = li.pg.back();
+      // each recording's tiles split evenly over the 8 XCDs (see ResUGroup)
+      auto stripes = [&](const std::vector<int64_t>& pre, int64_t*& dst, int64_t* grid) -> glmr_status {
+        std::vector<int64_t> x(8 * (m + 1), 0);
+        int64_t most = 0;
+        for (int xc = 0; xc < 8; ++xc) {
+          for (size_t r = 0; r < m; ++r) {
+            const int64_t t = pre[r + 1] - pre[r];
+            x[xc * (m + 1) + r + 1] = x[xc * (m + 1) + r] + t / 8 + (xc < t % 8 ? 1 : 0);
+          }
+          most = std::max(most, x[xc * (m + 1) + m]);
+        }
+        HIPCHK(c0, balloc(b, dst, x.size()));
+        HIPCHK(c0, hipMemcpy(dst, x.data(), x.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        *grid = 8 * most;
+        return GLMR_OK;
+      };
+      TRY(stripes(li.pu, gr.xu, &gr.gu));
+      TRY(stripes(li.pg, gr.xg, &gr.gg));
     }
   }
   return GLMR_OK;
@@ -1382,11 +1402,11 @@ glmr_status launch_chunk_groups(glmr_batch* b, size_t ci, bool want_u, bool want
     const int m = (int)gr.recs.size();
     if (want_u) {
       ProfScope ps(c0, K_BU);
-      HIPCHK(c0, launch_res_u_group(gr.su, fp8, ResUGroup{gr.du, gr.pu, m, gr.tu}, b->st));
+      HIPCHK(c0, launch_res_u_group(gr.su, fp8, ResUGroup{gr.du, gr.pu, m, gr.tu, gr.xu, gr.gu}, b->st));
     }
     if (want_g) {
       ProfScope ps(c0, K_BG);
-      HIPCHK(c0, launch_res_g_group(gr.sg, fp8, ResGGroup{gr.dg, gr.pg, m, gr.tg}, b->st));
+      HIPCHK(c0, launch_res_g_group(gr.sg, fp8, ResGGroup{gr.dg, gr.pg, m, gr.tg, gr.xg, gr.gg}, b->st));
     }
   }
   return GLMR_OK;
