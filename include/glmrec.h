@@ -337,9 +337,11 @@ glmr_status glmr_set_state(glmr_ctx* ctx, const void* buf, size_t len);
 /* ---------------------------------------------------------------- batching
  * Many independent recordings (contexts of possibly different N and B, all
  * on one device, all in GLMR_BF16 or all in the same precision) evaluated in
- * persistent launches with a work queue over (recording, time tile, neuron
+ * grouped launches with a work queue over (recording, time tile, neuron
  * tile): recordings with the same tile shapes share one launch per
- * contraction.  Each recording takes the shapes the batch autotuner chose
+ * contraction (the fragment-major kernels: one workgroup per tile, each
+ * recording's tiles spread evenly over the XCDs; the row-major kernels:
+ * persistent workgroups walking the queue).  Each recording takes the shapes the batch autotuner chose
  * for its class (padding that allows 256-neuron tiles, or not), else its
  * context's own, so that a batch evaluation equals each context's own
  * evaluation with those shapes.  The contexts must each have had set_spikes,
