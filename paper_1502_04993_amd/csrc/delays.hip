@@ -80,6 +80,25 @@ __device__ inline void w_store(void* W, int64_t k, double v) {
   ((WT*)W)[k] = (WT)v;
 }
 
+// One bin's correction: lambda_i[t] (W[k], times a^m where the rebuild
+// kernels stored it so) times exp(J_ii Delta), written back; returns lambda.
+template <typename WT>
+__device__ inline double self_delay_bin(const SelfDelayArgs& a, int64_t k, double jd, double delta, int m) {
+  // the factor in FP64, except for BF16 weights, whose rounding (2^-9) is far
+  // above the FP32 exponential's error (the FP32 mode holds L to 1e-10)
+  const double c = std::is_same<WT, __bf16>::value ? (double)expf((float)(jd * delta)) : exp(jd * delta);
+  double lam;
+  if (a.scaled) {  // the rebuild kernels store W a^m
+    const double pw = a.x.tab->pw[m];
+    lam = w_load<WT>(a.W, k) / pw * c;
+    w_store<WT>(a.W, k, lam * pw);
+  } else {
+    lam = w_load<WT>(a.W, k) * c;
+    w_store<WT>(a.W, k, lam);
+  }
+  return lam;
+}
+
 // one wave per (neuron, tile of a.tb bins of the chunk: the row-sum tile of
 // kernel U); lane = tb / 64 consecutive bins
 template <typename WT>
@@ -103,20 +122,8 @@ __global__ __launch_bounds__(256) void k_self_delay(SelfDelayArgs a) {
     xs = dec * xs + spikes_at(a.x, i, t - a.ds);
     xd = dec * xd + spikes_at(a.x, i, t - a.d);
     if (t >= a.B) continue;
-    // the factor in FP64, except for BF16 weights, whose rounding (2^-9) is far
-    // above the FP32 exponential's error (the FP32 mode holds L to 1e-10)
-    const double c = std::is_same<WT, __bf16>::value ? (double)expf((float)(jd * delta)) : exp(jd * delta);
     const int64_t tc = tl0 + tl;  // chunk-local bin
-    const int64_t k = w_elem(a.tiled, i, tc, a.x.Np, a.L);
-    double lam;
-    if (a.scaled) {  // the rebuild kernels store W a^m
-      const double pw = a.x.tab->pw[tl & 63];
-      lam = w_load<WT>(a.W, k) / pw * c;
-      w_store<WT>(a.W, k, lam * pw);
-    } else {
-      lam = w_load<WT>(a.W, k) * c;
-      w_store<WT>(a.W, k, lam);
-    }
+    const double lam = self_delay_bin<WT>(a, w_elem(a.tiled, i, tc, a.x.Np, a.L), jd, delta, tl & 63);
     s_lam += lam;
     s_gd += lam * delta;
   }
@@ -128,6 +135,40 @@ __global__ __launch_bounds__(256) void k_self_delay(SelfDelayArgs a) {
   if (lane == 0) {
     a.rowpart[(tt0 / a.tb) * a.x.Np + i] = s_lam;
     a.gpart[(tt0 / a.tb) * a.x.Np + i] = s_gd;
+  }
+}
+
+// The same with W as MFMA fragments (layout 2, 256-bin row-sum tiles): one
+// wave per (32-neuron block, 256-bin tile), lane l on neuron l % 32 of the
+// block and the tile's bins 128 (l / 32) .. + 128 in order.  At each bin the
+// 32 lanes of a half-wave touch one 512-byte run of W (their fragment slots),
+// where a wave per neuron would touch 16-byte pieces 512 bytes apart.
+template <typename WT>
+__global__ __launch_bounds__(256) void k_self_delay_frag(SelfDelayArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + (lane & 31);
+  const int64_t tile0 = (int64_t)blockIdx.y * 256;       // chunk-local first bin of the tile
+  const int64_t tl0 = tile0 + 128 * (lane >> 5);         // the lane's first bin
+  const double jd = a.Jr[i * a.x.Np + i];
+  const double dec = a.x.tab->pw[1];
+  double s_lam = 0.0, s_gd = 0.0;
+  double xs = trace_at(a.x, i, a.t0 + tl0 - a.ds), xd = trace_at(a.x, i, a.t0 + tl0 - a.d);
+  for (int e = 0; e < 128; ++e) {
+    const int64_t t = a.t0 + tl0 + e;
+    const double delta = xs - xd;
+    xs = dec * xs + spikes_at(a.x, i, t - a.ds);
+    xd = dec * xd + spikes_at(a.x, i, t - a.d);
+    if (t >= a.B) continue;
+    const double lam = self_delay_bin<WT>(a, w_elem(2, i, tl0 + e, a.x.Np, a.L), jd, delta, (int)(t & 63));
+    s_lam += lam;
+    s_gd += lam * delta;
+  }
+  s_lam += __shfl_xor(s_lam, 32, 64);
+  s_gd += __shfl_xor(s_gd, 32, 64);
+  if (lane < 32) {
+    const int64_t row = (a.t0 + tile0) / 256;
+    a.rowpart[row * a.x.Np + i] = s_lam;
+    a.gpart[row * a.x.Np + i] = s_gd;
   }
 }
 
@@ -180,6 +221,12 @@ hipError_t launch_shift_masks(const uint64_t* src, uint64_t* dst, int planes, in
 
 hipError_t launch_self_delay(const SelfDelayArgs& a, hipStream_t st) {
   if ((a.tb != 128 && a.tb != 256) || a.Lc % a.tb) return hipErrorInvalidValue;
+  if (a.tiled == 2) {
+    if (a.tb != 256 || a.x.Np % 128 || a.wtype != 2 || a.scaled) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_self_delay_frag<__bf16>, dim3((unsigned)(a.x.Np / 128), (unsigned)(a.Lc / 256)), dim3(256),
+                       0, st, a);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)(a.x.Np / 4), (unsigned)(a.Lc / a.tb));
   switch (a.wtype) {
     case 0: hipLaunchKernelGGL(k_self_delay<double>, grid, dim3(256), 0, st, a); break;
