@@ -66,6 +66,32 @@ def test_every_shape_agrees_and_matches_oracle():
         assert np.linalg.norm(g - grads[0]) / np.linalg.norm(grads[0]) < 1e-5
 
 
+@pytest.mark.parametrize("shape", [0, 3, 4, 5, 6])
+def test_fp8_shapes_match_oracle(shape):
+    """FP8 on each tile shape it offers (the row-major kernels): each within
+    the FP8 bounds of the oracle at the FP8-rounded J."""
+    import paper_1502_04993_amd as G
+    from test_gpu_parity import TOL, round_fp8_rows
+    rec = synth.balanced(N=512, B=40_000, seed=24)
+    J8 = round_fp8_rows(rec.J)
+    ref = O.loglik(rec.bins, rec.neurons, rec.n_neurons, rec.n_bins, rec.dt, rec.tau, J8, rec.mu)
+    old = os.environ.pop("GLMR_RES_SHAPE", None)
+    os.environ["GLMR_RES_SHAPE"] = f"{shape},{shape}"
+    try:
+        ctx = G.Context(rec.n_neurons, rec.n_bins, rec.dt, precision="fp8")
+    finally:
+        os.environ.pop("GLMR_RES_SHAPE", None)
+        if old is not None:
+            os.environ["GLMR_RES_SHAPE"] = old
+    ctx.set_spikes(rec.bins, rec.neurons)
+    ctx.set_kernel(rec.tau)
+    ctx.set_params(J8, rec.mu)
+    r = ctx.eval(grad=True)
+    assert ctx.query()["trace_resident"] and not ctx.query()["trace_frag"]
+    ctx.close()
+    check(f"fp8 shape {shape}", r, ref, TOL["fp8"])
+
+
 @pytest.mark.parametrize("frag", [True, False])
 def test_autotune_picks_valid_shapes_and_caches(tmp_path, frag):
     rec = synth.balanced(N=384, B=30_000, seed=22)  # Np = 384: only the 128-neuron tiles fit
