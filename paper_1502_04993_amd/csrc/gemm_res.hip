@@ -680,15 +680,16 @@ __device__ __forceinline__ f32x16 mma_bf16(const i32x4& a, const i32x4& b, const
 // 128 bytes.  Acc element r of lane l of block (a, b) is row 32 a + 8 (r / 4)
 // + 4 (l / 32) + r % 4 of the wave's rows, column 32 b + l % 32 of the 128
 // columns.
-template <int MB, bool BFRAG, typename GA, typename GB>
+template <int MB, bool BFRAG, typename GA, typename GB, int NT = 256>
 __device__ __forceinline__ void frag_loop(int nk, GA ga, GB gb, unsigned char* smem, f32x16 (&acc)[MB][4]) {
+  constexpr int PQ = 1024 / NT;  // 16-byte pieces of B per thread and step
   const int tid = threadIdx.x, lane = tid & 63;
   const int l32 = lane & 31, hi = lane >> 5;
-  i32x4 an[MB][4], bn[4];
+  i32x4 an[MB][4], bn[PQ];
   auto sb = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int p = tid + 256 * q, r = p >> 3, c = p & 7;
+    for (int q = 0; q < PQ; ++q) {
+      const int p = tid + NT * q, r = p >> 3, c = p & 7;
       *(i32x4*)(smem + buf * (FB * ROWB) + (BFRAG ? p * 16 : r * ROWB + c * 16)) = bn[q];
     }
   };
@@ -940,18 +941,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   res_uf_tile<false>(g, local % g.n_itiles, local / g.n_itiles, smem);
 }
 
-// Kernel G: tile (128 MB) x 128 of (i, j) over one split of the chunk's bins,
-// 4 waves of 32 MB rows x 128 columns.  A = W's fragments (rows i), B = the
-// fragments of Xjt's rows j0 .. j0 + 127, copied to LDS as they lie.
-template <int MB>
+// Kernel G: tile (32 MB NW) x 128 of (i, j) over one split of the chunk's
+// bins, NW waves of 32 MB rows x 128 columns.  A = W's fragments (rows i), B =
+// the fragments of Xjt's rows j0 .. j0 + 127, copied to LDS as they lie and
+// shared by the NW waves.
+template <int MB, int NW = 4>
 __device__ __forceinline__ void res_gf_tile(const ResGArgs& g, int64_t logical, unsigned char* smem) {
+  constexpr int NT = 64 * NW, PQ = 1024 / NT;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l32 = lane & 31, hi = lane >> 5;
   const int64_t jtile = logical % g.n_jtiles;
   const int64_t itile = (logical / g.n_jtiles) % g.n_itiles;
   const int64_t split = logical / ((int64_t)g.n_jtiles * g.n_itiles);
-  const int64_t i0 = itile * (4 * 32 * MB), j0 = jtile * FB;
+  const int64_t i0 = itile * (NW * 32 * MB), j0 = jtile * FB;
   const int64_t tb = split * g.ks;
   const int64_t te = (tb + g.ks < g.Lc) ? tb + g.ks : g.Lc;
   const int64_t wkb = g.L / 16, xkb = g.Bp / 16;
@@ -963,20 +966,25 @@ __device__ __forceinline__ void res_gf_tile(const ResGArgs& g, int64_t logical, 
 #pragma unroll
   for (int q = 0; q < 4; ++q)
     xr[q] = buf_rsrc((const unsigned char*)g.Xjt + (((j0 >> 5) + q) * xkb + (g.t0 + tb) / 16) * 1024, span);
-  const int va = lane * 16, vb = wave * 1024 + lane * 16;
+  // piece p = tid + NT q of a step's 16 KB: row block p / 256 (uniform over a
+  // wave), k block p / 64 % 4, lane p % 64
+  const int va = lane * 16, vb = (wave & 3) * 1024 + lane * 16;
   auto ga = [&](int ks, i32x4 (&an)[MB][4]) {
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc) an[a][kc] = __builtin_amdgcn_raw_buffer_load_b128(wr[a], va + kc * 1024, ks * 4096, 0);
   };
-  auto gb = [&](int ks, i32x4 (&bn)[4]) {
+  auto gb = [&](int ks, i32x4 (&bn)[PQ]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) bn[q] = __builtin_amdgcn_raw_buffer_load_b128(xr[q], vb, ks * 4096, 0);
+    for (int q = 0; q < PQ; ++q) {
+      const int rb = NW == 4 ? q : 2 * q + (wave >> 2);
+      bn[q] = __builtin_amdgcn_raw_buffer_load_b128(xr[rb], vb, ks * 4096, 0);
+    }
   };
   f32x16 acc[MB][4];
   zero_acc(acc);
-  frag_loop<MB, true>((int)((te - tb) / 64), ga, gb, smem, acc);
+  frag_loop<MB, true, decltype(ga), decltype(gb), NT>((int)((te - tb) / 64), ga, gb, smem, acc);
   float* __restrict__ Gp = (float*)g.Gp + split * g.Np * g.Np;
 #pragma unroll
   for (int a = 0; a < MB; ++a)
@@ -989,20 +997,21 @@ __device__ __forceinline__ void res_gf_tile(const ResGArgs& g, int64_t logical, 
       }
 }
 
-template <int MB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB == 4 ? 1 : 2))) void k_res_gf(ResGArgs g) {
+template <int MB, int NW = 4>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MB == 4 || NW == 8 ? 1 : 2))) void k_res_gf(
+    ResGArgs g) {
   __shared__ __align__(16) unsigned char smem[FLDS];
-  res_gf_tile<MB>(g, xcd_logical(blockIdx.x, gridDim.x), smem);
+  res_gf_tile<MB, NW>(g, xcd_logical(blockIdx.x, gridDim.x), smem);
 }
 
-template <int MB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB == 4 ? 1 : 2))) void k_res_gf_group(
-    ResGGroup q) {
+template <int MB, int NW = 4>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MB == 4 || NW == 8 ? 1 : 2))) void
+k_res_gf_group(ResGGroup q) {
   __shared__ __align__(16) unsigned char smem[FLDS];
   ResGArgs g;
   int64_t local;
   if (!striped_tile(q, g, local)) return;
-  res_gf_tile<MB>(g, local, smem);
+  res_gf_tile<MB, NW>(g, local, smem);
 }
 
 template <typename K>
@@ -1078,10 +1087,10 @@ hipError_t run_uf(const ResUArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int MB>
+template <int MB, int NW = 4>
 hipError_t run_gf(const ResGArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_res_gf<MB>, dim3((unsigned)((int64_t)a.n_splits * a.n_itiles * a.n_jtiles)), dim3(256), 0,
-                     st, a);
+  hipLaunchKernelGGL((k_res_gf<MB, NW>), dim3((unsigned)((int64_t)a.n_splits * a.n_itiles * a.n_jtiles)),
+                     dim3(64 * NW), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1100,12 +1109,12 @@ hipError_t run_uf_group(const ResUGroup& q, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int MB>
+template <int MB, int NW = 4>
 hipError_t run_gf_group(const ResGGroup& q, hipStream_t st) {
   unsigned grid = 0;
   const hipError_t e = striped_grid(q, &grid);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_res_gf_group<MB>, dim3(grid), dim3(256), 0, st, q);
+  hipLaunchKernelGGL((k_res_gf_group<MB, NW>), dim3(grid), dim3(64 * NW), 0, st, q);
   return hipGetLastError();
 }
 
@@ -1131,15 +1140,15 @@ hipError_t launch_build_x8(const ResXArgs& a, hipStream_t st) {
 // 0 .. 6: the row-major kernels (neuron tile BM x 256 bins for U, BM x BM for
 // G) with their wave grids.  The 8-wave 256-neuron tiles need more than the
 // 256 registers a wave may hold at two waves per SIMD once the fragments are
-// FP8 (32 bytes a lane), so FP8 skips them.  7 .. 9: the fragment-major
-// kernels (BF16, uniform grid): one kernel U, kernel G with 256, 512 or 128
-// rows per tile.
+// FP8 (32 bytes a lane), so FP8 skips them.  7 .. 10: the fragment-major
+// kernels (BF16): one kernel U, kernel G with 256, 512 or 128 rows per tile
+// of 4 waves, or 512 rows of 8 waves.
 const ResShape* res_shapes(int* n) {
   static const ResShape s[] = {
       {256, 256, 256, 2, 2, 1, 0, 1}, {256, 256, 256, 2, 4, 0, 0, 1}, {256, 256, 256, 4, 2, 0, 0, 1},
       {128, 128, 128, 2, 2, 1, 0, 1}, {128, 128, 128, 1, 4, 1, 0, 1}, {128, 128, 128, 4, 2, 1, 0, 1},
       {128, 128, 128, 2, 4, 1, 0, 1}, {128, 256, 128, 4, 1, 0, 1, 1}, {128, 512, 128, 4, 1, 0, 1, 0},
-      {128, 128, 128, 4, 1, 0, 1, 0},
+      {128, 128, 128, 4, 1, 0, 1, 0}, {128, 512, 128, 8, 1, 0, 1, 0},
   };
   *n = (int)(sizeof(s) / sizeof(s[0]));
   return s;
@@ -1157,7 +1166,8 @@ hipError_t res_u(int shape, const ResUArgs& a, hipStream_t st) {
     case 6: return run_u<128, 2, 4, F8, EV>(a, st);
     case 7:
     case 8:
-    case 9: return F8 ? hipErrorInvalidValue : run_uf<EV>(a, st);
+    case 9:
+    case 10: return F8 ? hipErrorInvalidValue : run_uf<EV>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1175,6 +1185,7 @@ hipError_t res_g(int shape, const ResGArgs& a, hipStream_t st) {
     case 7: return F8 ? hipErrorInvalidValue : run_gf<2>(a, st);
     case 8: return F8 ? hipErrorInvalidValue : run_gf<4>(a, st);
     case 9: return F8 ? hipErrorInvalidValue : run_gf<1>(a, st);
+    case 10: return F8 ? hipErrorInvalidValue : run_gf<2, 8>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1191,7 +1202,8 @@ hipError_t res_u_group(int shape, const ResUGroup& q, hipStream_t st) {
     case 6: return run_u_group<128, 2, 4, F8>(q, st);
     case 7:
     case 8:
-    case 9: return F8 ? hipErrorInvalidValue : run_uf_group(q, st);
+    case 9:
+    case 10: return F8 ? hipErrorInvalidValue : run_uf_group(q, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1209,6 +1221,7 @@ hipError_t res_g_group(int shape, const ResGGroup& q, hipStream_t st) {
     case 7: return F8 ? hipErrorInvalidValue : run_gf_group<2>(q, st);
     case 8: return F8 ? hipErrorInvalidValue : run_gf_group<4>(q, st);
     case 9: return F8 ? hipErrorInvalidValue : run_gf_group<1>(q, st);
+    case 10: return F8 ? hipErrorInvalidValue : run_gf_group<2, 8>(q, st);
     default: return hipErrorInvalidValue;
   }
 }

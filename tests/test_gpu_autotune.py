@@ -4,7 +4,7 @@ Kernel U accumulates every V in the same k order whatever the tile shape;
 the shapes differ only in how the FP32 sums of exp(V) over a wave's bins
 are grouped before the FP64 sums, and kernel G's in how its FP32 partials
 are grouped over time.  So all shapes agree far inside the BF16 tolerance.
-Shapes 0-6 are the row-major kernels (GLMR_XFRAG=0), 7-9 the fragment-major
+Shapes 0-6 are the row-major kernels (GLMR_XFRAG=0), 7-10 the fragment-major
 ones (the default for BF16 on the uniform grid).
 """
 import os
@@ -19,8 +19,8 @@ from oracle import glm_oracle as O
 
 pytestmark = pytest.mark.gpu
 
-N_SHAPES = 10
-FRAG = (7, 8, 9)
+N_SHAPES = 11
+FRAG = (7, 8, 9, 10)
 
 
 def _ctx(rec, shape=None, frag=True):
