@@ -917,8 +917,10 @@ void setup_precision(glmr_ctx* c) {
   const char* xf = std::getenv("GLMR_XFRAG");
   c->xfrag = (c->prec == PREC_BF16 && !(xf && std::strcmp(xf, "0") == 0)) ? 1 : 0;
   if (c->xfrag) {
+    // kernel G: 512-row tiles of 8 waves where the padding allows (each
+    // operand byte fetched from HBM once), else 256 or 128 rows of 4 waves
     c->res_shape_u = 7;
-    c->res_shape_g = (c->Np % 256 == 0) ? 7 : 9;
+    c->res_shape_g = (c->Np % 512 == 0) ? 10 : (c->Np % 256 == 0) ? 7 : 9;
   } else if (c->prec == PREC_FP8) {
     c->res_shape_u = c->res_shape_g = 5;
   } else {

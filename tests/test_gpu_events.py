@@ -205,7 +205,7 @@ def test_event_grid_fit_reaches_oracle_optimum():
 
 def test_event_grid_bf16_tile_shapes_and_autotune(tmp_path):
     # kernel U's event-grid variants: the fragment-major kernel (shape 7, the
-    # default) with kernel G's fragment tiles 7, 8, 9, and the row-major
+    # default) with kernel G's fragment tiles 7, 8, 9, 10, and the row-major
     # 128-neuron tiles (shapes 3-6, GLMR_XFRAG=0); every one matches the
     # oracle, they agree with each other far inside the tolerance, and the
     # autotuner keeps the event grid's choice apart from the regular grid's in
@@ -219,7 +219,7 @@ def test_event_grid_bf16_tile_shapes_and_autotune(tmp_path):
     J = _round(rec.J, "bf16")
     ref = O.continuous_eval(_lists(times, neu, N), T0, T1, rec.tau, J, rec.mu)
     lls = []
-    for u, g, frag in [(7, 7, True), (7, 8, True), (7, 9, True), (3, 2, False), (4, 2, False), (5, 2, False),
+    for u, g, frag in [(7, 7, True), (7, 8, True), (7, 9, True), (7, 10, True), (3, 2, False), (4, 2, False), (5, 2, False),
                        (6, 2, False)]:
         os.environ["GLMR_RES_SHAPE"] = f"{u},{g}"
         if not frag:
