@@ -380,9 +380,13 @@ constexpr uint32_t SR_WT = 0x85EBCA6Bu, SR_WI = 0xC2B2AE35u;  // rounding bits o
 // The quadrature and FP64 tiers of the interval integrals, out of line: few
 // intervals leave the expansion's bound, and inlined at every one of kernel
 // U's unrolled call sites this code would quadruple the kernel and its
-// register demand.
-__device__ __attribute__((noinline)) void ev_rare_tier(const float* o, double delta, float D, float* F, float* H) {
-  glmr_ev::gl_tier_f(o, delta, D, F, H);
+// register demand.  F and H come back in registers (as results through
+// pointers they would live in the stack, written at every call site whether
+// the call is taken or not).
+__device__ __attribute__((noinline)) float2 ev_rare_tier(const float* o, double delta, float D) {
+  float F, H;
+  glmr_ev::gl_tier_f(o, delta, D, &F, &H);
+  return float2{F, H};
 }
 
 constexpr int EVTS = 20;  // floats per slot of kernel U's staged expansion table (80 B: 16 used)
@@ -460,13 +464,19 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
 #pragma unroll
           for (int b = 0; b < T::NB; ++b) {
             const float D = acc[a][b][4 * q + e];
+            // the expansion's F joins the sum before the branch and the
+            // rare tier's inside it: no value is merged across the call,
+            // which would otherwise be kept in memory around it
             float F, H;
-            if (!glmr_ev::taylor_f(c, D, &F, &H)) {
+            const bool ok = glmr_ev::taylor_f(c, D, &F, &H);
+            cs[b] += ok ? F : 0.f;
+            if (!ok) {
               const int64_t t = tt0 + tq + e;  // t < B: slots past it are within the bound
-              ev_rare_tier(g.evgl + t * 16, g.evdelta[t], D, &F, &H);
+              const float2 r = ev_rare_tier(g.evgl + t * 16, g.evdelta[t], D);
+              cs[b] += r.x;
+              H = r.y;
             }
             lam[b][e] = H;
-            cs[b] += F;
           }
         }
 #pragma unroll
@@ -833,13 +843,19 @@ __device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, in
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const float D = acc[a][b][4 * q + e];
+            // the expansion's F joins the sum before the branch and the
+            // rare tier's inside it: no value is merged across the call,
+            // which would otherwise be kept in memory around it
             float F, H;
-            if (!glmr_ev::taylor_f(c, D, &F, &H)) {
+            const bool ok = glmr_ev::taylor_f(c, D, &F, &H);
+            cs[b] += ok ? F : 0.f;
+            if (!ok) {
               const int64_t t = tt0 + tq + e;  // t < B: slots past it are within the bound
-              ev_rare_tier(g.evgl + t * 16, g.evdelta[t], D, &F, &H);
+              const float2 r = ev_rare_tier(g.evgl + t * 16, g.evdelta[t], D);
+              cs[b] += r.x;
+              H = r.y;
             }
             lam[b][e] = H;
-            cs[b] += F;
           }
         }
 #pragma unroll
