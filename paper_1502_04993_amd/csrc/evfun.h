@@ -337,24 +337,27 @@ GLMR_HD inline void table_f(double delta, float* o) {
   o[15] = f.ok ? 1.0f : 0.0f;
 }
 
-// The second and third tiers from the table's quadrature half: 6-point
-// Gauss-Legendre in FP32 where delta <= 0.5 and |D| delta <= 1, else the FP64
-// evaluation.
-GLMR_HD inline void gl_tier_f(const float* o, double delta, float D, float* F, float* H) {
-  const float half = o[8];
-  if (o[15] != 0.0f && fabsf(D) * (2.0f * half) <= 1.0f) {
-    const float wn[3] = {4.67913934572691370e-01f, 3.60761573048138939e-01f, 1.71324492379169746e-01f};
-    float sf = 0.0f, sh = 0.0f;
+// The second tier from the table's quadrature half q (its entries 8 .. 15:
+// delta/2, the six nodes, the flag): 6-point Gauss-Legendre in FP32 where
+// delta <= 0.5 and |D| delta <= 1; returns whether it applies.
+GLMR_HD inline bool gl_quad_f(const float* q, float D, float* F, float* H) {
+  const float half = q[0];
+  if (!(q[7] != 0.0f && fabsf(D) * (2.0f * half) <= 1.0f)) return false;
+  const float wn[3] = {4.67913934572691370e-01f, 3.60761573048138939e-01f, 1.71324492379169746e-01f};
+  float sf = 0.0f, sh = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float v = half * wn[k >> 1] * expf(D * o[9 + k]);
-      sf += v;
-      sh += v * o[9 + k];
-    }
-    *F = sf;
-    *H = sh;
-    return;
+  for (int k = 0; k < 6; ++k) {
+    const float v = half * wn[k >> 1] * exp_f32(D * q[1 + k]);
+    sf += v;
+    sh += v * q[1 + k];
   }
+  *F = sf;
+  *H = sh;
+  return true;
+}
+
+// The third tier: the FP64 evaluation (zero for an empty interval).
+GLMR_HD inline void fp64_tier_f(float D, double delta, float* F, float* H) {
   if (!(delta > 0.0)) {
     *F = 0.0f;
     *H = 0.0f;
@@ -366,12 +369,17 @@ GLMR_HD inline void gl_tier_f(const float* o, double delta, float D, float* F, f
   *H = (float)Hd;
 }
 
+// The second and third tiers.
+GLMR_HD inline void gl_tier_f(const float* q, double delta, float D, float* F, float* H) {
+  if (!gl_quad_f(q, D, F, H)) fp64_tier_f(D, delta, F, H);
+}
+
 // The whole FP32 chain for one interval, as the resident BF16 kernels take it.
 GLMR_HD inline void interval_f32(float D, double delta, float* F, float* H) {
   float o[16], c[16];
   table_f(delta, o);
   stage_f(o[0], o[1], c);
-  if (!taylor_f(c, D, F, H)) gl_tier_f(o, delta, D, F, H);
+  if (!taylor_f(c, D, F, H)) gl_tier_f(o + 8, delta, D, F, H);
 }
 
 }  // namespace glmr_ev

@@ -449,7 +449,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_gemm1(Gemm1Args g) {
           const float D = (float)pwd * stage[e * WN + lane];
           float Ff, Hf;
           if (!glmr_ev::taylor_f(cf, D, &Ff, &Hf))
-            glmr_ev::gl_tier_f(g.evgl + (tt0 + tl) * 16, g.ev.delta[tt0 + tl], D, &Ff, &Hf);
+            glmr_ev::gl_tier_f(g.evgl + (tt0 + tl) * 16 + 8, g.ev.delta[tt0 + tl], D, &Ff, &Hf);
           F = Ff;
           H = Hf;
         } else {

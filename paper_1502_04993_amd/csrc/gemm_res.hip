@@ -382,14 +382,52 @@ constexpr uint32_t SR_WT = 0x85EBCA6Bu, SR_WI = 0xC2B2AE35u;  // rounding bits o
 // U's unrolled call sites this code would quadruple the kernel and its
 // register demand.  F and H come back in registers (as results through
 // pointers they would live in the stack, written at every call site whether
-// the call is taken or not).
-__device__ __attribute__((noinline)) float2 ev_rare_tier(const float* o, double delta, float D) {
+// the call is taken or not).  The quadrature tier makes no call of its own,
+// so that it saves nothing on entry: where it does not apply it returns NaN
+// and the caller takes the FP64 tier, a second call.  q is the slot's
+// quadrature half of its table, staged in LDS with the expansion's
+// coefficients.
+__device__ __attribute__((noinline)) float2 ev_quad_tier(const float* q, float D) {
   float F, H;
-  glmr_ev::gl_tier_f(o, delta, D, &F, &H);
+  if (glmr_ev::gl_quad_f(q, D, &F, &H)) return float2{F, H};
+  return float2{__builtin_nanf(""), 0.f};
+}
+
+__device__ __attribute__((noinline)) float2 ev_fp64_tier(const double* delta, float D) {
+  float F, H;
+  glmr_ev::fp64_tier_f(D, *delta, &F, &H);
   return float2{F, H};
 }
 
-constexpr int EVTS = 20;  // floats per slot of kernel U's staged expansion table (80 B: 16 used)
+__device__ __forceinline__ float2 ev_rare_tier(const float* q, const double* delta, float D) {
+  float2 r = ev_quad_tier(q, D);
+  if (r.x != r.x) r = ev_fp64_tier(delta, D);
+  return r;
+}
+
+// floats per slot of kernel U's staged table: the expansion's 16
+// coefficients, then the quadrature half of the slot's table (8: delta/2,
+// the nodes, the flag)
+constexpr int EVTS = 24;
+
+// one slot's staged entries from its table in memory (zero past the last slot)
+__device__ __forceinline__ void stage_slot(const float* __restrict__ evgl, int64_t t, int64_t B, float* dst) {
+  float4 q0 = float4{0.f, 0.f, 0.f, 0.f}, q2 = q0, q3 = q0;
+  if (t < B) {
+    const float4* src = (const float4*)(evgl + t * 16);
+    q0 = src[0];
+    q2 = src[2];
+    q3 = src[3];
+  }
+  // past the last slot: zero length and u = 0, so F = H = 0
+  float c[16];
+  glmr_ev::stage_f(q0.x, q0.y, c);
+  float4* o = (float4*)dst;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) o[v] = float4{c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]};
+  o[4] = q2;
+  o[5] = q3;
+}
 
 template <int BI, int WGM, int WGN, bool F8, bool EV = false>
 __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int64_t ttile,
@@ -425,20 +463,11 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
     // each of the tile's slots are formed once into LDS (after W's staging
     // rows and the row-sum partials); a lane reads its slot's with four
     // broadcast loads and uses them for its NB neuron blocks.  Intervals
-    // outside the expansion's bound take the quadrature or FP64 tier from
-    // the table in memory.
+    // outside the expansion's bound take the quadrature tier from the
+    // slot's staged quadrature entries, or the FP64 tier.
     static_assert(!F8, "the event grid's resident trace is BF16");
     float* ctab = (float*)(smem + (size_t)BI * WP + (size_t)WGM * BI * sizeof(double));  // [BT][EVTS]
-    for (int k = tid; k < BT; k += T::NT) {
-      const int64_t t = tt0 + k;
-      // past the last slot: zero length and u = 0, so F = H = 0
-      const float2 de = t < g.B ? *(const float2*)(g.evgl + t * 16) : float2{0.f, 0.f};
-      float c[16];
-      glmr_ev::stage_f(de.x, de.y, c);
-      float4* o = (float4*)(ctab + k * EVTS);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[v] = float4{c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]};
-    }
+    for (int k = tid; k < BT; k += T::NT) stage_slot(g.evgl, tt0 + k, g.B, ctab + k * EVTS);
     __syncthreads();
     float cs[T::NB];
 #pragma unroll
@@ -471,8 +500,8 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
             const bool ok = glmr_ev::taylor_f(c, D, &F, &H);
             cs[b] += ok ? F : 0.f;
             if (!ok) {
-              const int64_t t = tt0 + tq + e;  // t < B: slots past it are within the bound
-              const float2 r = ev_rare_tier(g.evgl + t * 16, g.evdelta[t], D);
+              // t < B: slots past it are within the bound
+              const float2 r = ev_rare_tier(ctab + (tq + e) * EVTS + 16, g.evdelta + tt0 + tq + e, D);
               cs[b] += r.x;
               H = r.y;
             }
@@ -804,21 +833,12 @@ __device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, in
     // expansion coefficients of each of the tile's slots are formed once into
     // LDS (after the row-sum partials); a lane reads its slot's with four
     // broadcast loads and uses them for its 4 neuron blocks.  Intervals
-    // outside the expansion's bound take the quadrature or FP64 tier from
-    // the table in memory.
+    // outside the expansion's bound take the quadrature tier from the
+    // slot's staged quadrature entries, or the FP64 tier.
     static_assert(4 * FB * sizeof(double) + GLMR_TT * EVTS * sizeof(float) <= FLDS && GLMR_TT == 256,
                   "one slot per thread, the staged table after the row-sum partials");
     float* ctab = (float*)(smem + 4 * FB * sizeof(double));  // [GLMR_TT][EVTS]
-    {
-      const int64_t t = tt0 + tid;
-      // past the last slot: zero length and u = 0, so F = H = 0
-      const float2 de = t < g.B ? *(const float2*)(g.evgl + t * 16) : float2{0.f, 0.f};
-      float c[16];
-      glmr_ev::stage_f(de.x, de.y, c);
-      float4* o = (float4*)(ctab + tid * EVTS);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[v] = float4{c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3]};
-    }
+    stage_slot(g.evgl, tt0 + tid, g.B, ctab + tid * EVTS);
     __syncthreads();
     float cs[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -850,8 +870,8 @@ __device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, in
             const bool ok = glmr_ev::taylor_f(c, D, &F, &H);
             cs[b] += ok ? F : 0.f;
             if (!ok) {
-              const int64_t t = tt0 + tq + e;  // t < B: slots past it are within the bound
-              const float2 r = ev_rare_tier(g.evgl + t * 16, g.evdelta[t], D);
+              // t < B: slots past it are within the bound
+              const float2 r = ev_rare_tier(ctab + (tq + e) * EVTS + 16, g.evdelta + tt0 + tq + e, D);
               cs[b] += r.x;
               H = r.y;
             }
