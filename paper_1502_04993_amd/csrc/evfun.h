@@ -261,6 +261,16 @@ GLMR_HD inline float exp_f32(float x) {
 #endif
 }
 
+// 2^x in FP32: the hardware's base-2 exponential on the device, the C
+// library's on the host.
+GLMR_HD inline float exp2_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_exp2f(x);
+#else
+  return exp2f(x);
+#endif
+}
+
 // The first tier of the FP32 evaluation (the resident BF16 trace): the
 // midpoint expansion of the short-interval branch above, to k = 3.  With
 // h = delta / 2 and u = D e^{-h},
@@ -268,60 +278,76 @@ GLMR_HD inline float exp_f32(float x) {
 //   H = delta e^{-h} e^u sum_k Q_2k(u) h^2k / (2k+1)!,   Q_n = T_{n+1} / u,
 // (the Touchard generating function exp(u (e^t - 1)) = sum_n T_n(u) t^n / n!
 // with t = -(s - h), odd powers of t integrating to zero).  Where
-// delta max(1, |u|) <= 0.25 the first omitted terms are below
-// Bell(8) 0.125^8 / 9! = 6.8e-10 (F) and Bell(9) 0.125^8 / 9! = 3.5e-9 (H)
+// delta max(1, |u|) <= 0.35 the first omitted terms are below
+// Bell(8) 0.175^8 / 9! = 1.0e-8 (F) and Bell(9) 0.175^8 / 9! = 5.1e-8 (H)
 // relative (T_n(m) <= Bell(n) m^n for m >= 1, and both sums lie within
-// e^{+-0.14} of their first term, so relative means relative to the result).
+// e^{+-0.2} of their first term, so relative means relative to the result).
 // The sums are polynomials in u whose coefficients depend on the interval
-// only, with delta and delta e^{-h} folded in: one exponential and two
-// degree-6 Horner evaluations per potential.  The 16 coefficients of an
-// interval (stage_f): [0..6] F / e^u = sum_j c_j u^j, [7] e^{-h},
-// [8..14] H / e^u = sum_j c_{8+j} u^j, [15] the bound on |u| (0.25 / delta,
-// negative where delta > 0.25, so that delta max(1, |u|) <= 0.25 reads
-// |u| <= [15]).
+// only, with delta and delta e^{-h} folded in; they are taken in
+// v = u log2(e), the base-2 exponential's argument, with the coefficients of
+// v^j scaled by ln(2)^j: one exponential and two degree-6 Horner evaluations
+// per potential.  The 16 coefficients of an interval (stage_f):
+// [0..6] F / e^u = sum_j c_j v^j, [7] e^{-h} log2(e), [8..14]
+// H / e^u = sum_j c_{8+j} v^j, [15] the bound on |v| (0.35 log2(e) / delta,
+// negative where delta > 0.35, so that delta max(1, |u|) <= 0.35 reads
+// |v| <= [15]).
+constexpr float EXP_BOUND = 0.35f;
+
 GLMR_HD inline void stage_f(float delta, float emh, float* o) {
   const float h = 0.5f * delta;
   const float c2 = h * h * (1.0f / 6.0f);    // h^2 / 3!
   const float c4 = 0.3f * c2 * c2;           // h^4 / 5!
   const float c6 = c4 * c2 * (1.0f / 7.0f);  // h^6 / 7!
   const float dq = delta * emh;
+  // ln(2)^j
+  const float l1 = 0.693147180559945309f, l2 = 0.480453013918201424f, l3 = 0.333024651988929479f,
+              l4 = 0.230835098583083444f, l5 = 0.160002697757141904f, l6 = 0.110905418239124928f;
   // T_0 = 1, T_2 = u + u^2, T_4 = u + 7u^2 + 6u^3 + u^4,
   // T_6 = u + 31u^2 + 90u^3 + 65u^4 + 15u^5 + u^6
   o[0] = delta;
-  o[1] = delta * (c2 + c4 + c6);
-  o[2] = delta * (c2 + 7.0f * c4 + 31.0f * c6);
-  o[3] = delta * (6.0f * c4 + 90.0f * c6);
-  o[4] = delta * (c4 + 65.0f * c6);
-  o[5] = delta * (15.0f * c6);
-  o[6] = delta * c6;
-  o[7] = emh;
+  o[1] = l1 * (delta * (c2 + c4 + c6));
+  o[2] = l2 * (delta * (c2 + 7.0f * c4 + 31.0f * c6));
+  o[3] = l3 * (delta * (6.0f * c4 + 90.0f * c6));
+  o[4] = l4 * (delta * (c4 + 65.0f * c6));
+  o[5] = l5 * (delta * (15.0f * c6));
+  o[6] = l6 * (delta * c6);
+  o[7] = emh * 1.44269504088896341f;
   // Q_0 = 1, Q_2 = 1 + 3u + u^2, Q_4 = 1 + 15u + 25u^2 + 10u^3 + u^4,
   // Q_6 = 1 + 63u + 301u^2 + 350u^3 + 140u^4 + 21u^5 + u^6
   o[8] = dq * (1.0f + c2 + c4 + c6);
-  o[9] = dq * (3.0f * c2 + 15.0f * c4 + 63.0f * c6);
-  o[10] = dq * (c2 + 25.0f * c4 + 301.0f * c6);
-  o[11] = dq * (10.0f * c4 + 350.0f * c6);
-  o[12] = dq * (c4 + 140.0f * c6);
-  o[13] = dq * (21.0f * c6);
-  o[14] = dq * c6;
-  o[15] = delta <= 0.25f ? (delta > 0.0f ? 0.25f / delta : 3.0e38f) : -1.0f;
+  o[9] = l1 * (dq * (3.0f * c2 + 15.0f * c4 + 63.0f * c6));
+  o[10] = l2 * (dq * (c2 + 25.0f * c4 + 301.0f * c6));
+  o[11] = l3 * (dq * (10.0f * c4 + 350.0f * c6));
+  o[12] = l4 * (dq * (c4 + 140.0f * c6));
+  o[13] = l5 * (dq * (21.0f * c6));
+  o[14] = l6 * (dq * c6);
+  o[15] = delta <= EXP_BOUND ? (delta > 0.0f ? EXP_BOUND * 1.44269504088896341f / delta : 3.0e38f) : -1.0f;
 }
 
-// F, H by the expansion from an interval's 16 coefficients; returns whether
-// the interval is within its bound (otherwise F, H are to be taken from the
-// next tier).
-GLMR_HD inline bool taylor_f(const float* c, float D, float* F, float* H) {
-  const float u = D * c[7];
-  const float E = exp_f32(u);
-  float pf = c[6], ph = c[14];
+// The expansion from an interval's 16 coefficients in three parts,
+// F = E pf and H = E ph; returns whether the interval is within its bound
+// (otherwise F, H are to be taken from the next tier).
+GLMR_HD inline bool taylor_parts(const float* c, float D, float* E, float* pf, float* ph) {
+  const float v = D * c[7];
+  *E = exp2_f32(v);
+  float f = c[6], g = c[14];
 #pragma unroll
   for (int k = 5; k >= 0; --k) {
-    pf = pf * u + c[k];
-    ph = ph * u + c[8 + k];
+    f = f * v + c[k];
+    g = g * v + c[8 + k];
   }
+  *pf = f;
+  *ph = g;
+  return fabsf(v) <= c[15];
+}
+
+// F, H by the expansion.
+GLMR_HD inline bool taylor_f(const float* c, float D, float* F, float* H) {
+  float E, pf, ph;
+  const bool ok = taylor_parts(c, D, &E, &pf, &ph);
   *F = E * pf;
   *H = E * ph;
-  return fabsf(u) <= c[15];
+  return ok;
 }
 
 // The per-interval table of the FP32 evaluation, 16 floats: [0] delta,

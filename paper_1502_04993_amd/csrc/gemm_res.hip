@@ -496,10 +496,11 @@ __device__ __forceinline__ void res_u_tile(const ResUArgs& g, int64_t itile, int
             // the expansion's F joins the sum before the branch and the
             // rare tier's inside it: no value is merged across the call,
             // which would otherwise be kept in memory around it
-            float F, H;
-            const bool ok = glmr_ev::taylor_f(c, D, &F, &H);
-            cs[b] += ok ? F : 0.f;
-            if (!ok) {
+            float E, pf, ph;
+            const bool out = !glmr_ev::taylor_parts(c, D, &E, &pf, &ph);
+            cs[b] = fmaf(E, out ? 0.f : pf, cs[b]);
+            float H = E * ph;
+            if (out) {
               // t < B: slots past it are within the bound
               const float2 r = ev_rare_tier(ctab + (tq + e) * EVTS + 16, g.evdelta + tt0 + tq + e, D);
               cs[b] += r.x;
@@ -860,22 +861,27 @@ __device__ __forceinline__ void res_uf_tile(const ResUArgs& g, int64_t itile, in
             c[4 * v + 2] = w.z;
             c[4 * v + 3] = w.w;
           }
+          // the expansion's F joins the sums before the branch and the rare
+          // tier's inside it (no value is merged across the call, which would
+          // otherwise be kept in memory around it); one branch per slot
+          bool out[4];
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
-            const float D = acc[a][b][4 * q + e];
-            // the expansion's F joins the sum before the branch and the
-            // rare tier's inside it: no value is merged across the call,
-            // which would otherwise be kept in memory around it
-            float F, H;
-            const bool ok = glmr_ev::taylor_f(c, D, &F, &H);
-            cs[b] += ok ? F : 0.f;
-            if (!ok) {
-              // t < B: slots past it are within the bound
-              const float2 r = ev_rare_tier(ctab + (tq + e) * EVTS + 16, g.evdelta + tt0 + tq + e, D);
-              cs[b] += r.x;
-              H = r.y;
-            }
-            lam[b][e] = H;
+            float E, pf, ph;
+            out[b] = !glmr_ev::taylor_parts(c, acc[a][b][4 * q + e], &E, &pf, &ph);
+            cs[b] = fmaf(E, out[b] ? 0.f : pf, cs[b]);
+            lam[b][e] = E * ph;
+          }
+          if (out[0] || out[1] || out[2] || out[3]) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              if (out[b]) {
+                // t < B: slots past it are within the bound
+                const float2 r = ev_rare_tier(ctab + (tq + e) * EVTS + 16, g.evdelta + tt0 + tq + e,
+                                              acc[a][b][4 * q + e]);
+                cs[b] += r.x;
+                lam[b][e] = r.y;
+              }
           }
         }
 #pragma unroll

@@ -70,7 +70,7 @@ def _tier_f32(D, delta):
     1 the 6-point quadrature, 2 the FP64 evaluation."""
     D = float(np.float32(D))
     u = D * float(np.float32(np.exp(-0.5 * delta)))
-    if float(np.float32(delta)) * max(1.0, abs(u)) <= 0.25:
+    if float(np.float32(delta)) * max(1.0, abs(u)) <= 0.35:
         return 0
     return 1 if (delta <= 0.5 and abs(D) * delta <= 1.0) else 2
 
@@ -102,10 +102,10 @@ def test_fp32_interval_chain_matches_mpmath_in_every_tier():
 
 def test_fp32_expansion_at_its_bound_and_degenerate_intervals():
     import paper_1502_04993_amd as G
-    # on the bound delta max(1, |u|) = 0.25 from both sides: the expansion's
+    # on the bound delta max(1, |u|) = 0.35 from both sides: the expansion's
     # truncation stays far below FP32 rounding
     for D in (-6.0, -1.0, 0.5, 1.0, 4.0):
-        for dl in np.linspace(0.2, 0.3, 21):
+        for dl in np.linspace(0.25, 0.45, 41):
             u = D * np.exp(-dl / 2)
             F, H = G.glmr_ei_interval_f32(D, dl)
             Fr, Hr = _ref(D, dl)
