@@ -144,15 +144,25 @@ __device__ inline double lane_bcast_d(double v, int l) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// EV: event grid; the trace at a spike is its left limit at the event time
+// EV: event grid; the trace at a spike is its left limit at the event time.
+// One wave per (64 columns, RB rows, time split) owns its FP64 sums in LDS
+// and takes the spikes of its rows out of the 64-row block's entry lists.
+// RB = 16: 8 KB of sums, so that five waves share a SIMD and hide each
+// other's latency (64-row waves, 32 KB, took 39 ms at 3.6e6 bins and
+// N = 1000, these 25 ms; on the event grid, whose subtiles hold about one
+// spike per 64-row block, 100 and 95 ms).
+constexpr int SPK_RB = 16;
+
 template <bool WANT_Y, bool EV>
 __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
-  __shared__ double acc[64][64];
-  __shared__ double accy[WANT_Y ? 64 : 1][64];
+  constexpr int RB = SPK_RB;
+  __shared__ double acc[RB][64];
+  __shared__ double accy[WANT_Y ? RB : 1][64];
   const int lane = threadIdx.x;
-  const int64_t jb = blockIdx.x, ib = blockIdx.y, split = blockIdx.z;
+  const int64_t jb = blockIdx.x, ib = blockIdx.y / (64 / RB), split = blockIdx.z;
+  const int h = (int)(blockIdx.y % (64 / RB));  // the wave's rows: h RB .. h RB + RB - 1 of block ib
   const int64_t j = jb * 64 + lane;
-  for (int r = 0; r < 64; ++r) {
+  for (int r = 0; r < RB; ++r) {
     acc[r][lane] = 0.0;
     if (WANT_Y) accy[r][lane] = 0.0;
   }
@@ -160,24 +170,30 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
   const int64_t sb = split * per;
   const int64_t se = (sb + per < a.NS) ? sb + per : a.NS;
   const double ctau = a.ctau;
-  // The loads of a subtile (its segment bounds, this lane's carry and mask,
-  // the event grid's slot tables) are issued one subtile ahead, so that their
-  // latency overlaps the walk of the spikes before.
+  // The loads of a subtile (this lane's carry and mask, the event grid's
+  // slot tables, the segment's first 64 entries) are issued one subtile
+  // ahead, its segment bounds two ahead, so that their latency overlaps the
+  // walk of the spikes before.
   struct Pre {
     int32_t e0, e1;
     double C, CY, left, ainv;
     uint64_t m0;
+    int mine;
   };
-  auto fetch = [&](int64_t s) {
-    Pre p;
+  auto bounds = [&](int64_t s) {
     const int64_t sg = s * a.NIB + ib;
-    p.e0 = a.seg_off[sg];
-    p.e1 = a.seg_off[sg + 1];
+    return int2{a.seg_off[sg], a.seg_off[sg + 1]};
+  };
+  auto fetch = [&](int64_t s, int2 eb) {
+    Pre p;
+    p.e0 = eb.x;
+    p.e1 = eb.y;
     p.C = a.C64[s * a.Np + j];
     p.CY = WANT_Y ? a.CY64[s * a.Np + j] : 0.0;
     p.m0 = a.masks[s * a.Np + j];
     p.left = EV ? a.ev.left[s * 64 + lane] : 0.0;
     p.ainv = EV ? a.ev.ainv[s * 64 + lane] : 0.0;
+    p.mine = lane < eb.y - eb.x ? (int)a.seg_ent[eb.x + lane] : 0;
     return p;
   };
   // lane b holds the factors of bin b: the decay a^b and a^-(b+1) (the event
@@ -185,12 +201,23 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
   const double pw_grid = EV ? 0.0 : a.tab->pw[lane];
   const double ainv_grid = EV ? 0.0 : a.tab->ainv[lane];
   Pre nxt{};
-  if (sb < se) nxt = fetch(sb);
+  int2 eb2{0, 0};
+  if (sb < se) nxt = fetch(sb, bounds(sb));
+  if (sb + 1 < se) eb2 = bounds(sb + 1);
   for (int64_t s = sb; s < se; ++s) {
     const Pre cur = nxt;
-    if (s + 1 < se) nxt = fetch(s + 1);
+    if (s + 1 < se) nxt = fetch(s + 1, eb2);
+    if (s + 2 < se) eb2 = bounds(s + 2);
     const int32_t e0 = cur.e0, e1 = cur.e1;
     if (e0 == e1) continue;
+    // the segment's first 64 entries, one per lane (most segments have no
+    // more); the wave's own (its rows) form a uniform mask, walked in order
+    // (bin order within the segment).  A segment with none of the wave's
+    // rows is passed before any set-up.
+    int cnt = (e1 - e0 < 64) ? e1 - e0 : 64;
+    int mine = cur.mine;
+    uint64_t sel = __ballot(lane < cnt && ((mine & 63) / RB) == h);
+    if (sel == 0 && e1 - e0 <= 64) continue;
     // this lane's column: carry and masks of subtile s
     const double C = cur.C;
     const double CY = cur.CY;
@@ -220,17 +247,26 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
     for (int p = 1; p < a.planes; ++p) slow = slow || a.masks[((int64_t)p * a.NS + s) * a.Np + j] != 0;
     // the term of one spike (entry v: bin b = v >> 6, row il = v & 63) by
     // the four registered bins
+    // the running sums C, C + w0, C + w0 + w1, ... of the registered bins
+    // (bt is ascending: the bins below b are a prefix of them), added in the
+    // order the per-spike sum would take
+    double pre[5];
+    pre[0] = C;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pre[q + 1] = pre[q] + wt[q];
     auto fast = [&](int v, double* ty) {
       const int b = v >> 6;
       double run = C, P0 = 0.0, P1 = 0.0;
+      if (WANT_Y) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool in = bt[q] < b;
-        run += in ? wt[q] : 0.0;
-        if (WANT_Y) {
+        for (int q = 0; q < 4; ++q) {
+          const bool in = bt[q] < b;
+          run += in ? wt[q] : 0.0;
           P0 += in ? wt[q] : 0.0;
           P1 += in ? ut[q] : 0.0;
         }
+      } else {
+        run = bt[3] < b ? pre[4] : bt[2] < b ? pre[3] : bt[1] < b ? pre[2] : bt[0] < b ? pre[1] : pre[0];
       }
       const double pw = lane_bcast_d(pw_lane, b);
       if (WANT_Y) *ty = pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
@@ -238,31 +274,36 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
     };
     const bool wave_fast = __ballot(slow) == 0;  // uniform over the wave
     for (int32_t eb = e0; eb < e1; eb += 64) {
-      // one entry per lane, then walk them in order (bin order within the segment)
-      const int cnt = (e1 - eb < 64) ? e1 - eb : 64;
-      const int mine = lane < cnt ? (int)a.seg_ent[eb + lane] : 0;
-      int k = 0;
+      if (eb != e0) {
+        cnt = (e1 - eb < 64) ? e1 - eb : 64;
+        mine = lane < cnt ? (int)a.seg_ent[eb + lane] : 0;
+        sel = __ballot(lane < cnt && ((mine & 63) / RB) == h);
+      }
+      auto next = [&]() {
+        const int k = __builtin_ctzll(sel);
+        sel &= sel - 1;
+        return lane_bcast(mine, k);
+      };
       if (wave_fast) {
         // four spikes at a time: their sums are independent, so their
         // instruction chains interleave; the adds keep the spikes' order
-        for (; k + 4 <= cnt; k += 4) {
-          const int v0 = lane_bcast(mine, k), v1 = lane_bcast(mine, k + 1);
-          const int v2 = lane_bcast(mine, k + 2), v3 = lane_bcast(mine, k + 3);
+        while (__builtin_popcountll(sel) >= 4) {
+          const int v0 = next(), v1 = next(), v2 = next(), v3 = next();
           double y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
           const double x0 = fast(v0, &y0), x1 = fast(v1, &y1), x2 = fast(v2, &y2), x3 = fast(v3, &y3);
-          atomicAdd(&acc[v0 & 63][lane], x0);
-          if (WANT_Y) atomicAdd(&accy[v0 & 63][lane], y0);
-          atomicAdd(&acc[v1 & 63][lane], x1);
-          if (WANT_Y) atomicAdd(&accy[v1 & 63][lane], y1);
-          atomicAdd(&acc[v2 & 63][lane], x2);
-          if (WANT_Y) atomicAdd(&accy[v2 & 63][lane], y2);
-          atomicAdd(&acc[v3 & 63][lane], x3);
-          if (WANT_Y) atomicAdd(&accy[v3 & 63][lane], y3);
+          atomicAdd(&acc[(v0 & 63) % RB][lane], x0);
+          if (WANT_Y) atomicAdd(&accy[(v0 & 63) % RB][lane], y0);
+          atomicAdd(&acc[(v1 & 63) % RB][lane], x1);
+          if (WANT_Y) atomicAdd(&accy[(v1 & 63) % RB][lane], y1);
+          atomicAdd(&acc[(v2 & 63) % RB][lane], x2);
+          if (WANT_Y) atomicAdd(&accy[(v2 & 63) % RB][lane], y2);
+          atomicAdd(&acc[(v3 & 63) % RB][lane], x3);
+          if (WANT_Y) atomicAdd(&accy[(v3 & 63) % RB][lane], y3);
         }
       }
-      for (; k < cnt; ++k) {
-        const int v = lane_bcast(mine, k);
-        const int il = v & 63, b = v >> 6;
+      while (sel) {
+        const int v = next();
+        const int il = (v & 63) % RB, b = v >> 6;
         double run = C, P0 = 0.0, P1 = 0.0;
         if (!slow) {
 #pragma unroll
@@ -296,11 +337,12 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
       }
     }
   }
+  const int64_t i0 = ib * 64 + h * RB;
   double* out = a.part + split * a.Np * a.Np;
-  for (int r = 0; r < 64; ++r) out[(ib * 64 + r) * a.Np + j] = acc[r][lane];
+  for (int r = 0; r < RB; ++r) out[(i0 + r) * a.Np + j] = acc[r][lane];
   if (WANT_Y) {
     double* outy = a.part + ((int64_t)a.splits + split) * a.Np * a.Np;
-    for (int r = 0; r < 64; ++r) outy[(ib * 64 + r) * a.Np + j] = accy[r][lane];
+    for (int r = 0; r < RB; ++r) outy[(i0 + r) * a.Np + j] = accy[r][lane];
   }
 }
 
@@ -331,7 +373,7 @@ hipError_t launch_carries(const CarryArgs& c, hipStream_t st) {
 }
 
 hipError_t launch_spike_term(const SpikeTermArgs& a, hipStream_t st) {
-  dim3 grid((unsigned)a.NIB, (unsigned)a.NIB, (unsigned)a.splits);
+  const dim3 grid((unsigned)a.NIB, (unsigned)(a.NIB * (64 / SPK_RB)), (unsigned)a.splits);
   if (a.ev.pw)
     hipLaunchKernelGGL((k_spike_term<false, true>), grid, dim3(64), 0, st, a);
   else if (a.CY64)
