@@ -147,15 +147,19 @@ __device__ inline double lane_bcast_d(double v, int l) {
 // EV: event grid; the trace at a spike is its left limit at the event time.
 // One wave per (64 columns, RB rows, time split) owns its FP64 sums in LDS
 // and takes the spikes of its rows out of the 64-row block's entry lists.
-// RB = 16: 8 KB of sums, so that five waves share a SIMD and hide each
-// other's latency (64-row waves, 32 KB, took 39 ms at 3.6e6 bins and
-// N = 1000, these 25 ms; on the event grid, whose subtiles hold about one
-// spike per 64-row block, 100 and 95 ms).
-constexpr int SPK_RB = 16;
+// Fewer rows per wave let more waves share a SIMD and hide each other's
+// latency, but every wave walks all subtiles of its split.  Measured at
+// N = 1000 (3.6e6 bins; its event grid of 24.3e6 slots, about one spike per
+// 64-row block and subtile): 64 / 32 / 16 / 8 rows took 39 / 29 / 24 / 28 ms
+// on the grid and 100 / 78 / 84 / 159 ms on the event grid.
+template <bool EV>
+constexpr int spk_rows() {
+  return EV ? 32 : 16;
+}
 
 template <bool WANT_Y, bool EV>
 __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
-  constexpr int RB = SPK_RB;
+  constexpr int RB = spk_rows<EV>();
   __shared__ double acc[RB][64];
   __shared__ double accy[WANT_Y ? RB : 1][64];
   const int lane = threadIdx.x;
@@ -373,13 +377,13 @@ hipError_t launch_carries(const CarryArgs& c, hipStream_t st) {
 }
 
 hipError_t launch_spike_term(const SpikeTermArgs& a, hipStream_t st) {
-  const dim3 grid((unsigned)a.NIB, (unsigned)(a.NIB * (64 / SPK_RB)), (unsigned)a.splits);
+  auto grid = [&](int rb) { return dim3((unsigned)a.NIB, (unsigned)(a.NIB * (64 / rb)), (unsigned)a.splits); };
   if (a.ev.pw)
-    hipLaunchKernelGGL((k_spike_term<false, true>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_spike_term<false, true>), grid(spk_rows<true>()), dim3(64), 0, st, a);
   else if (a.CY64)
-    hipLaunchKernelGGL((k_spike_term<true, false>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_spike_term<true, false>), grid(spk_rows<false>()), dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL((k_spike_term<false, false>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_spike_term<false, false>), grid(spk_rows<false>()), dim3(64), 0, st, a);
   const int64_t n = a.Np * a.Np;
   int blocks = (int)((n + 255) / 256);
   if (blocks > 65536) blocks = 65536;
