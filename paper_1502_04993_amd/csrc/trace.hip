@@ -254,11 +254,8 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
     // the running sums C, C + w0, C + w0 + w1, ... of the registered bins
     // (bt is ascending: the bins below b are a prefix of them), added in the
     // order the per-spike sum would take
-    double pre[5];
-    pre[0] = C;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) pre[q + 1] = pre[q] + wt[q];
-    auto fast = [&](int v, double* ty) {
+    const double pre1 = C + wt[0], pre2 = pre1 + wt[1], pre3 = pre2 + wt[2], pre4 = pre3 + wt[3];
+    auto fast = [&, pre1, pre2, pre3, pre4](int v, double* ty) {
       const int b = v >> 6;
       double run = C, P0 = 0.0, P1 = 0.0;
       if (WANT_Y) {
@@ -270,7 +267,10 @@ __global__ __launch_bounds__(64) void k_spike_term(SpikeTermArgs a) {
           P1 += in ? ut[q] : 0.0;
         }
       } else {
-        run = bt[3] < b ? pre[4] : bt[2] < b ? pre[3] : bt[1] < b ? pre[2] : bt[0] < b ? pre[1] : pre[0];
+        run = bt[0] < b ? pre1 : C;
+        run = bt[1] < b ? pre2 : run;
+        run = bt[2] < b ? pre3 : run;
+        run = bt[3] < b ? pre4 : run;
       }
       const double pw = lane_bcast_d(pw_lane, b);
       if (WANT_Y) *ty = pw * (CY + (double)b * ctau * C + ctau * ((double)b * P0 - P1));
