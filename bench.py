@@ -282,7 +282,7 @@ def main():
         if args.polish_iter > 0 and args.precision == "bf16" and args.polish != "none":
             t1 = time.perf_counter()
             ctx.set_precision(args.polish)
-            pr = ctx.fit(max_iter=args.polish_iter)
+            pr = ctx.fit(max_iter=args.polish_iter, keep_history=True)
             ctx.set_precision(args.precision)
             t_pol = time.perf_counter() - t1
             Jp, _, _ = ctx.get_params()
@@ -487,7 +487,7 @@ def bench_reconstruct(args, G, torch):
     pol = None
     if args.polish_iter > 0 and args.polish != "none":
         ctx.set_precision(args.polish)
-        pol = ctx.fit(max_iter=args.polish_iter, from_zero=False)
+        pol = ctx.fit(max_iter=args.polish_iter, from_zero=False, keep_history=True)
         ctx.set_precision("bf16")
     J, mu, _ = ctx.get_params()
     t_pol = time.perf_counter() - t2

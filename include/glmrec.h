@@ -278,6 +278,15 @@ typedef struct {
                              A fit of a + b steps equals one of a steps resumed for b.
                              GLMR_ESTATE if there is none: changing the spikes, kernel,
                              delays, precision or parameters ends an ascent. */
+  int32_t keep_history;   /* 1: a new ascent (starting point, penalty, bounds and stopping test
+                             from these opts) that starts from the L-BFGS curvature pairs of
+                             the context's last ascent instead of an empty history: to continue
+                             an ascent in a more exact precision after glmr_set_precision (the
+                             pairs are differences of the same objective's gradients, taken at
+                             the other precision).  Needs the same lbfgs_m; GLMR_ESTATE if the
+                             context holds no pairs (changing the spikes, kernel or delays drops
+                             them; changing the precision or parameters keeps them).  Ignored
+                             with resume; a batch fit refuses it. */
 } glmr_fit_opts;
 
 typedef struct {

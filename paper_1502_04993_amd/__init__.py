@@ -385,16 +385,19 @@ class Context:
 
     def fit(self, max_iter=500, ftol=0.0, lbfgs_m=40, max_backtracks=30, warm_start_mu=False,
             from_zero=False, polish=None, polish_iter=200, l1_alpha=0.0, l1_eps=0.0, j_max=0.0,
-            rate_min=0.0, rate_max=0.0, resume=False):
+            rate_min=0.0, rate_max=0.0, resume=False, keep_history=False):
         """Per-row L-BFGS ascent.  polish="bf16j2" (BF16 with a two-term J, the
         trace kept) or "fp32" continues a BF16 ascent from the BF16 optimum to
-        the exact one (then switches back).  l1_alpha /
+        the exact one (then switches back), starting from the BF16 ascent's
+        curvature pairs.  l1_alpha /
         l1_eps: the smooth epsilon-l1 penalty; j_max, rate_min, rate_max: bounds.
         resume=True continues the ascent the context holds (an earlier fit's, or
-        one restored by set_state)."""
+        one restored by set_state); keep_history=True starts a new ascent from
+        the last one's L-BFGS pairs (e.g. after set_precision)."""
         o = glmr_fit_defaults()
         o.max_iter, o.ftol, o.lbfgs_m, o.max_backtracks = max_iter, ftol, lbfgs_m, max_backtracks
         o.warm_start_mu, o.from_zero, o.resume = int(warm_start_mu), int(from_zero), int(resume)
+        o.keep_history = int(keep_history)
         o.l1_alpha, o.l1_eps, o.j_max, o.rate_min, o.rate_max = l1_alpha, l1_eps, j_max, rate_min, rate_max
         st, rep = glmr_fit(self._c, o)
         out = dict(status=st, converged=(st == GLMR_OK), iters=rep.iters, evals=rep.evals,
@@ -404,6 +407,7 @@ class Context:
             prec0 = self.precision
             self.set_precision(polish)
             o.max_iter, o.from_zero, o.warm_start_mu, o.ftol = polish_iter, 0, 0, 0.0
+            o.resume, o.keep_history = 0, 1
             st2, rep2 = glmr_fit(self._c, o)
             self.set_precision(prec0)
             out.update(status=st2, converged=(st2 == GLMR_OK), polish_iters=rep2.iters,

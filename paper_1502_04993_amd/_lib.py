@@ -44,7 +44,7 @@ class glmr_fit_opts(ctypes.Structure):
                 ("max_backtracks", ctypes.c_int32), ("warm_start_mu", ctypes.c_int32),
                 ("from_zero", ctypes.c_int32), ("l1_alpha", ctypes.c_double),
                 ("l1_eps", ctypes.c_double), ("j_max", ctypes.c_double), ("rate_min", ctypes.c_double),
-                ("rate_max", ctypes.c_double), ("resume", ctypes.c_int32)]
+                ("rate_max", ctypes.c_double), ("resume", ctypes.c_int32), ("keep_history", ctypes.c_int32)]
 
 
 class glmr_fit_report(ctypes.Structure):

@@ -146,6 +146,7 @@ struct glmr_ctx {
   AscentArgs asc{};
   bool have_asc = false;
   bool asc_live = false;  // asc holds an ascent of the current objective that a fit can resume
+  bool asc_hist = false;  // asc holds L-BFGS pairs of this recording, kernel and delays (any precision)
   int32_t* counters = nullptr;
   int32_t* host_cnt = nullptr;  // pinned copy of counters
   bool capturing = false;       // work is being captured into a graph (no profiling events)
@@ -1011,10 +1012,12 @@ glmr_status eval_theta(glmr_ctx* c, const double* theta_src, double* g, double* 
 }
 
 // Fresh ascent state: empty histories, every row active and asking for a direction.
-glmr_status ascent_reset(glmr_ctx* c) {
+glmr_status ascent_reset(glmr_ctx* c, bool keep_history = false) {
   AscentArgs& a = c->asc;
-  HIPCHK(c, launch_fill_i32(a.hist_len, c->N, 0, c->st));
-  HIPCHK(c, launch_fill_i32(a.hist_head, c->N, 0, c->st));
+  if (!keep_history) {
+    HIPCHK(c, launch_fill_i32(a.hist_len, c->N, 0, c->st));
+    HIPCHK(c, launch_fill_i32(a.hist_head, c->N, 0, c->st));
+  }
   HIPCHK(c, launch_fill_i32(a.state, c->N, 0, c->st));
   HIPCHK(c, launch_fill_i32(a.bt, c->N, 0, c->st));
   HIPCHK(c, launch_fill_i32(a.accepted, c->N, 3, c->st));
@@ -1089,11 +1092,15 @@ glmr_status check_fit_opts(glmr_ctx* c, const glmr_fit_opts* o_in, glmr_fit_opts
       !(o->rate_max >= 0) || (o->rate_min > 0 && o->rate_max > 0 && o->rate_min >= o->rate_max))
     return fail(c, GLMR_EINVAL, "bad fit options");
   if (o->resume != 0 && o->resume != 1) return fail(c, GLMR_EINVAL, "bad fit options");
+  if (o->keep_history != 0 && o->keep_history != 1) return fail(c, GLMR_EINVAL, "bad fit options");
   if (!c->have_spikes || !c->have_kernel) return fail(c, GLMR_ESTATE, "set spikes and kernel first");
   if (!c->all_spiking) return fail(c, GLMR_ENOSPIKES, "some neuron has no spike: its MLE does not exist");
   if (o->resume && !c->asc_live)
     return fail(c, GLMR_ESTATE, "no ascent to resume (fit or glmr_set_state first; changing spikes, "
                                 "kernel, delays, precision or parameters ends it)");
+  if (o->keep_history && !o->resume && !(c->asc_hist && c->have_asc && c->asc.m == o->lbfgs_m))
+    return fail(c, GLMR_ESTATE, "no L-BFGS history to keep (a fit with the same lbfgs_m first; changing "
+                                "spikes, kernel or delays drops it)");
   return GLMR_OK;
 }
 
@@ -1128,7 +1135,7 @@ glmr_status fit_begin(glmr_ctx* c, const glmr_fit_opts& o) {
   a.mu_hi = o.rate_max > 0 ? std::log(o.rate_max) : INFINITY;
   HIPCHK(c, launch_unpack_theta(N, Np, a.P, c->J64, c->mu, a.theta, c->st));
   HIPCHK(c, launch_project_theta(a, a.theta, c->st));  // start inside the box
-  TRY(ascent_reset(c));
+  TRY(ascent_reset(c, o.keep_history != 0));
   return GLMR_OK;
 }
 
@@ -1137,6 +1144,7 @@ glmr_status fit_end(glmr_ctx* c, int iters, int evals, double seconds, glmr_fit_
   const int N = c->N;
   AscentArgs& a = c->asc;
   c->asc_live = true;
+  c->asc_hist = true;
   HIPCHK(c, launch_pack_theta(N, c->Np, a.P, a.theta, c->J64, c->mu, c->st));
   TRY(prepare_params(c));
   std::vector<double> f(N), eta(N);
@@ -1610,6 +1618,7 @@ glmr_status glmr_set_state(glmr_ctx* c, const void* buf, size_t len) {
     c->asc.mu_hi = h.mu_hi;
     HIPCHK(c, hipStreamSynchronize(c->st));
     c->asc_live = true;
+    c->asc_hist = true;
   }
   return GLMR_OK;
 }
@@ -1832,7 +1841,8 @@ glmr_status glmr_batch_fit(glmr_batch* b, const glmr_fit_opts* o_in, glmr_fit_re
   for (glmr_ctx* c : b->ctxs) {
     c->err.clear();
     TRY(check_fit_opts(c, o_in, &o));
-    if (o.resume) return fail(c, GLMR_EINVAL, "a batch fit starts afresh (resume each context on its own)");
+    if (o.resume || o.keep_history)
+      return fail(c, GLMR_EINVAL, "a batch fit starts afresh (resume each context on its own)");
   }
   auto t_start = std::chrono::steady_clock::now();
   OnBatchStream on(b);
@@ -1921,6 +1931,7 @@ void glmr_fit_defaults(glmr_fit_opts* o) {
   o->rate_min = 0.0;
   o->rate_max = 0.0;
   o->resume = 0;
+  o->keep_history = 0;
 }
 
 glmr_status glmr_create(const glmr_config* cfg, glmr_ctx** out) {
@@ -1997,6 +2008,7 @@ namespace {
 glmr_status ingest_pairs(glmr_ctx* c, const int64_t* bin, const int32_t* neuron, int64_t n) {
   ProfScope ps(c, K_INGEST);
   c->asc_live = false;
+  c->asc_hist = false;
   const int64_t nseg = c->NS * c->NIB;
   IngestBufs b{};
   b.n = n;
@@ -2219,6 +2231,7 @@ glmr_status glmr_set_kernel(glmr_ctx* c, double tau) {
   if (!c->evm && tau < c->dt) return fail(c, GLMR_EINVAL, "tau must be >= dt");
   HIPCHK(c, hipSetDevice(c->cfg.device));
   c->asc_live = false;
+  c->asc_hist = false;
   c->tau = tau;
   c->a = std::exp(-c->dt / tau);
   c->have_kernel = false;
@@ -2251,6 +2264,7 @@ glmr_status glmr_set_kernel_noalloc(glmr_ctx* c, double tau) {
     return fail(c, GLMR_EINVAL, "this recording's per-tau set-up needs %zu bytes of scratch; the static "
                                 "scratch holds %zu (use glmr_set_kernel)", need, kScratchBytes);
   c->asc_live = false;
+  c->asc_hist = false;
   c->tau = tau;
   c->a = std::exp(-c->dt / tau);
   c->have_kernel = false;
@@ -2271,6 +2285,7 @@ glmr_status glmr_set_delays(glmr_ctx* c, int64_t d, int64_t d_self) {
   HIPCHK(c, hipSetDevice(c->cfg.device));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->asc_live = false;
+  c->asc_hist = false;
   c->dly = d;
   c->dly_s = d_self;
   if (!c->have_spikes) return GLMR_OK;  // applied when the spikes arrive

@@ -64,7 +64,7 @@ def test_null_context_calls():
     assert lib.glmr_set_state(None, b"GLMRST02", 8) == _lib.GLMR_EINVAL
     o = _lib.glmr_fit_opts()
     lib.glmr_fit_defaults(ctypes.byref(o))
-    assert o.resume == 0  # a fit starts afresh unless asked to resume
+    assert o.resume == 0 and o.keep_history == 0  # a fit starts afresh unless asked otherwise
 
 
 def test_null_context_event_calls():

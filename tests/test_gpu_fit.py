@@ -121,6 +121,44 @@ def test_bf16_fit_with_fp32_polish_matches_oracle_classification():
     assert np.array_equal(O.classify(J), O.classify(Jn))
 
 
+def test_continuation_with_kept_history_and_refusals():
+    """A BF16 ascent continued in FP64 from its L-BFGS pairs (keep_history)
+    reaches the oracle's Newton optimum like a continuation from an empty
+    history; keeping needs pairs of the same recording, kernel and lbfgs_m."""
+    rec = synth.config1(0)
+    N, B = rec.n_neurons, rec.n_bins
+    G = _G()
+    Jn, mun, _ = O.newton_fit(rec.bins, rec.neurons, N, B, rec.dt, rec.tau)
+    out = {}
+    for keep in (False, True):
+        ctx = G.Context(N, B, rec.dt, precision="bf16")
+        ctx.set_spikes(rec.bins, rec.neurons)
+        ctx.set_kernel(rec.tau)
+        if keep:
+            with pytest.raises(G.GlmrError) as e:  # no ascent yet
+                ctx.fit(max_iter=5, keep_history=True)
+            assert e.value.status == G.L.GLMR_ESTATE
+        ctx.fit(max_iter=1000, from_zero=True)
+        ctx.set_precision("fp64")
+        if keep:
+            with pytest.raises(G.GlmrError) as e:  # pairs of another history length
+                ctx.fit(max_iter=5, keep_history=True, lbfgs_m=10)
+            assert e.value.status == G.L.GLMR_ESTATE
+        rep = ctx.fit(max_iter=1000, keep_history=keep)
+        J, mu, _ = ctx.get_params()
+        out[keep] = rep
+        err = max(np.abs(J - Jn).max(), np.abs(mu - mun).max())
+        print(f"[fit config1 bf16 -> fp64, keep_history={keep}] {rep} max err {err:.3e}", flush=True)
+        assert rep["converged"] and err < 1e-5
+        assert np.array_equal(O.classify(J), O.classify(Jn))
+        if keep:
+            ctx.set_kernel(1.2 * rec.tau)  # another objective: the pairs are dropped
+            with pytest.raises(G.GlmrError) as e:
+                ctx.fit(max_iter=5, keep_history=True)
+            assert e.value.status == G.L.GLMR_ESTATE
+        ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16"])
 def test_graph_replays_match_eager_steps(prec):
     """The captured ascent step replayed k times gives bitwise the parameters
