@@ -663,8 +663,9 @@ glmr_status ensure_workspace(glmr_ctx* c, bool want_grad, bool want_tau) {
 // split length (bins) of kernel G for a chunk of Lc bins: about 2048
 // workgroups over `tiles` output tiles, at most max_splits partials.  (For
 // the 8-wave fragment tiles half as many splits halve the FP32 partials and
-// their reduction, 0.13 ms per evaluation at 3.6e6 bins, but the BF16 ascent
-// from J = 0 then took 62 steps instead of 46 to its stopping test.)
+// their reduction, 0.13 ms per evaluation at 3.6e6 bins; the number of BF16
+// ascent steps to the stopping test moves with such rounding changes, and in
+// the one comparison made it rose from 46 to 62.)
 int64_t split_len_tiles(const glmr_ctx* c, int64_t Lc, int64_t tiles) {
   int64_t want = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
   want = std::min<int64_t>(want, c->max_splits);
