@@ -98,6 +98,44 @@ def test_event_grid_matches_oracle(prec, N, B, chunk):
     _compare(r, ref, prec, slots, N, f"N={N} q={times.shape[0]} chunk={chunk}", q=np.bincount(neu, minlength=N))
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16-rc"])
+def test_event_grid_rare_tiers_and_mixed_slots(prec):
+    # a sparse, strongly coupled network (2 spikes/s per neuron, couplings
+    # 2.5x the default): about 60 % of the (slot, neuron) intervals lie past
+    # the FP32 expansion's bound (the quadrature and FP64 tiers), and in about
+    # 30 % of the slots some neurons' intervals are past it and others not,
+    # so the BF16 kernels' per-slot branch takes mixed slots (counted on the
+    # host from the events, as in the oracle's recursion of Eq. (8)).  BF16
+    # only: the FP32 chain of the interval integrals is the BF16 modes' (FP64
+    # and FP32 take the FP64 evaluation)
+    N = 70
+    rec = synth.balanced(N=N, B=30_000, in_frac=0.3, j_exc=0.5, j_inh=-1.5, rate_lo=1.0, rate_hi=3.0,
+                         seed=177)
+    times, neu = synth.event_times(rec, seed=5)
+    T0, T1 = 0.0, rec.T
+    c, slots = _ctx(N, times, neu, T0, T1, prec)
+    c.set_kernel(rec.tau)
+    J = _round(rec.J, prec)
+    c.set_params(J, rec.mu)
+    r = c.eval(grad=True)
+    c.close()
+    o = np.lexsort((neu, times))
+    ts, ns = np.concatenate([times[o], [T1]]), neu[o]
+    v, t_prev, past, mixed = np.zeros(N), T0, 0, 0
+    for m in range(ts.shape[0]):
+        delta = (ts[m] - t_prev) / rec.tau
+        if m >= 1:
+            v[ns[m - 1]] += 1.0
+        out = delta * np.maximum(1.0, np.abs((J @ v) * np.exp(-delta / 2))) > 0.35
+        past += int(out.sum())
+        mixed += int(out.any() and not out.all())
+        v *= np.exp(-delta)
+        t_prev = ts[m]
+    assert past > 0.3 * N * ts.shape[0] and mixed > 0.1 * ts.shape[0], (past, mixed)
+    ref = O.continuous_eval(_lists(times, neu, N), T0, T1, rec.tau, J, rec.mu)
+    _compare(r, ref, prec, slots, N, "rare tiers", q=np.bincount(neu, minlength=N))
+
+
 def test_event_grid_without_events_is_poisson():
     G = _G()
     N, T0, T1 = 3, 0.5, 2.5
