@@ -34,12 +34,21 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// four consecutive entries a thread (16-byte loads; n is a multiple of 4),
+// each summed over the splits in split order
 __global__ void k_gp_reduce_f(const float* Gp, int n_splits, int64_t n, double* G, int first) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+  const int64_t n4 = n / 4;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n4;
        k += (int64_t)gridDim.x * blockDim.x) {
-    double v = first ? 0.0 : G[k];
-    for (int s = 0; s < n_splits; ++s) v += (double)Gp[s * n + k];
-    G[k] = v;
+    double4 v = first ? double4{0.0, 0.0, 0.0, 0.0} : ((const double4*)G)[k];
+    for (int s = 0; s < n_splits; ++s) {
+      const float4 p = ((const float4*)(Gp + s * n))[k];
+      v.x += (double)p.x;
+      v.y += (double)p.y;
+      v.z += (double)p.z;
+      v.w += (double)p.w;
+    }
+    ((double4*)G)[k] = v;
   }
 }
 __global__ void k_gp_reduce_d(const double* Gp, int n_splits, int64_t n, double* G, int first) {
@@ -522,7 +531,7 @@ hipError_t launch_gp_reduce(int prec, const void* Gp, int n_splits, int64_t Np, 
     hipLaunchKernelGGL(k_gp_reduce_d, dim3(grid_for(n, 256)), dim3(256), 0, st, (const double*)Gp,
                        n_splits, n, G64, first);
   else
-    hipLaunchKernelGGL(k_gp_reduce_f, dim3(grid_for(n, 256)), dim3(256), 0, st, (const float*)Gp,
+    hipLaunchKernelGGL(k_gp_reduce_f, dim3(grid_for(n / 4, 256)), dim3(256), 0, st, (const float*)Gp,
                        n_splits, n, G64, first);
   return hipGetLastError();
 }
